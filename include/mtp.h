@@ -1,0 +1,205 @@
+/*
+ * mtp.h -- C ABI of the MI355X (gfx950) Model Tensor Planning replan engine.
+ *
+ * One replan is the loop body of Alg. 2 of "Model Tensor Planning" (Le et al.,
+ * arXiv 2505.01059) repeated n_iters times:
+ *   sample the random multipartite graph Z (Def. 1) and P paths (Alg. 1);
+ *   interpolate them (Def. 2 B-spline, Def. 3 Akima);
+ *   draw G-1 local Gaussian samples around the mean and add the mean itself;
+ *   roll every candidate out and sum its per-step cost (Eq. 1);
+ *   keep the E cheapest, weight them by a softmax and refit mean / std.
+ * The action is the first control of the cheapest candidate of the last
+ * iteration.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns mtp_status; nothing throws, aborts or prints.
+ *   - Arguments are validated before anything is enqueued; on error the object
+ *     is unchanged and mtp_last_error() says why.  A failed HIP call returns
+ *     MTP_ERR_DEVICE and the error sticks to the object until it is destroyed.
+ *   - "d_" pointers are device memory on the current HIP device, "h_" pointers
+ *     host memory.  The caller owns the workspace and the stream; both must
+ *     outlive the plan.  The plan copies the config and its host tables at
+ *     create and never allocates device memory itself (the batch and server
+ *     objects below take caller workspaces too).
+ *   - Work is enqueued asynchronously on the plan's stream; only calls that
+ *     return host data (mtp_get_action, ...) synchronise that stream.
+ *   - A plan is used by one host thread at a time.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
+ * seed, counter = (block, item, replan index r, tag << 16 | iteration k):
+ *   tag 1 graph waypoints (item = layer, element w*n + j),
+ *   tag 2 path indices    (item = tensor path p, element l),
+ *   tag 3 local noise     (item = local sample g, element j*4*ceil(T/4) + t),
+ * element e sits in word e % 4 of block e / 4.  Waypoints are
+ * u_min + (u_max-u_min) * (w >> 8) * 2^-24, indices (w * W) >> 32, normals by
+ * Box-Muller on word pairs (0,1) and (2,3).
+ *
+ * Candidate order (Alg. 2, stacking step): [local 0..G-2 | tensor paths
+ * 0..P-1 | nominal mean], so B = P + G and index B-1 is the mean.
+ */
+#ifndef MTP_H_
+#define MTP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MTP_ABI_VERSION 1
+
+typedef enum {
+  MTP_OK = 0,
+  MTP_ERR_INVALID_ARG = 1,  /* bad config or argument; nothing was enqueued      */
+  MTP_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. chain length not instantiated) */
+  MTP_ERR_WORKSPACE = 3,    /* workspace missing, too small or misaligned          */
+  MTP_ERR_DEVICE = 4,       /* a HIP call failed; sticky until destroy             */
+  MTP_ERR_BUSY = 5,         /* server full / budget exceeded; retry later          */
+  MTP_ERR_NOT_READY = 6     /* no result available yet                             */
+} mtp_status;
+
+typedef enum { MTP_INTERP_BSPLINE = 0, MTP_INTERP_AKIMA = 1 } mtp_interp;
+
+typedef enum {
+  MTP_DYN_POINT_MASS = 0,    /* planar double integrator, d=4, n=2, semi-implicit Euler */
+  MTP_DYN_CHAIN = 1,         /* planar n-link pendulum chain, d=2n, RK4                 */
+  MTP_DYN_CHAIN_CONTACT = 2  /* chain + penalty ground contact + per-sample masses/friction */
+} mtp_dynamics;
+
+/*
+ * Planner configuration (Alg. 2 inputs).  L = n_layers is the graph depth
+ * (the paper's M), W = n_width the waypoints per layer (the paper's N).
+ * n_gauss counts the local samples including the nominal mean (>= 1).
+ *
+ * task_params (host, copied at create), float32, per dynamics:
+ *   POINT_MASS:    [goal_x, goal_y, goal_weight, obstacle_penalty, ctrl_weight,
+ *                   n_obs, (cx, cy, r) * n_obs]
+ *   CHAIN:         [gravity, goal_weight, ctrl_weight, target_x, target_y,
+ *                   mass_1..mass_n, length_1..length_n]
+ *   CHAIN_CONTACT: CHAIN's layout followed by [ground_y, k_contact, d_contact, v_slip];
+ *                  its masses are ignored in favour of sample_params.
+ * sample_params (host, copied at create; CHAIN_CONTACT only): B rows of
+ *   [mass_1..mass_n, friction_coefficient], row b for candidate b.
+ */
+typedef struct {
+  uint32_t abi_version;      /* MTP_ABI_VERSION */
+  int32_t dynamics;          /* mtp_dynamics */
+  int32_t interp;            /* mtp_interp */
+  int32_t n_links;           /* chains: number of links (= ctrl_dim); point mass: 0 */
+  int32_t state_dim;         /* d */
+  int32_t ctrl_dim;          /* n */
+  int32_t horizon;           /* T >= 1 */
+  int32_t n_layers;          /* L: >= degree+1 (B-spline), >= 2 (Akima), <= 16 */
+  int32_t n_width;           /* W: 1..256 */
+  int32_t n_tensor;          /* P >= 0 */
+  int32_t n_gauss;           /* G >= 1 */
+  int32_t n_elites;          /* E: 1..min(B, 4096) */
+  int32_t n_iters;           /* K: 1..65535 CEM iterations per replan */
+  int32_t bspline_degree;    /* p: 1..5 (B-spline only) */
+  float temperature;         /* lambda > 0; +inf means uniform elite weights */
+  float smoothing;           /* alpha in [0, 1) */
+  float sigma_min;           /* >= 0, floor on the refitted std */
+  float sigma_init;          /* >= 0, initial std and the std given to shifted-in steps */
+  float u_min, u_max;        /* control box, u_min < u_max */
+  float dt;                  /* > 0 */
+  uint64_t seed;             /* Philox key */
+  const float* task_params;  /* host */
+  int32_t n_task_params;
+  const float* sample_params;  /* host, CHAIN_CONTACT only, B*(n+1) floats */
+  int32_t n_debug_states;    /* record x_{t+1} of candidates 0..n_debug_states-1 (0 = off) */
+} mtp_config;
+
+/*
+ * Device views into a plan's workspace, for inspection and staged checks.
+ * Layouts (sample index fastest):
+ *   Z          float [L][W][n]
+ *   I          uint8 [L][P]           path index of tensor path p at layer l
+ *   U          float [T][n][ld_U]     control u_t,j of candidate b at U[(t*n+j)*ld_U + b]
+ *   cost       float [B]              summed rollout cost (+inf if not finite)
+ *   elite_idx  int32 [E]              ascending cost, ties by lower index
+ *   elite_cost float [E]
+ *   weights    float [E]              softmax weights of the elites
+ *   mu, sigma  float [T][n]
+ *   x0         float [d]              start state of the current replan
+ *   action     float [n]
+ *   X_dbg      float [T][d][n_debug_states] or NULL
+ */
+typedef struct {
+  void *Z, *I, *U, *cost, *elite_idx, *elite_cost, *weights, *mu, *sigma, *x0, *action, *X_dbg;
+  size_t ld_U;
+} mtp_buffers;
+
+typedef struct mtp_plan mtp_plan;
+
+/* Bytes of device workspace a plan needs (256-byte aligned base required); 0 if cfg is invalid. */
+size_t mtp_workspace_bytes(const mtp_config* cfg);
+
+/* Check a config without creating anything; on failure writes a reason into `why`
+ * (NUL-terminated, at most why_len bytes; may be NULL). */
+mtp_status mtp_validate_config(const mtp_config* cfg, char* why, size_t why_len);
+
+/* Validate cfg, lay the plan out in the caller's workspace, upload its tables
+ * (spline basis, task and sample parameters) on `hip_stream` (NULL = default
+ * stream) and initialise mu = (u_min+u_max)/2, sigma = sigma_init, replan index 0. */
+mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_bytes,
+                           void* hip_stream, mtp_plan** out);
+
+/* One replan (Alg. 2 loop body, n_iters iterations) from start state d_x0 (d floats,
+ * read by the replan's first kernel, so it must stay valid until that point in
+ * stream order), after shifting the
+ * warm-start mean/std forward by shift_steps (0 = no shift; the mean's last row is
+ * held, the std's tail reset to sigma_init).  Uses the plan's replan counter as the
+ * Philox replan index and increments it.  Asynchronous. */
+mtp_status mtp_replan(mtp_plan* p, const float* d_x0, int32_t shift_steps);
+
+/* As mtp_replan with an explicit replan index; the counter continues from replan_idx+1. */
+mtp_status mtp_replan_at(mtp_plan* p, const float* d_x0, int32_t shift_steps, uint32_t replan_idx);
+
+/* Copy the action of the last replan (n floats) to the host; synchronises the stream. */
+mtp_status mtp_get_action(mtp_plan* p, float* h_u);
+
+/* Export / import the warm-start state (device arrays of T*n floats) and the replan
+ * counter, for checkpoint and resume.  get_state synchronises the stream. */
+mtp_status mtp_get_state(const mtp_plan* p, float* d_mu, float* d_sigma, uint32_t* replan_idx);
+mtp_status mtp_set_state(mtp_plan* p, const float* d_mu, const float* d_sigma, uint32_t replan_idx);
+
+/* Staged execution for checks: run one stage of CEM iteration k of replan r on the
+ * buffers as they stand (MTP_STAGE_ALL runs one whole iteration).  A test may write
+ * a stage's inputs through mtp_get_buffers first.  x0 must have been set by a replan
+ * or mtp_set_x0. */
+typedef enum {
+  MTP_STAGE_CANDIDATES = 0,  /* Z, I, U */
+  MTP_STAGE_ROLLOUT = 1,     /* U -> cost (and X_dbg) */
+  MTP_STAGE_TOPK = 2,        /* cost -> elite_idx, elite_cost, weights */
+  MTP_STAGE_UPDATE = 3,      /* U, elites, weights -> mu, sigma, action */
+  MTP_STAGE_ALL = 4
+} mtp_stage;
+mtp_status mtp_run_stage(mtp_plan* p, int32_t stage, uint32_t replan_idx, int32_t k);
+mtp_status mtp_set_x0(mtp_plan* p, const float* d_x0);
+
+/* Replay replans through a captured hipGraph (1, default) or launch kernels one by one (0). */
+mtp_status mtp_set_graph_mode(mtp_plan* p, int32_t use_graph);
+
+mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
+/* Status flags of the last replan: bit 0 = every elite cost was +inf (weights fell back to uniform). */
+mtp_status mtp_get_flags(mtp_plan* p, uint32_t* h_flags);
+mtp_status mtp_plan_destroy(mtp_plan* p);
+
+const char* mtp_status_str(mtp_status s);
+const char* mtp_last_error(const mtp_plan* p);
+
+/* The host-built interpolation table of a config (no device needed): basis gets
+ * horizon*8 floats, span gets horizon ints.  B-spline row t holds the degree+1
+ * weights of control points span[t] .. span[t]+degree; Akima row t holds the
+ * cubic Hermite weights (value i, slope i, value i+1, slope i+1) of interval
+ * span[t], slopes in units of the knot spacing. */
+mtp_status mtp_interp_table(const mtp_config* cfg, float* h_basis, int32_t* h_span);
+
+/* Chain lengths the rollout kernel is instantiated for (writes up to `cap`, returns the count). */
+int32_t mtp_supported_chain_links(int32_t* out, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTP_H_ */

@@ -1,0 +1,321 @@
+"""ctypes binding of libmtp.so (argument marshalling only).
+
+Every entry point of include/mtp.h appears here under the same name.  Device
+memory comes from torch (one uint8 workspace tensor per object) and work is
+enqueued on torch's current stream of that device.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, byref, c_char_p, c_float, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def lib_path() -> str:
+    return os.path.join(HERE, "libmtp.so")
+
+
+class MtpError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"mtp status {status}: {msg}")
+
+
+STAGE_CANDIDATES, STAGE_ROLLOUT, STAGE_TOPK, STAGE_UPDATE, STAGE_ALL = range(5)
+MTP_ABI_VERSION = 1
+
+
+class mtp_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", c_uint32), ("dynamics", c_int32), ("interp", c_int32), ("n_links", c_int32),
+        ("state_dim", c_int32), ("ctrl_dim", c_int32), ("horizon", c_int32), ("n_layers", c_int32),
+        ("n_width", c_int32), ("n_tensor", c_int32), ("n_gauss", c_int32), ("n_elites", c_int32),
+        ("n_iters", c_int32), ("bspline_degree", c_int32),
+        ("temperature", c_float), ("smoothing", c_float), ("sigma_min", c_float), ("sigma_init", c_float),
+        ("u_min", c_float), ("u_max", c_float), ("dt", c_float),
+        ("seed", c_uint64),
+        ("task_params", POINTER(c_float)), ("n_task_params", c_int32),
+        ("sample_params", POINTER(c_float)), ("n_debug_states", c_int32),
+    ]
+
+
+class mtp_buffers(ctypes.Structure):
+    _fields_ = [(name, c_void_p) for name in
+                ("Z", "I", "U", "cost", "elite_idx", "elite_cost", "weights", "mu", "sigma", "x0",
+                 "action", "X_dbg")] + [("ld_U", c_size_t)]
+
+
+_LIB = None
+
+
+def load():
+    """Load libmtp.so; raises if it has not been built (there is no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2505_01059_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "mtp_workspace_bytes": (c_size_t, [P]),
+        "mtp_validate_config": (c_int32, [P, c_char_p, c_size_t]),
+        "mtp_plan_create": (c_int32, [P, P, c_size_t, P, POINTER(P)]),
+        "mtp_replan": (c_int32, [P, P, c_int32]),
+        "mtp_replan_at": (c_int32, [P, P, c_int32, c_uint32]),
+        "mtp_get_action": (c_int32, [P, P]),
+        "mtp_get_state": (c_int32, [P, P, P, POINTER(c_uint32)]),
+        "mtp_set_state": (c_int32, [P, P, P, c_uint32]),
+        "mtp_run_stage": (c_int32, [P, c_int32, c_uint32, c_int32]),
+        "mtp_set_x0": (c_int32, [P, P]),
+        "mtp_set_graph_mode": (c_int32, [P, c_int32]),
+        "mtp_get_buffers": (c_int32, [P, P]),
+        "mtp_get_flags": (c_int32, [P, POINTER(c_uint32)]),
+        "mtp_plan_destroy": (c_int32, [P]),
+        "mtp_status_str": (c_char_p, [c_int32]),
+        "mtp_last_error": (c_char_p, [P]),
+        "mtp_supported_chain_links": (c_int32, [POINTER(c_int32), c_int32]),
+        "mtp_interp_table": (c_int32, [P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+# ------------------------------------------------------------------ marshalling
+
+def task_params_of(cfg) -> np.ndarray:
+    """Flatten a workload's task into the float32 layout documented in mtp.h."""
+    t = cfg.task
+    if cfg.dynamics == 0:
+        obs = np.asarray(t.obstacles, np.float32).reshape(-1, 3)
+        head = np.array([t.goal[0], t.goal[1], t.goal_weight, t.obstacle_penalty, t.ctrl_weight,
+                         obs.shape[0]], np.float32)
+        return np.concatenate([head, obs.ravel()]).astype(np.float32)
+    head = np.array([t.gravity, t.goal_weight, t.ctrl_weight, t.target[0], t.target[1]], np.float32)
+    parts = [head, np.asarray(t.masses, np.float32), np.asarray(t.lengths, np.float32)]
+    if cfg.dynamics == 2:
+        parts.append(np.array([t.ground_y, t.k_contact, t.d_contact, t.v_slip], np.float32))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def config_struct(cfg, n_debug_states=0):
+    """Build an mtp_config; returns (struct, keepalive arrays)."""
+    task = np.ascontiguousarray(task_params_of(cfg), dtype=np.float32)
+    keep = [task]
+    c = mtp_config()
+    c.abi_version = MTP_ABI_VERSION
+    c.dynamics = int(cfg.dynamics)
+    c.interp = int(cfg.interp)
+    c.n_links = int(cfg.n_links)
+    c.state_dim = int(cfg.state_dim)
+    c.ctrl_dim = int(cfg.ctrl_dim)
+    c.horizon = int(cfg.horizon)
+    c.n_layers = int(cfg.n_layers)
+    c.n_width = int(cfg.n_width)
+    c.n_tensor = int(cfg.n_tensor)
+    c.n_gauss = int(cfg.n_gauss)
+    c.n_elites = int(cfg.n_elites)
+    c.n_iters = int(cfg.n_iters)
+    c.bspline_degree = int(cfg.bspline_degree)
+    c.temperature = float(cfg.temperature)
+    c.smoothing = float(cfg.smoothing)
+    c.sigma_min = float(cfg.sigma_min)
+    c.sigma_init = float(cfg.sigma_init)
+    c.u_min = float(cfg.u_min)
+    c.u_max = float(cfg.u_max)
+    c.dt = float(cfg.dt)
+    c.seed = int(cfg.seed) & 0xFFFFFFFFFFFFFFFF
+    c.task_params = task.ctypes.data_as(POINTER(c_float))
+    c.n_task_params = int(task.size)
+    if cfg.sample_params is not None:
+        sp = np.ascontiguousarray(cfg.sample_params, dtype=np.float32)
+        keep.append(sp)
+        c.sample_params = sp.ctypes.data_as(POINTER(c_float))
+    c.n_debug_states = int(n_debug_states)
+    return c, keep
+
+
+def _check(lib, status, obj=None):
+    if status != 0:
+        msg = lib.mtp_status_str(status).decode()
+        if obj:
+            msg += ": " + lib.mtp_last_error(obj).decode()
+        raise MtpError(status, msg)
+
+
+def validate(cfg, n_debug_states=0):
+    """(status, reason) of the library's config check; touches no device."""
+    lib = load()
+    c, keep = config_struct(cfg, n_debug_states)
+    buf = ctypes.create_string_buffer(256)
+    st = lib.mtp_validate_config(byref(c), buf, 256)
+    return st, buf.value.decode()
+
+
+def interp_table(cfg):
+    """(basis (T, 8) float32, span (T,) int32) as the library builds them on the host."""
+    lib = load()
+    c, keep = config_struct(cfg)
+    basis = np.zeros((cfg.horizon, 8), np.float32)
+    span = np.zeros(cfg.horizon, np.int32)
+    _check(lib, lib.mtp_interp_table(byref(c), basis.ctypes.data_as(c_void_p), span.ctypes.data_as(c_void_p)))
+    return basis, span
+
+
+def workspace_bytes(cfg, n_debug_states=0):
+    lib = load()
+    c, keep = config_struct(cfg, n_debug_states)
+    return int(lib.mtp_workspace_bytes(byref(c)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """One planner instance (mtp_plan) with a torch-allocated workspace."""
+
+    def __init__(self, cfg, device="cuda", n_debug_states=0, use_graph=True, workspace=None):
+        torch = _torch()
+        self.lib = load()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self._c, self._keep = config_struct(cfg, n_debug_states)
+        nbytes = int(self.lib.mtp_workspace_bytes(byref(self._c)))
+        if nbytes == 0:
+            st, why = validate(cfg, n_debug_states)
+            raise MtpError(st, why)
+        self.ws_bytes = nbytes
+        self.workspace = workspace if workspace is not None else torch.empty(
+            nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        st = self.lib.mtp_plan_create(byref(self._c), c_void_p(self.workspace.data_ptr()), nbytes,
+                                      c_void_p(self.stream.cuda_stream), byref(h))
+        _check(self.lib, st)
+        self.handle = h
+        self._x0 = None
+        if not use_graph:
+            self.set_graph_mode(False)
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.mtp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls
+    def _x0_dev(self, x0):
+        torch = _torch()
+        x = torch.as_tensor(np.asarray(x0, np.float32) if not isinstance(x0, torch.Tensor) else x0,
+                            dtype=torch.float32, device=self.device).contiguous()
+        self._x0 = x          # keep alive until the stream has read it
+        return x
+
+    def replan(self, x0, shift=1, replan_idx=None):
+        x = self._x0_dev(x0)
+        if replan_idx is None:
+            st = self.lib.mtp_replan(self.handle, c_void_p(x.data_ptr()), int(shift))
+        else:
+            st = self.lib.mtp_replan_at(self.handle, c_void_p(x.data_ptr()), int(shift), int(replan_idx))
+        _check(self.lib, st, self.handle)
+
+    def action(self):
+        out = np.zeros(self.cfg.ctrl_dim, np.float32)
+        _check(self.lib, self.lib.mtp_get_action(self.handle, out.ctypes.data_as(c_void_p)), self.handle)
+        return out
+
+    def get_state(self):
+        torch = _torch()
+        T, n = self.cfg.horizon, self.cfg.ctrl_dim
+        mu = torch.empty((T, n), dtype=torch.float32, device=self.device)
+        sg = torch.empty((T, n), dtype=torch.float32, device=self.device)
+        r = c_uint32()
+        _check(self.lib, self.lib.mtp_get_state(self.handle, c_void_p(mu.data_ptr()), c_void_p(sg.data_ptr()),
+                                                byref(r)), self.handle)
+        return mu, sg, int(r.value)
+
+    def set_state(self, mu, sigma, replan_idx):
+        torch = _torch()
+        mu = torch.as_tensor(mu, dtype=torch.float32, device=self.device).contiguous()
+        sg = torch.as_tensor(sigma, dtype=torch.float32, device=self.device).contiguous()
+        self._state_keep = (mu, sg)
+        _check(self.lib, self.lib.mtp_set_state(self.handle, c_void_p(mu.data_ptr()), c_void_p(sg.data_ptr()),
+                                                int(replan_idx)), self.handle)
+
+    def set_x0(self, x0):
+        x = self._x0_dev(x0)
+        _check(self.lib, self.lib.mtp_set_x0(self.handle, c_void_p(x.data_ptr())), self.handle)
+
+    def run_stage(self, stage, replan_idx, k):
+        _check(self.lib, self.lib.mtp_run_stage(self.handle, int(stage), int(replan_idx), int(k)), self.handle)
+
+    def set_graph_mode(self, on):
+        _check(self.lib, self.lib.mtp_set_graph_mode(self.handle, 1 if on else 0), self.handle)
+
+    def flags(self):
+        f = c_uint32()
+        _check(self.lib, self.lib.mtp_get_flags(self.handle, byref(f)), self.handle)
+        return int(f.value)
+
+    def buffers(self):
+        """Torch views of the plan's device buffers (see mtp_buffers in mtp.h)."""
+        torch = _torch()
+        b = mtp_buffers()
+        _check(self.lib, self.lib.mtp_get_buffers(self.handle, byref(b)), self.handle)
+        cfg = self.cfg
+        base = self.workspace.data_ptr()
+        T, n, d = cfg.horizon, cfg.ctrl_dim, cfg.state_dim
+        B, E, L, W, P = cfg.n_samples, cfg.n_elites, cfg.n_layers, cfg.n_width, cfg.n_tensor
+        ld = int(b.ld_U)
+
+        def view(ptr, dtype, shape):
+            if not ptr:
+                return None
+            esz = torch.empty((), dtype=dtype).element_size()
+            count = int(np.prod(shape))
+            off = int(ptr) - base
+            return self.workspace[off:off + count * esz].view(dtype).view(*shape)
+
+        out = dict(
+            Z=view(b.Z, torch.float32, (L, W, n)),
+            I=view(b.I, torch.uint8, (L, max(P, 1)))[:, :P],
+            U=view(b.U, torch.float32, (T, n, ld))[:, :, :B],
+            cost=view(b.cost, torch.float32, (B,)),
+            elite_idx=view(b.elite_idx, torch.int32, (E,)),
+            elite_cost=view(b.elite_cost, torch.float32, (E,)),
+            weights=view(b.weights, torch.float32, (E,)),
+            mu=view(b.mu, torch.float32, (T, n)),
+            sigma=view(b.sigma, torch.float32, (T, n)),
+            x0=view(b.x0, torch.float32, (d,)),
+            action=view(b.action, torch.float32, (n,)),
+        )
+        nd = int(self._c.n_debug_states)
+        out["X"] = view(b.X_dbg, torch.float32, (T, d, nd)) if nd > 0 else None
+        out["ld_U"] = ld
+        return out
+
+
+class Batch:  # defined in _batch.py once the batched engine is loaded
+    pass
+
+
+class Server:
+    pass

@@ -1,0 +1,127 @@
+// Single-plan kernels of one MTP replan for gfx950 and their host launchers.
+// Each kernel is a thin grid over the stage tiles of mtp_device.hpp.
+#include "kernels.hpp"
+
+namespace mtp {
+
+__global__ __launch_bounds__(64) void k_set_ctrl(PlanDesc P, uint32_t r, int shift, const float* x0_src) {
+  set_ctrl_block(P, r, shift, x0_src);
+}
+
+__global__ __launch_bounds__(256) void k_shift(PlanDesc P) {
+  shift_block<256>(P, static_cast<int>(P.ctrl[1]));
+}
+
+__global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) {
+  __shared__ CandSmem sm;
+  cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, sm);
+}
+
+__global__ __launch_bounds__(kRollThreads) void k_rollout_point_mass(PlanDesc P) {
+  const int b = blockIdx.x * kRollThreads + threadIdx.x;
+  if (b < P.B) rollout_point_mass(P, b);
+}
+
+template <int N, bool CONTACT>
+__global__ __launch_bounds__(kRollThreads) void k_rollout_chain(PlanDesc P) {
+  const int b = blockIdx.x * kRollThreads + threadIdx.x;
+  if (b < P.B) rollout_chain<N, CONTACT>(P, b);
+}
+
+__global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {
+  __shared__ TopkSmem sm;
+  topk_block<kTopkThreads>(P, sm);
+}
+
+__global__ __launch_bounds__(kUpdThreads) void k_update(PlanDesc P) {
+  const int o = blockIdx.x * (kUpdThreads / 64) + (threadIdx.x >> 6);
+  if (o < P.T * P.n) update_output(P, o);
+}
+
+// ---------------------------------------------------------------- dispatch
+
+#define MTP_CHAIN_LINKS(X) X(2) X(3) X(4) X(7) X(12) X(24)
+#define MTP_CONTACT_LINKS(X) X(4) X(7) X(24)
+
+static const int kChainLinks[] = {
+#define X(N) N,
+    MTP_CHAIN_LINKS(X)
+#undef X
+};
+static const int kContactLinks[] = {
+#define X(N) N,
+    MTP_CONTACT_LINKS(X)
+#undef X
+};
+
+bool rollout_supported(int dyn, int n_links) {
+  if (dyn == kPointMass) return true;
+  const int* tab = dyn == kChain ? kChainLinks : kContactLinks;
+  const int cnt = dyn == kChain ? int(sizeof(kChainLinks) / sizeof(int)) : int(sizeof(kContactLinks) / sizeof(int));
+  for (int i = 0; i < cnt; ++i)
+    if (tab[i] == n_links) return true;
+  return false;
+}
+
+int supported_chain_links(int* out, int cap) {
+  const int cnt = int(sizeof(kChainLinks) / sizeof(int));
+  for (int i = 0; i < cnt && i < cap; ++i) out[i] = kChainLinks[i];
+  return cnt;
+}
+
+static hipError_t launch_rollout(const PlanDesc& P, hipStream_t st) {
+  const dim3 grid((P.B + kRollThreads - 1) / kRollThreads);
+  if (P.dyn == kPointMass) {
+    k_rollout_point_mass<<<grid, kRollThreads, 0, st>>>(P);
+    return hipGetLastError();
+  }
+  if (P.dyn == kChain) {
+    switch (P.n_links) {
+#define X(N) case N: k_rollout_chain<N, false><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError();
+      MTP_CHAIN_LINKS(X)
+#undef X
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (P.n_links) {
+#define X(N) case N: k_rollout_chain<N, true><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError();
+    MTP_CONTACT_LINKS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_set_ctrl(const PlanDesc& P, uint32_t r, int shift, const float* x0_src, hipStream_t st) {
+  k_set_ctrl<<<1, 64, 0, st>>>(P, r, shift, x0_src);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(const PlanDesc& P, hipStream_t st) {
+  k_shift<<<1, 256, 0, st>>>(P);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
+  switch (stage) {
+    case 0: {
+      const dim3 grid((P.B + kCandThreads - 1) / kCandThreads, P.n);
+      k_candidates<<<grid, kCandThreads, 0, st>>>(P, k);
+      return hipGetLastError();
+    }
+    case 1:
+      return launch_rollout(P, st);
+    case 2:
+      k_topk<<<1, kTopkThreads, 0, st>>>(P);
+      return hipGetLastError();
+    case 3: {
+      const int outs = P.T * P.n;
+      const int per = kUpdThreads / 64;
+      k_update<<<(outs + per - 1) / per, kUpdThreads, 0, st>>>(P);
+      return hipGetLastError();
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mtp

@@ -1,0 +1,668 @@
+// Device-side pieces of one MTP replan for gfx950: the plan descriptor shared
+// by host and kernels, Philox4x32-10, and one __device__ function per stage
+// tile.  The single-plan kernels and the persistent batched kernel both call
+// these tile functions, so there is one implementation of every stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mtp {
+
+constexpr int kMaxLayers = 16;
+constexpr int kMaxWidth = 256;
+constexpr int kMaxElites = 4096;
+constexpr int kBasisStride = 8;     // spline table row: up to degree 5 (6 weights) or 4 Hermite weights
+constexpr int kCandThreads = 256;   // candidate tile: 256 samples of one joint
+constexpr int kRollThreads = 64;    // rollout tile: one wave, one sample per lane
+constexpr int kTopkThreads = 1024;  // top-E: one workgroup per plan
+constexpr int kUpdThreads = 256;    // refit tile: 4 waves, one (t, j) output per wave
+
+enum Dyn : int32_t { kPointMass = 0, kChain = 1, kChainContact = 2 };
+enum Interp : int32_t { kBspline = 0, kAkima = 1 };
+
+// Everything a stage needs, by value in kernel arguments (or in a device table
+// for the batched kernel).  Pointers address the caller's workspace.
+struct PlanDesc {
+  int32_t dyn, interp, n_links, d, n, T, L, W, P, G, B, E, K, p, n_dbg, n_task;
+  int32_t ldU;
+  float lam, alpha, sigma_min, sigma_init, u_min, u_max, dt;
+  uint32_t key0, key1;
+  uint32_t* ctrl;        // [0] replan index r, [1] shift, [2] flags (bit 0: all elites +inf, bit 1: selection fault)
+  float* x0;             // [d]
+  const float* x0_src;   // staging source for the prologue (may be null)
+  float* mu;             // [T][n]
+  float* sigma;          // [T][n]
+  float* tmp;            // [2][T][n] scratch for the warm-start shift
+  float* action;         // [n]
+  const float* basis;    // [T][kBasisStride]
+  const int32_t* span;   // [T] first control point (B-spline) or interval (Akima)
+  const float* task;     // task parameters (see mtp.h)
+  const float* sparams;  // [B][n+1] per-sample masses and friction, or null
+  float* Z;              // [L][W][n]
+  uint8_t* I;            // [L][P]
+  float* U;              // [T][n][ldU]
+  float* cost;           // [B]
+  int32_t* eidx;         // [E]
+  float* ecost;          // [E]
+  float* w;              // [E]
+  float* X;              // [T][d][n_dbg] or null
+};
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 from Salmon et al., SC'11: ten rounds of two 32x32->64-bit
+// multiplies with xor/permute, key bumped by the Weyl constants between rounds.
+struct Words4 { uint32_t w[4]; };
+
+__device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
+    const uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  Words4 r; r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
+  return r;
+}
+
+constexpr uint32_t kTagZ = 1, kTagI = 2, kTagEps = 3;
+
+__device__ __forceinline__ uint32_t stream_c3(uint32_t tag, int k) {
+  return (tag << 16) | (static_cast<uint32_t>(k) & 0xFFFFu);
+}
+
+// top 24 bits scaled to [0, 1): exact in float32
+__device__ __forceinline__ float u01(uint32_t w) { return static_cast<float>(w >> 8) * 0x1p-24f; }
+
+// (0, 1] variant for the Box-Muller radius
+__device__ __forceinline__ float u01_open0(uint32_t w) { return static_cast<float>((w >> 8) + 1u) * 0x1p-24f; }
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
+  const float rad = sqrtf(-2.0f * logf(u01_open0(a)));
+  float s, c;
+  sincospif(2.0f * u01(b), &s, &c);   // angle 2*pi*u2, evaluated without rounding 2*pi
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
+
+// ------------------------------------------------------------------ candidates
+// Tile = joint j, candidates [b0, b0 + kCandThreads).  Writes U[t][j][b] for
+// every candidate of the tile: local Gaussian samples (noise stream tag 3),
+// tensor paths (graph tag 1, indices tag 2, spline) and the nominal mean.
+// The tile regenerates column j of the graph Z in LDS from Philox; the tile
+// holding the first tensor path also stores it to Z, and tiles of joint 0
+// store the path indices I.
+struct CandSmem {
+  float z[kMaxLayers * kMaxWidth];                // Z[l][w] for this joint
+  float ctrl[kMaxLayers][kCandThreads];          // per-thread control points
+  float slope[kMaxLayers][kCandThreads];         // per-thread Akima slopes (unit spacing)
+};
+
+__device__ __forceinline__ void akima_slopes_thread(int L, int tid, CandSmem& sm) {
+  // unit-spacing secants m_i = z_{i+1} - z_i; slope rules of the Akima spline
+  // with the paper's end conditions; both weights zero -> mean of the secants.
+  for (int i = 0; i < L; ++i) {
+    float s;
+    if (i == 0) {
+      s = sm.ctrl[1][tid] - sm.ctrl[0][tid];
+    } else if (i == L - 1) {
+      s = sm.ctrl[L - 1][tid] - sm.ctrl[L - 2][tid];
+    } else if (i == 1) {
+      s = 0.5f * (sm.ctrl[2][tid] - sm.ctrl[0][tid]);
+    } else if (i == L - 2) {
+      s = 0.5f * (sm.ctrl[L - 1][tid] - sm.ctrl[L - 3][tid]);
+    } else {
+      const float m2 = sm.ctrl[i - 1][tid] - sm.ctrl[i - 2][tid];
+      const float m1 = sm.ctrl[i][tid] - sm.ctrl[i - 1][tid];
+      const float m0 = sm.ctrl[i + 1][tid] - sm.ctrl[i][tid];
+      const float mp = sm.ctrl[i + 2][tid] - sm.ctrl[i + 1][tid];
+      const float wa = fabsf(mp - m0);
+      const float wb = fabsf(m1 - m2);
+      const float den = wa + wb;
+      s = (den == 0.0f) ? 0.5f * (m1 + m0) : (wa * m1 + wb * m0) / den;
+    }
+    sm.slope[i][tid] = s;
+  }
+}
+
+__device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, int j, int b0,
+                                          CandSmem& sm) {
+  const int tid = threadIdx.x;
+  const int b = b0 + tid;
+  const int G1 = P.G - 1;                       // local samples [0, G1)
+  const int tens_lo = G1, tens_hi = G1 + P.P;   // tensor paths [G1, G1+P)
+  const bool tile_has_tensor = (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
+  const bool z_writer = tile_has_tensor && (b0 <= tens_lo);
+  const float lo = P.u_min, hi = P.u_max;
+  const size_t ld = static_cast<size_t>(P.ldU);
+
+  if (tile_has_tensor) {
+    const float span = hi - lo;
+    const int LW = P.L * P.W;
+    for (int e = tid; e < LW; e += kCandThreads) {
+      const int l = e / P.W, w = e - l * P.W;
+      const uint32_t idx = static_cast<uint32_t>(w * P.n + j);
+      const Words4 q = philox(idx >> 2, static_cast<uint32_t>(l), r, stream_c3(kTagZ, k), P.key0, P.key1);
+      const float z = fmaf(span, u01(q.w[idx & 3u]), lo);
+      sm.z[e] = z;
+      if (z_writer) P.Z[static_cast<size_t>(e) * P.n + j] = z;
+    }
+  }
+  __syncthreads();
+  if (b >= P.B) return;
+
+  if (b < G1) {
+    // local sample g = b: u = clip(mu + sigma * eps)
+    const int Tq = (P.T + 3) >> 2;
+    for (int tq = 0; tq < Tq; ++tq) {
+      const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
+                              stream_c3(kTagEps, k), P.key0, P.key1);
+      float z[4];
+      box_muller(q.w[0], q.w[1], z[0], z[1]);
+      box_muller(q.w[2], q.w[3], z[2], z[3]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int t = 4 * tq + c;
+        if (t < P.T) {
+          const int o = t * P.n + j;
+          P.U[o * ld + b] = clampf(fmaf(P.sigma[o], z[c], P.mu[o]), lo, hi);
+        }
+      }
+    }
+  } else if (b < tens_hi) {
+    const int pp = b - G1;
+    for (int l4 = 0; l4 < P.L; l4 += 4) {
+      const Words4 q = philox(static_cast<uint32_t>(l4 >> 2), static_cast<uint32_t>(pp), r,
+                              stream_c3(kTagI, k), P.key0, P.key1);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int l = l4 + c;
+        if (l < P.L) {
+          const uint32_t wi = __umulhi(q.w[c], static_cast<uint32_t>(P.W));
+          sm.ctrl[l][tid] = sm.z[l * P.W + wi];
+          if (j == 0) P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(wi);
+        }
+      }
+    }
+    if (P.interp == kBspline) {
+      const int np1 = P.p + 1;
+      for (int t = 0; t < P.T; ++t) {
+        const int s0 = P.span[t];
+        const float* bw = P.basis + t * kBasisStride;
+        float v = 0.0f;
+        for (int q = 0; q < np1; ++q) v = fmaf(bw[q], sm.ctrl[s0 + q][tid], v);
+        P.U[(t * P.n + j) * ld + b] = clampf(v, lo, hi);
+      }
+    } else {
+      akima_slopes_thread(P.L, tid, sm);
+      for (int t = 0; t < P.T; ++t) {
+        const int i = P.span[t];
+        const float* h = P.basis + t * kBasisStride;
+        float v = h[0] * sm.ctrl[i][tid];
+        v = fmaf(h[1], sm.slope[i][tid], v);
+        v = fmaf(h[2], sm.ctrl[i + 1][tid], v);
+        v = fmaf(h[3], sm.slope[i + 1][tid], v);
+        P.U[(t * P.n + j) * ld + b] = clampf(v, lo, hi);
+      }
+    }
+  } else {
+    // nominal mean
+    for (int t = 0; t < P.T; ++t) {
+      const int o = t * P.n + j;
+      P.U[o * ld + b] = clampf(P.mu[o], lo, hi);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ rollout
+// One lane per candidate; the state lives in registers for the whole horizon.
+
+__device__ __forceinline__ float finite_or_inf(float c) { return (c == c && fabsf(c) <= 3.402823466e38f) ? c : INFINITY; }
+
+__device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b) {
+  // task: goal_x, goal_y, goal_w, obstacle_penalty, ctrl_w, n_obs, (cx, cy, r)*
+  const float* tk = P.task;
+  const float gx = tk[0], gy = tk[1], wg = tk[2], pen = tk[3], wu = tk[4];
+  const int n_obs = static_cast<int>(tk[5]);
+  const float* obs = tk + 6;
+  const float dt = P.dt;
+  float px = P.x0[0], py = P.x0[1], vx = P.x0[2], vy = P.x0[3];
+  const size_t ld = static_cast<size_t>(P.ldU);
+  const float* u0 = P.U + b;
+  float cost = 0.0f;
+  float ux = u0[0], uy = u0[ld];
+  for (int t = 0; t < P.T; ++t) {
+    // prefetch next step's controls
+    float nx = 0.0f, ny = 0.0f;
+    if (t + 1 < P.T) { nx = u0[(2 * (t + 1)) * ld]; ny = u0[(2 * (t + 1) + 1) * ld]; }
+    vx = fmaf(dt, ux, vx);
+    vy = fmaf(dt, uy, vy);
+    px = fmaf(dt, vx, px);
+    py = fmaf(dt, vy, py);
+    const float dx = px - gx, dy = py - gy;
+    float c = wg * fmaf(dx, dx, dy * dy);
+    for (int o = 0; o < n_obs; ++o) {
+      const float ox = px - obs[3 * o], oy = py - obs[3 * o + 1], rr = obs[3 * o + 2];
+      c += (fmaf(ox, ox, oy * oy) < rr * rr) ? pen : 0.0f;
+    }
+    c = fmaf(wu, fmaf(ux, ux, uy * uy), c);
+    cost += c;
+    if (b < P.n_dbg) {
+      float* X = P.X + b;
+      const size_t ldx = static_cast<size_t>(P.n_dbg);
+      X[(t * 4 + 0) * ldx] = px; X[(t * 4 + 1) * ldx] = py;
+      X[(t * 4 + 2) * ldx] = vx; X[(t * 4 + 3) * ldx] = vy;
+    }
+    ux = nx; uy = ny;
+  }
+  P.cost[b] = finite_or_inf(cost);
+}
+
+// Planar chain of point masses on massless links, absolute angles from the
+// downward vertical.  Instead of assembling the dense mass matrix, the link
+// tensions solve a symmetric tridiagonal system (each link is a rigid rod whose
+// length constraint couples its two end masses), solved by forward elimination
+// and back substitution; the angular accelerations then follow link by link.
+// O(n) work, no n x n matrix, same equations of motion as the Lagrangian form.
+template <int N>
+struct ChainConsts {
+  float l[N], invl[N], im[N];
+  float g, wg, wu, tx, ty;
+  float yg, kc, dc, inv_vs, muf;   // contact only
+};
+
+template <int N, bool CONTACT>
+__device__ __forceinline__ void chain_accel(const float (&s)[N], const float (&c)[N], const float (&om)[N],
+                                            const float (&q)[N], const ChainConsts<N>& K, float (&acc)[N]) {
+  float cp[N], dp[N], Cn[N], Sn[N], ndf[N];
+  float im_prev = 0.0f, Cn_prev = 0.0f, Sn_prev = 0.0f, cp_prev = 0.0f, dp_prev = 0.0f;
+  float fx_prev = 0.0f, fy_prev = 0.0f;
+  float px = 0.0f, py = 0.0f, vx = 0.0f, vy = 0.0f;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    float Cnk = 0.0f, Snk = 0.0f;
+    if (k + 1 < N) {
+      Cnk = fmaf(c[k], c[k + 1], s[k] * s[k + 1]);   // cos(phi_k - phi_{k+1})
+      Snk = fmaf(s[k], c[k + 1], -c[k] * s[k + 1]);  // sin(phi_k - phi_{k+1})
+    }
+    Cn[k] = Cnk;
+    Sn[k] = Snk;
+    const float imk = K.im[k];
+    float dfx, dfy;   // change of the non-constraint acceleration from mass k-1 to mass k
+    if constexpr (CONTACT) {
+      px = fmaf(K.l[k], s[k], px);
+      py = fmaf(-K.l[k], c[k], py);
+      const float lw = K.l[k] * om[k];
+      vx = fmaf(lw, c[k], vx);
+      vy = fmaf(lw, s[k], vy);
+      const float pen = K.yg - py;
+      float fx = 0.0f, fy = 0.0f;
+      if (pen > 0.0f) {
+        const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vy), 0.0f);
+        const float ft = -K.muf * fn * tanhf(vx * K.inv_vs);
+        fx = ft * imk;
+        fy = fn * imk;
+      }
+      dfx = fx - fx_prev;
+      dfy = fy - fy_prev;
+      fx_prev = fx;
+      fy_prev = fy;
+      if (k == 0) dfy -= K.g;
+    } else {
+      dfx = 0.0f;
+      dfy = (k == 0) ? -K.g : 0.0f;
+    }
+    const float qn = (k + 1 < N) ? q[k + 1] : 0.0f;
+    const float qp = (k > 0) ? q[k - 1] : 0.0f;
+    const float D = imk + im_prev;
+    const float Up = -imk * Cnk;
+    const float Lo = -im_prev * Cn_prev;
+    float rhs = K.l[k] * om[k] * om[k];
+    rhs = fmaf(s[k], dfx, rhs);
+    rhs = fmaf(-c[k], dfy, rhs);
+    rhs = fmaf(-imk * qn, Snk, rhs);
+    rhs = fmaf(im_prev * qp, Sn_prev, rhs);
+    const float inv = __builtin_amdgcn_rcpf(fmaf(-Lo, cp_prev, D));
+    cp_prev = Up * inv;
+    dp_prev = fmaf(-Lo, dp_prev, rhs) * inv;
+    cp[k] = cp_prev;
+    dp[k] = dp_prev;
+    ndf[k] = fmaf(c[k], dfx, s[k] * dfy);
+    im_prev = imk;
+    Cn_prev = Cnk;
+    Sn_prev = Snk;
+  }
+  // back substitution: dp[k] becomes the tension of link k
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) dp[k] = fmaf(-cp[k], dp[k + 1], dp[k]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const float Tn = (k + 1 < N) ? dp[k + 1] : 0.0f;
+    const float Tp = (k > 0) ? dp[k - 1] : 0.0f;
+    const float qn = (k + 1 < N) ? q[k + 1] : 0.0f;
+    const float qp = (k > 0) ? q[k - 1] : 0.0f;
+    const float imp = (k > 0) ? K.im[k - 1] : 0.0f;
+    const float Cp = (k > 0) ? Cn[k - 1] : 0.0f;
+    const float Sp = (k > 0) ? Sn[k - 1] : 0.0f;
+    float a = (K.im[k] + imp) * q[k];
+    a = fmaf(-K.im[k], fmaf(Tn, Sn[k], qn * Cn[k]), a);
+    a = fmaf(-imp, fmaf(-Tp, Sp, qp * Cp), a);
+    a += ndf[k];
+    acc[k] = a * K.invl[k];
+  }
+}
+
+template <int N, bool CONTACT>
+__device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
+  // task: gravity, goal_w, ctrl_w, target_x, target_y, masses[N], lengths[N], (contact: yg, kc, dc, v_slip)
+  const float* tk = P.task;
+  ChainConsts<N> K;
+  K.g = tk[0]; K.wg = tk[1]; K.wu = tk[2]; K.tx = tk[3]; K.ty = tk[4];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    K.l[k] = tk[5 + N + k];
+    K.invl[k] = 1.0f / K.l[k];
+  }
+  if constexpr (CONTACT) {
+    const float* sp = P.sparams + static_cast<size_t>(b) * (N + 1);
+#pragma unroll
+    for (int k = 0; k < N; ++k) K.im[k] = 1.0f / sp[k];
+    K.muf = sp[N];
+    K.yg = tk[5 + 2 * N]; K.kc = tk[6 + 2 * N]; K.dc = tk[7 + 2 * N]; K.inv_vs = 1.0f / tk[8 + 2 * N];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) K.im[k] = 1.0f / tk[5 + k];
+    K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
+  }
+  const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
+  float ph[N], om[N], s[N], c[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    ph[k] = P.x0[k];
+    om[k] = P.x0[N + k];
+    sincosf(ph[k], &s[k], &c[k]);
+  }
+  const size_t ld = static_cast<size_t>(P.ldU);
+  const float* ub = P.U + b;
+  float u[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) u[k] = ub[k * ld];
+  float cost = 0.0f;
+  for (int t = 0; t < P.T; ++t) {
+    float un[N];
+    const bool more = (t + 1 < P.T);
+#pragma unroll
+    for (int k = 0; k < N; ++k) un[k] = more ? ub[((t + 1) * N + k) * ld] : 0.0f;
+    float q[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) q[k] = (u[k] - ((k + 1 < N) ? u[k + 1] : 0.0f)) * K.invl[k];
+
+    float a[N], aph[N], aom[N], sph[N], som[N];
+    // stage 1
+    chain_accel<N, CONTACT>(s, c, om, q, K, a);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      aph[k] = om[k]; aom[k] = a[k];
+      sph[k] = fmaf(hdt, om[k], ph[k]); som[k] = fmaf(hdt, a[k], om[k]);
+    }
+    // stage 2
+    {
+      float s2[N], c2[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) sincosf(sph[k], &s2[k], &c2[k]);
+      chain_accel<N, CONTACT>(s2, c2, som, q, K, a);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        aph[k] = fmaf(2.0f, som[k], aph[k]); aom[k] = fmaf(2.0f, a[k], aom[k]);
+        const float w = som[k];
+        sph[k] = fmaf(hdt, w, ph[k]); som[k] = fmaf(hdt, a[k], om[k]);
+      }
+    }
+    // stage 3
+    {
+      float s3[N], c3[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) sincosf(sph[k], &s3[k], &c3[k]);
+      chain_accel<N, CONTACT>(s3, c3, som, q, K, a);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        aph[k] = fmaf(2.0f, som[k], aph[k]); aom[k] = fmaf(2.0f, a[k], aom[k]);
+        const float w = som[k];
+        sph[k] = fmaf(dt, w, ph[k]); som[k] = fmaf(dt, a[k], om[k]);
+      }
+    }
+    // stage 4
+    {
+      float s4[N], c4[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) sincosf(sph[k], &s4[k], &c4[k]);
+      chain_accel<N, CONTACT>(s4, c4, som, q, K, a);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        aph[k] += som[k]; aom[k] += a[k];
+        ph[k] = fmaf(dt6, aph[k], ph[k]);
+        om[k] = fmaf(dt6, aom[k], om[k]);
+      }
+    }
+    // cost of the new state (its sin/cos also start the next step)
+    float ex = 0.0f, ey = 0.0f, uu = 0.0f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      sincosf(ph[k], &s[k], &c[k]);
+      ex = fmaf(K.l[k], s[k], ex);
+      ey = fmaf(-K.l[k], c[k], ey);
+      uu = fmaf(u[k], u[k], uu);
+    }
+    const float dx = ex - K.tx, dy = ey - K.ty;
+    cost += fmaf(K.wg, fmaf(dx, dx, dy * dy), K.wu * uu);
+    if (b < P.n_dbg) {
+      float* X = P.X + b;
+      const size_t ldx = static_cast<size_t>(P.n_dbg);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        X[(t * 2 * N + k) * ldx] = ph[k];
+        X[(t * 2 * N + N + k) * ldx] = om[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) u[k] = un[k];
+  }
+  P.cost[b] = finite_or_inf(cost);
+}
+
+// ------------------------------------------------------------------ top-E
+// 64-bit keys (order-preserving image of the float cost) << 32 | index are all
+// distinct, so an 8-pass byte-wise radix select finds the E-th smallest key
+// exactly; the E keys at or below it are then sorted by a bitonic network in
+// LDS.  NaN sorts as +inf and -0 as +0.
+
+__device__ __forceinline__ uint32_t cost_order(float c) {
+  if (c != c) c = INFINITY;
+  uint32_t u = __float_as_uint(c);
+  if (u == 0x80000000u) u = 0u;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+struct TopkSmem {
+  unsigned long long keys[kMaxElites];
+  uint32_t hist[256];
+  uint32_t wave_sum[kTopkThreads / 64];
+  unsigned long long prefix;
+  uint32_t rank;
+  uint32_t count;
+  float red[kTopkThreads / 64];
+};
+
+template <int BS>
+__device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
+  const int tid = threadIdx.x;
+  const int B = P.B, E = P.E;
+  unsigned long long prefix = 0ull, mask = 0ull;
+  uint32_t rank = static_cast<uint32_t>(E);   // 1-based rank of the wanted key among the candidates
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    for (int i = tid; i < 256; i += BS) sm.hist[i] = 0u;
+    __syncthreads();
+    for (int b = tid; b < B; b += BS) {
+      const unsigned long long key = (static_cast<unsigned long long>(cost_order(P.cost[b])) << 32) |
+                                     static_cast<uint32_t>(b);
+      if ((key & mask) == prefix) atomicAdd(&sm.hist[(key >> shift) & 0xFFull], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // lane l owns bins 4l..4l+3; inclusive wave scan of the lane totals
+      const uint32_t h0 = sm.hist[4 * tid], h1 = sm.hist[4 * tid + 1], h2 = sm.hist[4 * tid + 2],
+                     h3 = sm.hist[4 * tid + 3];
+      const uint32_t tot = h0 + h1 + h2 + h3;
+      uint32_t inc = tot;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (tid >= o) inc += v;
+      }
+      const uint32_t exc = inc - tot;
+      if (exc < rank && rank <= inc) {
+        uint32_t rr = rank - exc, d = 4u * tid;
+        if (rr > h0) { rr -= h0; d += 1; if (rr > h1) { rr -= h1; d += 1; if (rr > h2) { rr -= h2; d += 1; } } }
+        sm.prefix = prefix | (static_cast<unsigned long long>(d) << shift);
+        sm.rank = rr;
+      }
+    }
+    __syncthreads();
+    prefix = sm.prefix;
+    rank = sm.rank;
+    mask |= 0xFFull << shift;
+    __syncthreads();
+  }
+  // prefix is now the E-th smallest key: gather the E keys <= prefix
+  int M = 1;
+  while (M < E) M <<= 1;
+  if (tid == 0) sm.count = 0u;
+  for (int i = tid; i < M; i += BS) sm.keys[i] = ~0ull;
+  __syncthreads();
+  for (int b = tid; b < B; b += BS) {
+    const unsigned long long key = (static_cast<unsigned long long>(cost_order(P.cost[b])) << 32) |
+                                   static_cast<uint32_t>(b);
+    if (key <= prefix) {
+      const uint32_t slot = atomicAdd(&sm.count, 1u);
+      if (slot < static_cast<uint32_t>(M)) sm.keys[slot] = key;
+    }
+  }
+  __syncthreads();
+  // bitonic sort ascending of M keys
+  for (int size = 2; size <= M; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < M; i += BS) {
+        const int jx = i ^ stride;
+        if (jx > i) {
+          const bool up = ((i & size) == 0);
+          const unsigned long long a = sm.keys[i], c = sm.keys[jx];
+          if ((a > c) == up) { sm.keys[i] = c; sm.keys[jx] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // elites, costs and softmax weights w_e = exp(-(s_e - s_0)/lambda) / sum
+  const uint32_t i0 = static_cast<uint32_t>(sm.keys[0]);
+  const float s0 = P.cost[i0 < static_cast<uint32_t>(B) ? i0 : 0u];
+  const bool uniform = !(P.lam < INFINITY) || !(s0 < INFINITY);
+  float part = 0.0f;
+  for (int e = tid; e < E; e += BS) {
+    uint32_t uidx = static_cast<uint32_t>(sm.keys[e]);
+    if (uidx >= static_cast<uint32_t>(B)) { uidx = 0u; atomicOr(&P.ctrl[2], 2u); }   // never expected
+    const int idx = static_cast<int>(uidx);
+    const float ce = P.cost[idx];
+    P.eidx[e] = idx;
+    P.ecost[e] = ce;
+    const float z = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
+    P.w[e] = z;
+    part += z;
+  }
+  // deterministic block sum: fixed wave shuffles, then wave totals in order
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((tid & 63) == 0) sm.red[tid >> 6] = part;
+  __syncthreads();
+  float tot = 0.0f;
+  for (int wv = 0; wv < BS / 64; ++wv) tot += sm.red[wv];
+  const float inv = 1.0f / tot;
+  __syncthreads();
+  for (int e = tid; e < E; e += BS) P.w[e] *= inv;
+  if (tid == 0 && !(s0 < INFINITY)) atomicOr(&P.ctrl[2], 1u);
+}
+
+// ------------------------------------------------------------------ refit
+// One wave per output (t, j): lanes stride over the elites, fixed-order
+// butterfly reduction, then the sigma floor and exponential smoothing.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
+  const int lane = threadIdx.x & 63;
+  const size_t ld = static_cast<size_t>(P.ldU);
+  const float* row = P.U + static_cast<size_t>(o) * ld;
+  float m = 0.0f;
+  for (int e = lane; e < P.E; e += 64) m = fmaf(P.w[e], row[P.eidx[e]], m);
+  m = wave_sum(m);
+  float v = 0.0f;
+  for (int e = lane; e < P.E; e += 64) {
+    const float dv = row[P.eidx[e]] - m;
+    v = fmaf(P.w[e], dv * dv, v);
+  }
+  v = wave_sum(v);
+  if (lane == 0) {
+    const float sd = fmaxf(sqrtf(v), P.sigma_min);
+    const float mu_old = P.mu[o], sg_old = P.sigma[o];
+    P.mu[o] = fmaf(P.alpha, mu_old - m, m);
+    P.sigma[o] = fmaf(P.alpha, sg_old - sd, sd);
+    if (o < P.n) P.action[o] = row[P.eidx[0]];   // first control of the best candidate
+  }
+}
+
+// ------------------------------------------------------------------ prologue
+// Replan prologue.  set_ctrl runs outside any captured graph (its arguments
+// change every replan): it records the replan index and the shift and stages
+// x0.  shift_block runs inside the graph and shifts the warm start by the
+// recorded amount; a single workgroup stages through the tmp buffer so the
+// in-place shift has no read-after-write hazard.
+__device__ __forceinline__ void set_ctrl_block(const PlanDesc& P, uint32_t r, int shift, const float* x0_src) {
+  const int tid = threadIdx.x;
+  if (tid == 0) { P.ctrl[0] = r; P.ctrl[1] = static_cast<uint32_t>(shift > 0 ? shift : 0); P.ctrl[2] = 0u; }
+  if (x0_src != nullptr)
+    for (int i = tid; i < P.d; i += blockDim.x) P.x0[i] = x0_src[i];
+}
+
+template <int BS>
+__device__ __forceinline__ void shift_block(const PlanDesc& P, int shift) {
+  const int tid = threadIdx.x;
+  if (shift <= 0) return;
+  const int Tn = P.T * P.n;
+  const int s = shift < P.T ? shift : P.T;
+  float* tmu = P.tmp;
+  float* tsg = P.tmp + Tn;
+  for (int e = tid; e < Tn; e += BS) {
+    const int t = e / P.n, j = e - t * P.n;
+    if (t < P.T - s) {
+      tmu[e] = P.mu[e + s * P.n];
+      tsg[e] = P.sigma[e + s * P.n];
+    } else {
+      tmu[e] = P.mu[(P.T - 1) * P.n + j];
+      tsg[e] = P.sigma_init;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < Tn; e += BS) {
+    P.mu[e] = tmu[e];
+    P.sigma[e] = tsg[e];
+  }
+}
+
+}  // namespace mtp

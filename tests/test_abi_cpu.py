@@ -1,0 +1,162 @@
+"""The C-ABI library loads, exports every symbol its headers declare, and rejects
+bad configurations before touching a device (CPU only)."""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import mtp_workloads as W
+import paper_2505_01059_amd as mtp
+from paper_2505_01059_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(mtp_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    lib = mtp.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    lib = mtp.load()
+    for s in range(7):
+        assert lib.mtp_status_str(s)
+    assert lib.mtp_status_str(99) == b"unknown status"
+
+
+def test_supported_chain_lengths_cover_workloads():
+    lib = mtp.load()
+    buf = (ctypes.c_int32 * 32)()
+    n = lib.mtp_supported_chain_links(buf, 32)
+    links = set(buf[:n])
+    assert {7, 12, 24} <= links
+
+
+@pytest.mark.parametrize("cfg", [W.c0(), W.c1(), W.point_mass_config(interp=W.AKIMA)])
+def test_valid_configs_and_workspace(cfg):
+    st, why = N.validate(cfg)
+    assert st == 0, why
+    nb = N.workspace_bytes(cfg)
+    B, T, n = cfg.n_samples, cfg.horizon, cfg.ctrl_dim
+    assert nb >= B * T * n * 4 and nb % 256 == 0
+
+
+def test_c4_config_valid():
+    st, why = N.validate(W.c4())
+    assert st == 0, why
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (dict(n_gauss=0), 1),
+    (dict(n_elites=0), 1),
+    (dict(n_elites=10 ** 6), 1),
+    (dict(horizon=0), 1),
+    (dict(n_layers=3), 1),                  # cubic B-spline needs 4 layers
+    (dict(n_layers=17), 1),
+    (dict(n_width=257), 1),
+    (dict(bspline_degree=6), 1),
+    (dict(temperature=np.float32(0)), 1),
+    (dict(temperature=np.float32(-1)), 1),
+    (dict(smoothing=np.float32(1.0)), 1),
+    (dict(sigma_min=np.float32(-0.1)), 1),
+    (dict(u_min=np.float32(1.0)), 1),
+    (dict(dt=np.float32(0)), 1),
+    (dict(n_iters=0), 1),
+    (dict(state_dim=5), 1),
+])
+def test_invalid_configs_rejected(mutate, code):
+    cfg = W.c0().replace(**mutate)
+    st, why = N.validate(cfg)
+    assert st == code and why
+    assert N.workspace_bytes(cfg) == 0
+
+
+def test_inf_temperature_is_valid():
+    st, why = N.validate(W.c0().replace(temperature=np.float32(np.inf)))
+    assert st == 0, why
+
+
+def test_unsupported_chain_length():
+    cfg = W.chain_config(n_links=5, n_tensor=64, n_gauss=64, n_elites=8)
+    st, why = N.validate(cfg)
+    assert st == 2 and "instantiated" in why
+
+
+def test_bad_task_params():
+    cfg = W.c1()
+    c, keep = N.config_struct(cfg)
+    c.n_task_params = 3
+    lib = mtp.load()
+    buf = ctypes.create_string_buffer(128)
+    assert lib.mtp_validate_config(ctypes.byref(c), buf, 128) == 1
+    c2, keep2 = N.config_struct(W.c4())
+    c2.sample_params = None
+    assert lib.mtp_validate_config(ctypes.byref(c2), buf, 128) == 1
+
+
+def test_create_rejects_bad_workspace_without_device():
+    lib = mtp.load()
+    c, keep = N.config_struct(W.c0())
+    h = ctypes.c_void_p()
+    nb = lib.mtp_workspace_bytes(ctypes.byref(c))
+    assert lib.mtp_plan_create(ctypes.byref(c), None, nb, None, ctypes.byref(h)) == 3
+    assert lib.mtp_plan_create(ctypes.byref(c), ctypes.c_void_p(256), nb - 1, None, ctypes.byref(h)) == 3
+    assert lib.mtp_plan_create(ctypes.byref(c), ctypes.c_void_p(260), nb, None, ctypes.byref(h)) == 3
+    assert not h.value
+
+
+def test_null_handles():
+    lib = mtp.load()
+    assert lib.mtp_replan(None, None, 0) == 1
+    assert lib.mtp_plan_destroy(None) == 1
+    assert lib.mtp_get_buffers(None, None) == 1
+
+
+# ---------------------------------------------------------------- host tables
+
+@pytest.mark.parametrize("L,p,T", [(4, 3, 50), (12, 3, 256), (6, 2, 37), (9, 5, 64), (5, 1, 20)])
+def test_bspline_table_matches_oracle_basis(L, p, T):
+    """The engine's per-span weights equal the oracle's Cox-de Boor matrix (Def. 2)."""
+    from oracle import interp as OI
+    cfg = W.point_mass_config(n_layers=L, bspline_degree=p, horizon=T)
+    basis, span = N.interp_table(cfg)
+    Bm = OI.bspline_matrix(L, p, T)
+    for t in range(T):
+        full = np.zeros(L)
+        full[span[t]:span[t] + p + 1] = basis[t, :p + 1]
+        np.testing.assert_allclose(full, Bm[:, t], atol=1e-7)
+
+
+@pytest.mark.parametrize("L,T", [(8, 128), (4, 50), (12, 37), (2, 10), (3, 7)])
+def test_akima_table_reproduces_oracle_akima(L, T):
+    """Hermite weights applied to unit-spacing Akima slopes give the oracle's Eq. 5-7 curve."""
+    from oracle import interp as OI
+    cfg = W.point_mass_config(interp=W.AKIMA, n_layers=L, horizon=T)
+    basis, span = N.interp_table(cfg)
+    rng = np.random.default_rng(L)
+    z = rng.uniform(-1, 1, size=(5, L, 1))
+    t = OI.akima_knots(L)
+    hs = OI.akima_slopes(z, t) * (1.0 / L)                   # slope times knot spacing
+    U = OI.akima_interp(z, T)
+    for j in range(T):
+        i = span[j]
+        h = basis[j, :4].astype(np.float64)
+        v = h[0] * z[:, i] + h[1] * hs[:, i] + h[2] * z[:, i + 1] + h[3] * hs[:, i + 1]
+        np.testing.assert_allclose(v, U[:, j], atol=2e-6)

@@ -1,0 +1,247 @@
+"""Stage-wise and per-iteration parity of the HIP path against the FP64 oracle.
+
+Every stage runs through the C ABI (mtp_run_stage / mtp_replan) on inputs the
+oracle also sees; see gpu_helpers for the rules.  Sizes span several tiles
+and leave ragged tails (B not a multiple of 64 or 256, T not a multiple of 4).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import mtp_workloads as W
+from oracle import planner as OP, sampling as OS
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def configs():
+    return {
+        "pm_bspline": W.point_mass_config(name="pm_bspline", n_tensor=300, n_gauss=45, horizon=37,
+                                          n_layers=5, n_width=7, n_elites=20, n_iters=2),
+        "pm_akima": W.point_mass_config(name="pm_akima", interp=W.AKIMA, n_tensor=260, n_gauss=33,
+                                        horizon=50, n_layers=6, n_width=9, n_elites=16, n_iters=2),
+        "pm_c0": W.c0(),
+        "chain7_akima": W.chain_config(name="chain7_akima", n_tensor=700, n_gauss=101, horizon=66,
+                                       n_elites=40, n_iters=2),
+        "chain7_bspline": W.chain_config(name="chain7_bspline", interp=W.BSPLINE, n_tensor=333,
+                                         n_gauss=64, horizon=41, n_layers=6, n_width=20,
+                                         n_elites=24, n_iters=2),
+        "chain2": W.chain_config(name="chain2", n_links=2, n_tensor=200, n_gauss=57, horizon=30,
+                                 n_layers=4, n_width=5, n_elites=10, n_iters=2),
+        "chain12": W.chain_config(name="chain12", n_links=12, interp=W.BSPLINE, n_tensor=250,
+                                  n_gauss=70, horizon=32, n_layers=9, n_width=40, n_elites=30, n_iters=2),
+        "chain24": W.chain_config(name="chain24", n_links=24, interp=W.AKIMA, n_tensor=130,
+                                  n_gauss=70, horizon=24, n_layers=12, n_width=64, n_elites=16, n_iters=2),
+        "contact24": W.chain_contact_config(name="contact24", n_tensor=200, n_gauss=56, horizon=48,
+                                            n_elites=16, n_iters=2),
+    }
+
+
+CONFIGS = configs()
+NAMES = list(CONFIGS)
+
+
+def random_state(cfg, seed=0):
+    rng = np.random.default_rng(seed)
+    T, n = cfg.horizon, cfg.ctrl_dim
+    um = float(cfg.u_max)
+    mu = rng.uniform(-0.5 * um, 0.5 * um, size=(T, n)).astype(np.float32)
+    sg = rng.uniform(0.1 * um, 0.6 * um, size=(T, n)).astype(np.float32)
+    return mu, sg
+
+
+@pytest.fixture(scope="module")
+def torch_mod(lib):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def make_plan(cfg, **kw):
+    import paper_2505_01059_amd as mtp
+    return mtp.Plan(cfg, device="cuda:0", **kw)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_candidates_stage(name, torch_mod):
+    cfg = CONFIGS[name]
+    _log(f"[candidates] {name} B={cfg.n_samples} T={cfg.horizon} n={cfg.ctrl_dim}")
+    plan = make_plan(cfg)
+    mu, sg = random_state(cfg, 1)
+    plan.set_state(mu, sg, 0)
+    r, k = 5, 3
+    plan.run_stage(0, r, k)
+    torch_mod.cuda.synchronize()
+    b = plan.buffers()
+    Z_ref = OS.waypoints(cfg.seed, r, k, cfg.n_layers, cfg.n_width, cfg.ctrl_dim, cfg.u_min, cfg.u_max)
+    I_ref = OS.path_indices(cfg.seed, r, k, cfg.n_tensor, cfg.n_layers, cfg.n_width)
+    assert np.array_equal(b["Z"].cpu().numpy(), Z_ref), "graph waypoints not bit-exact"
+    assert np.array_equal(b["I"].cpu().numpy().T.astype(np.int64), I_ref), "path indices not bit-exact"
+    _, _, U_ref = OP.candidates(cfg, mu.astype(np.float64), sg.astype(np.float64), r, k)
+    U = H.to_oracle_U(b["U"])
+    ok = H.u_close(U, U_ref, cfg.u_max)
+    ill = H.akima_ill_conditioned(cfg, I_ref, Z_ref)
+    rows_bad = ~np.all(ok, axis=(1, 2))
+    G1 = cfg.n_gauss - 1
+    rows_bad[G1:G1 + cfg.n_tensor] &= ~ill
+    assert not rows_bad.any(), f"{rows_bad.sum()} candidates differ, max err {np.max(np.abs(U - U_ref))}"
+    _log(f"  max |dU| = {np.max(np.abs(U - U_ref)):.3e}; ill-conditioned Akima paths {ill.sum()}")
+    plan.close()
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_rollout_stage(name, torch_mod):
+    cfg = CONFIGS[name]
+    _log(f"[rollout] {name}")
+    nd = min(8, cfg.n_samples)
+    plan = make_plan(cfg, n_debug_states=nd)
+    mu, sg = random_state(cfg, 2)
+    _, _, U_ref = OP.candidates(cfg, mu.astype(np.float64), sg.astype(np.float64), 1, 0)
+    U32 = U_ref.astype(np.float32).astype(np.float64)
+    b = plan.buffers()
+    H.write_U(b, U32)
+    x0 = W.initial_state(cfg, seed=3)
+    plan.set_x0(x0)
+    plan.run_stage(1, 1, 0)
+    torch_mod.cuda.synchronize()
+    s = b["cost"].cpu().numpy()
+    s_ref, X_ref = OP.rollout(cfg, x0, U32, keep_states=True)
+    flagged = H.switching_flags(cfg, x0, U32)
+    bad = H.cost_check(s, s_ref, flagged)
+    rel = np.abs(s - s_ref) / np.maximum(np.abs(s_ref), 1e-12)
+    _log(f"  cost rel err max {rel[~flagged].max():.3e} median {np.median(rel):.3e}; flagged {flagged.sum()}")
+    assert not bad.any(), f"{bad.sum()} costs out of tolerance: {np.flatnonzero(bad)[:10]}"
+    X = b["X"].cpu().numpy().transpose(2, 0, 1).astype(np.float64)        # (nd, T, d)
+    Xr = X_ref[:nd]
+    okx = np.abs(X - Xr) <= 1e-4 * np.maximum(1.0, np.abs(Xr))
+    okx |= flagged[:nd, None, None]
+    assert okx.all(), f"state trajectory mismatch, max {np.max(np.abs(X - Xr))}"
+    plan.close()
+
+
+def test_topk_stage_exact_with_ties(torch_mod):
+    import torch
+    cfg = W.point_mass_config(n_tensor=5000, n_gauss=1000, n_elites=300)
+    plan = make_plan(cfg)
+    b = plan.buffers()
+    rng = np.random.default_rng(4)
+    s = np.round(rng.normal(size=cfg.n_samples), 2).astype(np.float32)      # many exact ties
+    s[rng.choice(cfg.n_samples, 40, replace=False)] = np.nan
+    s[rng.choice(cfg.n_samples, 40, replace=False)] = np.inf
+    s[rng.choice(cfg.n_samples, 10, replace=False)] = -0.0
+    s[rng.choice(cfg.n_samples, 10, replace=False)] = 0.0
+    b["cost"].copy_(torch.from_numpy(s).cuda())
+    plan.run_stage(2, 0, 0)
+    torch_mod.cuda.synchronize()
+    iE = b["elite_idx"].cpu().numpy()
+    want = OP.top_elites(np.where(s == 0, 0.0, s).astype(np.float64), cfg.n_elites)
+    assert np.array_equal(iE, want)
+    w = b["weights"].cpu().numpy()
+    w_ref = OP.softmax_weights(s[want].astype(np.float64), float(cfg.temperature))
+    np.testing.assert_allclose(w, w_ref, rtol=1e-5, atol=1e-7)
+    plan.close()
+
+
+@pytest.mark.parametrize("E", [1, 7, 64, 511, 4096])
+def test_topk_sizes(E, torch_mod):
+    import torch
+    B = max(E, 5000) + 77
+    cfg = W.point_mass_config(n_tensor=B - 40, n_gauss=40, n_elites=E)
+    plan = make_plan(cfg)
+    b = plan.buffers()
+    s = np.random.default_rng(E).uniform(0, 10, size=B).astype(np.float32)
+    b["cost"].copy_(torch.from_numpy(s).cuda())
+    plan.run_stage(2, 0, 0)
+    torch_mod.cuda.synchronize()
+    assert np.array_equal(b["elite_idx"].cpu().numpy(), OP.top_elites(s.astype(np.float64), E))
+    plan.close()
+
+
+def test_all_inf_costs_flag_uniform_weights(torch_mod):
+    import torch
+    cfg = W.point_mass_config(n_tensor=100, n_gauss=28, n_elites=8)
+    plan = make_plan(cfg)
+    b = plan.buffers()
+    b["cost"].fill_(float("inf"))
+    plan.run_stage(2, 0, 0)
+    torch_mod.cuda.synchronize()
+    assert list(b["elite_idx"].cpu().numpy()) == list(range(8))
+    np.testing.assert_allclose(b["weights"].cpu().numpy(), 1 / 8, rtol=1e-6)
+    assert plan.flags() & 1
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["pm_bspline", "chain7_akima", "chain24"])
+@pytest.mark.parametrize("lam,alpha", [(0.1, 0.0), (10.0, 0.3), (np.inf, 0.0)])
+def test_update_stage(name, lam, alpha, torch_mod):
+    import torch
+    cfg = CONFIGS[name].replace(temperature=np.float32(lam), smoothing=np.float32(alpha))
+    plan = make_plan(cfg)
+    mu, sg = random_state(cfg, 5)
+    plan.set_state(mu, sg, 0)
+    b = plan.buffers()
+    rng = np.random.default_rng(6)
+    U = rng.uniform(float(cfg.u_min), float(cfg.u_max), size=(cfg.n_samples, cfg.horizon, cfg.ctrl_dim))
+    U = U.astype(np.float32).astype(np.float64)
+    H.write_U(b, U)
+    s = rng.uniform(0, 1, size=cfg.n_samples).astype(np.float32)
+    b["cost"].copy_(torch.from_numpy(s).cuda())
+    plan.run_stage(2, 0, 0)
+    plan.run_stage(3, 0, 0)
+    torch_mod.cuda.synchronize()
+    iE = b["elite_idx"].cpu().numpy()
+    mu2, sg2, _ = OP.refit(U, s.astype(np.float64), iE, mu.astype(np.float64), sg.astype(np.float64), cfg)
+    assert H.refit_close(b["mu"].cpu().numpy(), mu2, cfg).all()
+    assert H.refit_close(b["sigma"].cpu().numpy(), sg2, cfg).all()
+    np.testing.assert_array_equal(b["action"].cpu().numpy(), U[iE[0], 0].astype(np.float32))
+    plan.close()
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_teacher_forced_replan(name, torch_mod):
+    """Whole replan on the GPU; after every iteration the oracle re-runs that
+    iteration from the GPU's own input mean/std and every stage is compared."""
+    cfg = CONFIGS[name]
+    _log(f"[replan] {name}")
+    plan = make_plan(cfg)
+    x0 = W.initial_state(cfg, seed=7)
+    mu, sg = random_state(cfg, 8)
+    r = 11
+    margin_events = 0
+    for k in range(cfg.n_iters):
+        plan.set_state(mu, sg, r)
+        plan.set_x0(x0)
+        plan.run_stage(4, r, k)
+        torch_mod.cuda.synchronize()
+        b = plan.buffers()
+        ref = OP.iterate(cfg, x0, mu.astype(np.float64), sg.astype(np.float64), r, k)
+        assert np.array_equal(b["I"].cpu().numpy().T.astype(np.int64), ref["I"])
+        U = H.to_oracle_U(b["U"])
+        s = b["cost"].cpu().numpy()
+        iE = b["elite_idx"].cpu().numpy()
+        flagged = H.switching_flags(cfg, x0, ref["U"])
+        ill = H.akima_ill_conditioned(cfg, ref["I"], ref["Z"])
+        G1 = cfg.n_gauss - 1
+        flagged[G1:G1 + cfg.n_tensor] |= ill
+        assert not H.cost_check(s, ref["s"], flagged).any()
+        # the oracle's selection on the GPU's own costs is bit-exact
+        assert np.array_equal(iE, OP.top_elites(s.astype(np.float64), cfg.n_elites))
+        if H.elite_margin_safe(ref["s"], cfg.n_elites) and not flagged.any():
+            assert set(iE) == set(ref["iE"])
+        else:
+            margin_events += 1
+        mu2, sg2, _ = OP.refit(ref["U"], s.astype(np.float64), iE, mu.astype(np.float64),
+                               sg.astype(np.float64), cfg)
+        assert H.refit_close(b["mu"].cpu().numpy(), mu2, cfg).all()
+        assert H.refit_close(b["sigma"].cpu().numpy(), sg2, cfg).all()
+        mu = b["mu"].cpu().numpy().copy()
+        sg = b["sigma"].cpu().numpy().copy()
+    _log(f"  margin events {margin_events}")
+    plan.close()
