@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Throughput of one MTP replan on one MI355X.
+
+A step is one replan: n_iters CEM iterations of candidate generation (Philox
+graph + paths + spline, Gaussian samples), fused rollout + cost, top-E and
+softmax refit, replayed from a captured hipGraph with every input already in
+HBM.  The default workload is the 7-link pendulum chain with Akima
+interpolation (9216 candidates = 8192 tensor + 1024 Gaussian, horizon 128,
+8x32 graph, 128 elites, 8 iterations).
+
+Prints one JSON line:
+  value        rollout steps/s = candidates x horizon x iterations per replan,
+               times replans, over the wall time of the timed replans;
+  roofline     the rollout kernel's algorithmic FP32 flops per launch over its
+               mean launch time (HIP events around every rollout launch on the
+               plan's stream, in a second timed pass launching kernels one by one);
+  cpu_baseline the FP64 oracle timed on one CEM iteration of the same workload.
+"""
+import argparse
+import json
+import os
+import platform
+import statistics
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rollout steps/sec (samples x horizon) + replans/sec; p50/p99 replan latency"
+
+
+def workloads():
+    import mtp_workloads as W
+    return {
+        "chain7_akima": W.c1,
+        "point_mass_bspline": W.c0,
+        "chain24_contact_bspline": W.c4,
+    }
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per rollout launch from the committed PMC summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", f"rollout_{workload}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        return rec.get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, x0):
+    """Oracle (FP64 NumPy, as written) on one CEM iteration of the same workload, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import planner as OP
+    mu, sg = OP.initial_distribution(cfg)
+    sub = cfg
+    if cfg.n_samples > 20000:
+        # bounded sample: the first 1024 candidates of the batch, same horizon and model
+        sub = cfg.replace(n_tensor=1024 - min(cfg.n_gauss, 128), n_gauss=min(cfg.n_gauss, 128),
+                          n_elites=min(cfg.n_elites, 64))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        OP.iterate(sub, x0, mu, sg, 0, 0)
+        dt = time.perf_counter() - t0
+    steps = sub.n_samples * sub.horizon
+    return {
+        "value": steps / dt, "unit": "rollout steps/s", "cores": 1, "kind": "oracle",
+        "sample": f"one CEM iteration, {sub.n_samples} candidates x {sub.horizon} steps "
+                  f"(FP64 NumPy oracle, 1 thread, {dt:.1f} s; host {cpu_model()}, nproc {os.cpu_count()})",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="chain7_akima", choices=sorted(workloads()))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(instances shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import mtp_workloads as W
+    import paper_2505_01059_amd as mtp
+    from paper_2505_01059_amd import roofline as RF
+
+    cfg = workloads()[args.workload]()
+    x0 = W.initial_state(cfg)
+    dev = torch.device("cuda:0")
+    plan = mtp.Plan(cfg, device=dev)
+    x0_dev = torch.tensor(x0, device=dev)
+    B, T, K = cfg.n_samples, cfg.horizon, cfg.n_iters
+    print(f"[bench] workload {args.workload}: B={B} T={T} n={cfg.ctrl_dim} K={K}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        plan.replan(x0_dev, shift=1)
+    torch.cuda.synchronize()
+
+    # timed region: back-to-back replans from the captured graph
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.replan(x0_dev, shift=1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = B * T * K * args.steps / wall
+    print(f"[bench] {ms_per_step:.3f} ms/replan", file=sys.stderr, flush=True)
+
+    # latency: submit a replan and wait for its action, per replan
+    lat = []
+    for _ in range(max(args.steps, 30)):
+        t = time.perf_counter()
+        plan.replan(x0_dev, shift=1)
+        plan.action()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat.sort()
+    p50 = statistics.median(lat)
+    p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
+
+    # kernel timing pass: HIP events around every stage launch on the plan's stream
+    plan.set_stage_timing(True)
+    for _ in range(args.steps):
+        plan.replan(x0_dev, shift=1)
+    torch.cuda.synchronize()
+    st = plan.stage_times()
+    plan.set_stage_timing(False)
+    roll_ms, roll_n = st["rollout"]
+    roll_avg_ms = roll_ms / max(roll_n, 1)
+    n_obs = len(cfg.task.obstacles) if cfg.dynamics == 0 else 0
+    flops_step = RF.flops_per_sample_step(cfg.dynamics, cfg.n_links, n_obs)
+    achieved = B * T * flops_step / (roll_avg_ms * 1e-3) / 1e12
+    traffic = traffic_from_profiles(args.workload)
+    roofline = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": RF.PEAK_FP32_VECTOR_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / RF.PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+        "kernel": f"rollout ({'point mass' if cfg.dynamics == 0 else f'{cfg.n_links}-link chain'})",
+        "flops_per_sample_step": flops_step, "launch_ms": round(roll_avg_ms, 4),
+        "frac_of_unpacked_fp32": round(achieved / RF.PEAK_FP32_UNPACKED_TFLOPS, 4),
+    }
+    stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items()}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "rollout steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "candidates": B, "tensor": cfg.n_tensor,
+                   "gaussian": cfg.n_gauss, "horizon": T, "ctrl_dim": cfg.ctrl_dim,
+                   "layers": cfg.n_layers, "width": cfg.n_width, "elites": cfg.n_elites,
+                   "iters": K, "interp": "akima" if cfg.interp else "bspline"},
+        "replans_per_s": args.steps / wall,
+        "latency_ms_p50": round(p50, 4), "latency_ms_p99": round(p99, 4),
+        "stage_ms_per_launch": stage_ms,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, x0)
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -181,6 +181,14 @@ mtp_status mtp_set_x0(mtp_plan* p, const float* d_x0);
 /* Replay replans through a captured hipGraph (1, default) or launch kernels one by one (0). */
 mtp_status mtp_set_graph_mode(mtp_plan* p, int32_t use_graph);
 
+/* Per-stage kernel timing with hipEvents recorded on the plan's stream around every
+ * stage launch.  While enabled, replans launch their kernels one by one (no graph).
+ * mtp_get_stage_times waits for the recorded events and returns, per stage
+ * (candidates, rollout, top-E, refit), the summed kernel milliseconds and the
+ * number of launches since timing was enabled. */
+mtp_status mtp_set_stage_timing(mtp_plan* p, int32_t enable);
+mtp_status mtp_get_stage_times(mtp_plan* p, double* h_ms4, uint64_t* h_count4);
+
 mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
 /* Status flags of the last replan: bit 0 = every elite cost was +inf (weights fell back to uniform). */
 mtp_status mtp_get_flags(mtp_plan* p, uint32_t* h_flags);

@@ -82,6 +82,8 @@ def load():
         "mtp_last_error": (c_char_p, [P]),
         "mtp_supported_chain_links": (c_int32, [POINTER(c_int32), c_int32]),
         "mtp_interp_table": (c_int32, [P, P, P]),
+        "mtp_set_stage_timing": (c_int32, [P, c_int32]),
+        "mtp_get_stage_times": (c_int32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -269,6 +271,18 @@ class Plan:
 
     def set_graph_mode(self, on):
         _check(self.lib, self.lib.mtp_set_graph_mode(self.handle, 1 if on else 0), self.handle)
+
+    def set_stage_timing(self, on):
+        _check(self.lib, self.lib.mtp_set_stage_timing(self.handle, 1 if on else 0), self.handle)
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} for candidates, rollout, topk, update."""
+        ms = np.zeros(4, np.float64)
+        cnt = np.zeros(4, np.uint64)
+        _check(self.lib, self.lib.mtp_get_stage_times(self.handle, ms.ctypes.data_as(c_void_p),
+                                                      cnt.ctypes.data_as(c_void_p)), self.handle)
+        names = ("candidates", "rollout", "topk", "update")
+        return {nm: (float(ms[i]), int(cnt[i])) for i, nm in enumerate(names)}
 
     def flags(self):
         f = c_uint32()

@@ -204,6 +204,12 @@ struct mtp_plan {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   bool use_graph = true;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double stage_ms[4] = {0, 0, 0, 0};
+  uint64_t stage_count[4] = {0, 0, 0, 0};
   uint32_t next_r = 0;
   bool sticky = false;
   std::string err;
@@ -298,6 +304,52 @@ hipError_t mtp::enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hi
   return hipSuccess;
 }
 
+static hipError_t take_event(mtp_plan* p, hipEvent_t* ev) {
+  if (!p->ev_free.empty()) {
+    *ev = p->ev_free.back();
+    p->ev_free.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(ev);
+}
+
+static hipError_t drain_events(mtp_plan* p) {
+  for (auto& q : p->pending) {
+    hipError_t e = hipEventSynchronize(q.b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, q.a, q.b);
+    if (e != hipSuccess) return e;
+    p->stage_ms[q.stage] += ms;
+    p->stage_count[q.stage] += 1;
+    p->ev_free.push_back(q.a);
+    p->ev_free.push_back(q.b);
+  }
+  p->pending.clear();
+  return hipSuccess;
+}
+
+// Launch iterations [k0, k1) one kernel at a time, with event pairs around each
+// stage when timing is on.
+static hipError_t enqueue_iterations_plan(mtp_plan* p, int k0, int k1) {
+  if (!p->timing) return enqueue_iterations(p->P, k0, k1, p->stream);
+  for (int k = k0; k < k1; ++k)
+    for (int stage = 0; stage < 4; ++stage) {
+      hipEvent_t a, b;
+      hipError_t e = take_event(p, &a);
+      if (e == hipSuccess) e = take_event(p, &b);
+      if (e == hipSuccess) e = hipEventRecord(a, p->stream);
+      if (e == hipSuccess) e = launch_stage(p->P, stage, k, p->stream);
+      if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+      if (e != hipSuccess) return e;
+      p->pending.push_back({stage, a, b});
+      if (p->pending.size() >= 4096) {
+        e = drain_events(p);
+        if (e != hipSuccess) return e;
+      }
+    }
+  return hipSuccess;
+}
+
 extern "C" {
 
 size_t mtp_workspace_bytes(const mtp_config* cfg) {
@@ -368,16 +420,17 @@ mtp_status mtp_replan_at(mtp_plan* p, const float* d_x0, int32_t shift_steps, ui
   if (p->sticky) return MTP_ERR_DEVICE;
   if (d_x0 == nullptr) return set_err(p, MTP_ERR_INVALID_ARG, "d_x0 is NULL");
   if (shift_steps < 0) return set_err(p, MTP_ERR_INVALID_ARG, "shift_steps must be >= 0");
-  if (p->use_graph) {
+  const bool graph = p->use_graph && !p->timing;
+  if (graph) {
     const mtp_status s = ensure_graph(p);
     if (s != MTP_OK) return s;
   }
   HIPCHK(p, launch_set_ctrl(p->P, replan_idx, shift_steps, d_x0, p->stream), "set ctrl");
-  if (p->use_graph) {
+  if (graph) {
     HIPCHK(p, hipGraphLaunch(p->exec, p->stream), "graph launch");
   } else {
     HIPCHK(p, launch_shift(p->P, p->stream), "shift");
-    HIPCHK(p, enqueue_iterations(p->P, 0, p->cfg.n_iters, p->stream), "iterations");
+    HIPCHK(p, enqueue_iterations_plan(p, 0, p->cfg.n_iters), "iterations");
   }
   p->next_r = replan_idx + 1;
   return MTP_OK;
@@ -432,7 +485,7 @@ mtp_status mtp_run_stage(mtp_plan* p, int32_t stage, uint32_t replan_idx, int32_
   if (k < 0 || k > 65535) return set_err(p, MTP_ERR_INVALID_ARG, "iteration index out of range");
   HIPCHK(p, launch_set_ctrl(p->P, replan_idx, 0, nullptr, p->stream), "set ctrl");
   if (stage == MTP_STAGE_ALL) {
-    HIPCHK(p, enqueue_iterations(p->P, k, k + 1, p->stream), "iteration");
+    HIPCHK(p, enqueue_iterations_plan(p, k, k + 1), "iteration");
   } else {
     HIPCHK(p, launch_stage(p->P, stage, k, p->stream), "stage");
   }
@@ -442,6 +495,23 @@ mtp_status mtp_run_stage(mtp_plan* p, int32_t stage, uint32_t replan_idx, int32_
 mtp_status mtp_set_graph_mode(mtp_plan* p, int32_t use_graph) {
   if (p == nullptr) return MTP_ERR_INVALID_ARG;
   p->use_graph = use_graph != 0;
+  return MTP_OK;
+}
+
+mtp_status mtp_set_stage_timing(mtp_plan* p, int32_t enable) {
+  if (p == nullptr) return MTP_ERR_INVALID_ARG;
+  if (p->sticky) return MTP_ERR_DEVICE;
+  HIPCHK(p, drain_events(p), "timing drain");
+  p->timing = enable != 0;
+  for (int i = 0; i < 4; ++i) { p->stage_ms[i] = 0.0; p->stage_count[i] = 0; }
+  return MTP_OK;
+}
+
+mtp_status mtp_get_stage_times(mtp_plan* p, double* h_ms4, uint64_t* h_count4) {
+  if (p == nullptr || h_ms4 == nullptr || h_count4 == nullptr) return MTP_ERR_INVALID_ARG;
+  if (p->sticky) return MTP_ERR_DEVICE;
+  HIPCHK(p, drain_events(p), "timing drain");
+  for (int i = 0; i < 4; ++i) { h_ms4[i] = p->stage_ms[i]; h_count4[i] = p->stage_count[i]; }
   return MTP_OK;
 }
 
@@ -464,6 +534,8 @@ mtp_status mtp_get_flags(mtp_plan* p, uint32_t* h_flags) {
 
 mtp_status mtp_plan_destroy(mtp_plan* p) {
   if (p == nullptr) return MTP_ERR_INVALID_ARG;
+  (void)drain_events(p);
+  for (auto ev : p->ev_free) (void)hipEventDestroy(ev);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
