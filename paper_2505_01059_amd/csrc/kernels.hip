@@ -18,8 +18,11 @@ __global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) 
 }
 
 __global__ __launch_bounds__(kRollThreads) void k_rollout_point_mass(PlanDesc P) {
+  __shared__ PointMassSmem sm;
+  stage_obstacles(P, sm);
+  __syncthreads();
   const int b = blockIdx.x * kRollThreads + threadIdx.x;
-  if (b < P.B) rollout_point_mass(P, b);
+  if (b < P.B) rollout_point_mass(P, b, sm);
 }
 
 template <int N, bool CONTACT>

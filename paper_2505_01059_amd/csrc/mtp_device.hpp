@@ -90,6 +90,14 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
 
+// sin and cos of an angle in radians on the hardware transcendental unit: the
+// angle is turned into revolutions, reduced to [0, 1) and fed to v_sin / v_cos.
+__device__ __forceinline__ void hw_sincos(float x, float* s, float* c) {
+  const float rev = __builtin_amdgcn_fractf(x * 0.15915494309189535f);
+  *s = __builtin_amdgcn_sinf(rev);
+  *c = __builtin_amdgcn_cosf(rev);
+}
+
 // ------------------------------------------------------------------ candidates
 // Tile = joint j, candidates [b0, b0 + kCandThreads).  Writes U[t][j][b] for
 // every candidate of the tile: local Gaussian samples (noise stream tag 3),
@@ -224,12 +232,30 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
 
 __device__ __forceinline__ float finite_or_inf(float c) { return (c == c && fabsf(c) <= 3.402823466e38f) ? c : INFINITY; }
 
-__device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b) {
+constexpr int kMaxObstacles = 256;
+struct PointMassSmem {
+  float obs[3 * kMaxObstacles];   // centre x, centre y, squared radius
+};
+
+// The obstacle table is staged in LDS by the calling tile (all lanes read the
+// same entry at once, so every read is a broadcast).
+__device__ __forceinline__ void stage_obstacles(const PlanDesc& P, PointMassSmem& sm) {
+  const float* tk = P.task;
+  const int n_obs = static_cast<int>(tk[5]);
+  for (int i = threadIdx.x; i < n_obs; i += blockDim.x) {
+    const float r = tk[6 + 3 * i + 2];
+    sm.obs[3 * i] = tk[6 + 3 * i];
+    sm.obs[3 * i + 1] = tk[6 + 3 * i + 1];
+    sm.obs[3 * i + 2] = r * r;
+  }
+}
+
+__device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, const PointMassSmem& sm) {
   // task: goal_x, goal_y, goal_w, obstacle_penalty, ctrl_w, n_obs, (cx, cy, r)*
   const float* tk = P.task;
   const float gx = tk[0], gy = tk[1], wg = tk[2], pen = tk[3], wu = tk[4];
   const int n_obs = static_cast<int>(tk[5]);
-  const float* obs = tk + 6;
+  const float* obs = sm.obs;
   const float dt = P.dt;
   float px = P.x0[0], py = P.x0[1], vx = P.x0[2], vy = P.x0[3];
   const size_t ld = static_cast<size_t>(P.ldU);
@@ -247,8 +273,8 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b) {
     const float dx = px - gx, dy = py - gy;
     float c = wg * fmaf(dx, dx, dy * dy);
     for (int o = 0; o < n_obs; ++o) {
-      const float ox = px - obs[3 * o], oy = py - obs[3 * o + 1], rr = obs[3 * o + 2];
-      c += (fmaf(ox, ox, oy * oy) < rr * rr) ? pen : 0.0f;
+      const float ox = px - obs[3 * o], oy = py - obs[3 * o + 1];
+      c += (fmaf(ox, ox, oy * oy) < obs[3 * o + 2]) ? pen : 0.0f;
     }
     c = fmaf(wu, fmaf(ux, ux, uy * uy), c);
     cost += c;
@@ -385,7 +411,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
   for (int k = 0; k < N; ++k) {
     ph[k] = P.x0[k];
     om[k] = P.x0[N + k];
-    sincosf(ph[k], &s[k], &c[k]);
+    hw_sincos(ph[k], &s[k], &c[k]);
   }
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* ub = P.U + b;
@@ -414,7 +440,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     {
       float s2[N], c2[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) sincosf(sph[k], &s2[k], &c2[k]);
+      for (int k = 0; k < N; ++k) hw_sincos(sph[k], &s2[k], &c2[k]);
       chain_accel<N, CONTACT>(s2, c2, som, q, K, a);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
@@ -427,7 +453,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     {
       float s3[N], c3[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) sincosf(sph[k], &s3[k], &c3[k]);
+      for (int k = 0; k < N; ++k) hw_sincos(sph[k], &s3[k], &c3[k]);
       chain_accel<N, CONTACT>(s3, c3, som, q, K, a);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
@@ -440,7 +466,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     {
       float s4[N], c4[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) sincosf(sph[k], &s4[k], &c4[k]);
+      for (int k = 0; k < N; ++k) hw_sincos(sph[k], &s4[k], &c4[k]);
       chain_accel<N, CONTACT>(s4, c4, som, q, K, a);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
@@ -453,7 +479,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     float ex = 0.0f, ey = 0.0f, uu = 0.0f;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      sincosf(ph[k], &s[k], &c[k]);
+      hw_sincos(ph[k], &s[k], &c[k]);
       ex = fmaf(K.l[k], s[k], ex);
       ey = fmaf(-K.l[k], c[k], ey);
       uu = fmaf(u[k], u[k], uu);

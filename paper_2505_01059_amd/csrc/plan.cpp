@@ -77,9 +77,9 @@ bool validate_config(const mtp_config* c, std::string* why, mtp_status* code) {
   if (c->dynamics == MTP_DYN_POINT_MASS) {
     if (c->n_task_params < 6) return fail(MTP_ERR_INVALID_ARG, "point mass task needs >= 6 parameters");
     const float nobs = c->task_params[5];
-    if (!(nobs >= 0.0f) || nobs != std::floor(nobs) || nobs > 4096.0f ||
+    if (!(nobs >= 0.0f) || nobs != std::floor(nobs) || nobs > static_cast<float>(kMaxObstacles) ||
         c->n_task_params != 6 + 3 * static_cast<int>(nobs))
-      return fail(MTP_ERR_INVALID_ARG, "point mass task: n_task_params must be 6 + 3 n_obs");
+      return fail(MTP_ERR_INVALID_ARG, "point mass task: n_task_params must be 6 + 3 n_obs, n_obs <= 256");
   } else {
     if (static_cast<size_t>(c->n_task_params) != expected_task_params(*c))
       return fail(MTP_ERR_INVALID_ARG, "chain task parameter count does not match n_links");
