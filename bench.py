@@ -37,6 +37,7 @@ def workloads():
         "chain7_akima": W.c1,
         "point_mass_bspline": W.c0,
         "chain24_contact_bspline": W.c4,
+        "mix256": lambda: W.mix(256),
     }
 
 
@@ -107,6 +108,8 @@ def main():
     from paper_2505_01059_amd import roofline as RF
 
     cfg = workloads()[args.workload]()
+    if isinstance(cfg, list):
+        return bench_mix(args, cfg)
     x0 = W.initial_state(cfg)
     dev = torch.device("cuda:0")
     plan = mtp.Plan(cfg, device=dev)
@@ -180,6 +183,93 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg, x0)
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def mix_flops(cfgs):
+    from paper_2505_01059_amd import roofline as RF
+    tot = 0
+    for c in cfgs:
+        n_obs = len(c.task.obstacles) if c.dynamics == 0 else 0
+        tot += c.n_samples * c.horizon * c.n_iters * RF.flops_per_sample_step(c.dynamics, c.n_links, n_obs)
+    return tot
+
+
+def bench_mix(args, cfgs):
+    """The uneven 256-instance mix: one persistent launch per replan of all instances,
+    against the same instances replanned one plan at a time on one stream."""
+    import torch
+    import mtp_workloads as W
+    import paper_2505_01059_amd as mtp
+    from paper_2505_01059_amd import roofline as RF
+    dev = torch.device("cuda:0")
+    x0s = [W.initial_state(c, seed=i) for i, c in enumerate(cfgs)]
+    steps_per_replan = sum(c.n_samples * c.horizon * c.n_iters for c in cfgs)
+    bt = mtp.Batch(cfgs, device=dev)
+    wg, order, tune_ms = bt.autotune(reps=1)
+    print(f"[bench] autotune: {wg} workgroups/CU, order {order}, {tune_ms:.2f} ms", file=sys.stderr, flush=True)
+    xp = bt.pack_x0(x0s)
+    for _ in range(args.warmup):
+        bt.replan(xp, shift=1)
+    bt.actions()
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        bt.replan(xp, shift=1)
+        ev[i][1].record(stream)
+    bt.actions()
+    wall = time.perf_counter() - t0
+    launch_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    lat = []
+    for _ in range(max(3, min(args.steps, 10))):
+        t = time.perf_counter()
+        bt.replan(xp, shift=1)
+        bt.actions()
+        lat.append((time.perf_counter() - t) * 1e3)
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()
+
+    # per-instance plain launches: one plan per instance, replanned in turn on one stream
+    plans = [mtp.Plan(c, device=dev) for c in cfgs]
+    xs = [torch.tensor(x, device=dev) for x in x0s]
+    for p, x in zip(plans, xs):
+        p.replan(x, shift=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_steps = max(1, args.steps // 2)
+    for _ in range(plain_steps):
+        for p, x in zip(plans, xs):
+            p.replan(x, shift=1)
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t0
+    for p in plans:
+        p.close()
+
+    value = steps_per_replan * args.steps / wall
+    flops = mix_flops(cfgs)
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    lat.sort()
+    out = {
+        "metric": METRIC, "value": value, "unit": "rollout steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mix256", "instances": len(cfgs),
+                   "candidates_total": sum(c.n_samples for c in cfgs),
+                   "schedule": {"workgroups_per_cu": wg, "longest_first": bool(order)}},
+        "replans_per_s": len(cfgs) * args.steps / wall,
+        "latency_ms_p50": round(statistics.median(lat), 3), "latency_ms_p99": round(lat[-1], 3),
+        "plain_launches": {"replans_per_s": len(cfgs) * plain_steps / plain_wall,
+                           "rollout_steps_per_s": steps_per_replan * plain_steps / plain_wall,
+                           "ms_per_round": plain_wall / plain_steps * 1e3},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": RF.PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / RF.PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "traffic": None, "kernel": "persistent batched replan (all stages, rollout flops)",
+                     "launch_ms": round(launch_ms, 3)},
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -204,6 +204,50 @@ const char* mtp_last_error(const mtp_plan* p);
  * span[t], slopes in units of the knot spacing. */
 mtp_status mtp_interp_table(const mtp_config* cfg, float* h_basis, int32_t* h_span);
 
+/* ---------------------------------------------------------------- batching
+ * Many independent instances (uneven candidate counts, horizons, control dims,
+ * graphs, interpolation, iteration counts) replanned together by ONE
+ * persistent kernel launch replayed from a hipGraph.  Workgroups pull
+ * (instance, stage, iteration, tile) items from a device queue; the last tile of
+ * an instance's stage publishes its next stage.  Every per-instance reduction
+ * has a fixed order, so each instance's result is bit-identical to running it
+ * alone as an mtp_plan with the same config and replan index.
+ *
+ * Packed vectors concatenate the instances in config order: x0 (sum of
+ * state_dim floats) and actions (sum of ctrl_dim floats). */
+typedef struct mtp_batch mtp_batch;
+
+size_t mtp_batch_workspace_bytes(const mtp_config* cfgs, int32_t n);
+mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes,
+                            void* hip_stream, mtp_batch** out);
+/* Replan every instance from the packed start states (device, read by the launch's
+ * first kernel) with per-instance warm-start shifts (host array of n ints; NULL = 0).
+ * All instances use the batch's replan counter, which then increments. */
+mtp_status mtp_batch_replan(mtp_batch* b, const float* d_x0_packed, const int32_t* h_shift);
+/* General step: run CEM iterations [h_k_begin[i], h_k_end[i]) of replan h_r[i] for the
+ * n_active instances listed in h_active (host arrays indexed like h_active).  The shift
+ * applies to instances whose k_begin is 0; x0 is staged for those too (d_x0_packed may
+ * be NULL to keep each instance's x0). */
+mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_active, const int32_t* h_k_begin,
+                          const int32_t* h_k_end, const int32_t* h_shift, const uint32_t* h_r,
+                          const float* d_x0_packed);
+/* Actions of the last launch (packed, host); synchronises; MTP_ERR_DEVICE if the
+ * launch reported a queue timeout or overflow. */
+mtp_status mtp_batch_get_actions(mtp_batch* b, float* h_u_packed);
+mtp_status mtp_batch_get_buffers(const mtp_batch* b, int32_t i, mtp_buffers* out);
+mtp_status mtp_batch_set_state(mtp_batch* b, int32_t i, const float* d_mu, const float* d_sigma);
+/* Schedule knobs of the persistent launch: workgroups per compute unit (0 = the
+ * occupancy limit) and the order of the initial queue (0 = config order,
+ * 1 = longest estimated work first). */
+mtp_status mtp_batch_set_schedule(mtp_batch* b, int32_t wg_per_cu, int32_t order);
+/* Time every schedule (reps replans each, HIP events) and keep the fastest; writes
+ * {wg_per_cu, order} to h_choice and the best milliseconds per replan to h_ms.
+ * Every instance is reset to its initial state and replan index 0 afterwards. */
+mtp_status mtp_batch_autotune(mtp_batch* b, int32_t reps, int32_t* h_choice, float* h_ms);
+mtp_status mtp_batch_set_graph_mode(mtp_batch* b, int32_t use_graph);
+mtp_status mtp_batch_destroy(mtp_batch* b);
+const char* mtp_batch_last_error(const mtp_batch* b);
+
 /* Chain lengths the rollout kernel is instantiated for (writes up to `cap`, returns the count). */
 int32_t mtp_supported_chain_links(int32_t* out, int32_t cap);
 

@@ -83,6 +83,18 @@ def load():
         "mtp_supported_chain_links": (c_int32, [POINTER(c_int32), c_int32]),
         "mtp_interp_table": (c_int32, [P, P, P]),
         "mtp_set_stage_timing": (c_int32, [P, c_int32]),
+        "mtp_batch_workspace_bytes": (c_size_t, [P, c_int32]),
+        "mtp_batch_create": (c_int32, [P, c_int32, P, c_size_t, P, POINTER(P)]),
+        "mtp_batch_replan": (c_int32, [P, P, P]),
+        "mtp_batch_step": (c_int32, [P, c_int32, P, P, P, P, P, P]),
+        "mtp_batch_get_actions": (c_int32, [P, P]),
+        "mtp_batch_get_buffers": (c_int32, [P, c_int32, P]),
+        "mtp_batch_set_state": (c_int32, [P, c_int32, P, P]),
+        "mtp_batch_set_schedule": (c_int32, [P, c_int32, c_int32]),
+        "mtp_batch_autotune": (c_int32, [P, c_int32, P, P]),
+        "mtp_batch_set_graph_mode": (c_int32, [P, c_int32]),
+        "mtp_batch_destroy": (c_int32, [P]),
+        "mtp_batch_last_error": (c_char_p, [P]),
         "mtp_get_stage_times": (c_int32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -291,44 +303,146 @@ class Plan:
 
     def buffers(self):
         """Torch views of the plan's device buffers (see mtp_buffers in mtp.h)."""
-        torch = _torch()
         b = mtp_buffers()
         _check(self.lib, self.lib.mtp_get_buffers(self.handle, byref(b)), self.handle)
-        cfg = self.cfg
-        base = self.workspace.data_ptr()
-        T, n, d = cfg.horizon, cfg.ctrl_dim, cfg.state_dim
-        B, E, L, W, P = cfg.n_samples, cfg.n_elites, cfg.n_layers, cfg.n_width, cfg.n_tensor
-        ld = int(b.ld_U)
-
-        def view(ptr, dtype, shape):
-            if not ptr:
-                return None
-            esz = torch.empty((), dtype=dtype).element_size()
-            count = int(np.prod(shape))
-            off = int(ptr) - base
-            return self.workspace[off:off + count * esz].view(dtype).view(*shape)
-
-        out = dict(
-            Z=view(b.Z, torch.float32, (L, W, n)),
-            I=view(b.I, torch.uint8, (L, max(P, 1)))[:, :P],
-            U=view(b.U, torch.float32, (T, n, ld))[:, :, :B],
-            cost=view(b.cost, torch.float32, (B,)),
-            elite_idx=view(b.elite_idx, torch.int32, (E,)),
-            elite_cost=view(b.elite_cost, torch.float32, (E,)),
-            weights=view(b.weights, torch.float32, (E,)),
-            mu=view(b.mu, torch.float32, (T, n)),
-            sigma=view(b.sigma, torch.float32, (T, n)),
-            x0=view(b.x0, torch.float32, (d,)),
-            action=view(b.action, torch.float32, (n,)),
-        )
-        nd = int(self._c.n_debug_states)
-        out["X"] = view(b.X_dbg, torch.float32, (T, d, nd)) if nd > 0 else None
-        out["ld_U"] = ld
-        return out
+        return _buffer_views(b, self.cfg, self.workspace, int(self._c.n_debug_states))
 
 
-class Batch:  # defined in _batch.py once the batched engine is loaded
-    pass
+def _buffer_views(b, cfg, workspace, n_debug):
+    torch = _torch()
+    base = workspace.data_ptr()
+    T, n, d = cfg.horizon, cfg.ctrl_dim, cfg.state_dim
+    B, E, L, W, P = cfg.n_samples, cfg.n_elites, cfg.n_layers, cfg.n_width, cfg.n_tensor
+    ld = int(b.ld_U)
+
+    def view(ptr, dtype, shape):
+        if not ptr:
+            return None
+        esz = torch.empty((), dtype=dtype).element_size()
+        count = int(np.prod(shape))
+        off = int(ptr) - base
+        return workspace[off:off + count * esz].view(dtype).view(*shape)
+
+    out = dict(
+        Z=view(b.Z, torch.float32, (L, W, n)),
+        I=view(b.I, torch.uint8, (L, max(P, 1)))[:, :P],
+        U=view(b.U, torch.float32, (T, n, ld))[:, :, :B],
+        cost=view(b.cost, torch.float32, (B,)),
+        elite_idx=view(b.elite_idx, torch.int32, (E,)),
+        elite_cost=view(b.elite_cost, torch.float32, (E,)),
+        weights=view(b.weights, torch.float32, (E,)),
+        mu=view(b.mu, torch.float32, (T, n)),
+        sigma=view(b.sigma, torch.float32, (T, n)),
+        x0=view(b.x0, torch.float32, (d,)),
+        action=view(b.action, torch.float32, (n,)),
+    )
+    out["X"] = view(b.X_dbg, torch.float32, (T, d, n_debug)) if n_debug > 0 else None
+    out["ld_U"] = ld
+    return out
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+class Batch:
+    """Many instances replanned by one persistent launch (mtp_batch)."""
+
+    def __init__(self, cfgs, device="cuda", use_graph=True):
+        torch = _torch()
+        self.lib = load()
+        self.cfgs = list(cfgs)
+        self.n = len(self.cfgs)
+        self.device = torch.device(device)
+        structs = [config_struct(c) for c in self.cfgs]
+        self._keep = [k for _, k in structs]
+        arr = (mtp_config * self.n)(*[c for c, _ in structs])
+        self._arr = arr
+        nbytes = int(self.lib.mtp_batch_workspace_bytes(arr, self.n))
+        if nbytes == 0:
+            for i, c in enumerate(self.cfgs):
+                st, why = validate(c)
+                if st != 0:
+                    raise MtpError(st, f"config {i}: {why}")
+            raise MtpError(1, "batch layout failed")
+        self.ws_bytes = nbytes
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        st = self.lib.mtp_batch_create(arr, self.n, c_void_p(self.workspace.data_ptr()), nbytes,
+                                       c_void_p(self.stream.cuda_stream), byref(h))
+        _check(self.lib, st)
+        self.handle = h
+        self.x0_sizes = [c.state_dim for c in self.cfgs]
+        self.act_sizes = [c.ctrl_dim for c in self.cfgs]
+        self._x0 = None
+        if not use_graph:
+            self.lib.mtp_batch_set_graph_mode(self.handle, 0)
+
+    def _err(self, st):
+        if st != 0:
+            raise MtpError(st, self.lib.mtp_status_str(st).decode() + ": " +
+                           self.lib.mtp_batch_last_error(self.handle).decode())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.mtp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack_x0(self, x0s):
+        torch = _torch()
+        flat = np.concatenate([np.asarray(x, np.float32).ravel() for x in x0s]).astype(np.float32)
+        return torch.tensor(flat, device=self.device)
+
+    def replan(self, x0_packed, shift=None):
+        x = x0_packed
+        self._x0 = x
+        sh = None if shift is None else _i32(np.broadcast_to(np.asarray(shift), (self.n,)))
+        self._sh = sh
+        self._err(self.lib.mtp_batch_replan(self.handle, c_void_p(x.data_ptr()),
+                                            None if sh is None else sh.ctypes.data_as(c_void_p)))
+
+    def step(self, active, k_begin, k_end, shift, replan_idx, x0_packed=None):
+        active, kb, ke, sh = _i32(active), _i32(k_begin), _i32(k_end), _i32(shift)
+        rr = np.ascontiguousarray(np.asarray(replan_idx, dtype=np.uint32))
+        self._hold = (active, kb, ke, sh, rr, x0_packed)
+        self._err(self.lib.mtp_batch_step(
+            self.handle, len(active), active.ctypes.data_as(c_void_p), kb.ctypes.data_as(c_void_p),
+            ke.ctypes.data_as(c_void_p), sh.ctypes.data_as(c_void_p), rr.ctypes.data_as(c_void_p),
+            None if x0_packed is None else c_void_p(x0_packed.data_ptr())))
+
+    def actions(self):
+        out = np.zeros(sum(self.act_sizes), np.float32)
+        self._err(self.lib.mtp_batch_get_actions(self.handle, out.ctypes.data_as(c_void_p)))
+        return np.split(out, np.cumsum(self.act_sizes)[:-1])
+
+    def buffers(self, i):
+        b = mtp_buffers()
+        self._err(self.lib.mtp_batch_get_buffers(self.handle, int(i), byref(b)))
+        return _buffer_views(b, self.cfgs[i], self.workspace, 0)
+
+    def set_state(self, i, mu, sigma):
+        torch = _torch()
+        mu = torch.as_tensor(mu, dtype=torch.float32, device=self.device).contiguous()
+        sg = torch.as_tensor(sigma, dtype=torch.float32, device=self.device).contiguous()
+        self._state_keep = (mu, sg)
+        self._err(self.lib.mtp_batch_set_state(self.handle, int(i), c_void_p(mu.data_ptr()),
+                                               c_void_p(sg.data_ptr())))
+
+    def set_schedule(self, wg_per_cu, order):
+        self._err(self.lib.mtp_batch_set_schedule(self.handle, int(wg_per_cu), int(order)))
+
+    def autotune(self, reps=2):
+        choice = np.zeros(2, np.int32)
+        ms = c_float()
+        self._err(self.lib.mtp_batch_autotune(self.handle, int(reps), choice.ctypes.data_as(c_void_p), byref(ms)))
+        return int(choice[0]), int(choice[1]), float(ms.value)
 
 
 class Server:

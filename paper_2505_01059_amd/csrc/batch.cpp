@@ -1,0 +1,521 @@
+// Host side of the persistent batched launch: workspace layout for many
+// instances, queue sizing, staging of per-launch parameters through pinned
+// memory, hipGraph capture of the persistent kernel, and the schedule
+// autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mtp.h"
+#include "batch.hpp"
+#include "plan_internal.hpp"
+
+using namespace mtp;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Rough relative work of one CEM iteration, for longest-first ordering.
+double work_estimate(const mtp_config& c) {
+  const double B = static_cast<double>(c.n_tensor) + c.n_gauss;
+  double per_step = 180.0;
+  if (c.dynamics != MTP_DYN_POINT_MASS) per_step = 186.0 * c.n_links - 108.0 + 12.0 * c.n_links;
+  if (c.dynamics == MTP_DYN_CHAIN_CONTACT) per_step += 96.0 * c.n_links;
+  return B * c.horizon * per_step * c.n_iters;
+}
+
+uint32_t items_for(const mtp_config& c, int k_begin, int k_end) {
+  const int B = c.n_tensor + c.n_gauss;
+  const uint32_t per_iter = host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhCand) +
+                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhRoll) + 1u +
+                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhUpd);
+  return 1u + per_iter * static_cast<uint32_t>(k_end - k_begin);
+}
+
+struct BatchLayout {
+  size_t ctl, descs, ictl, order, out, queue, ready, inst0;
+  std::vector<size_t> res, tr;
+  std::vector<Layout> lays;
+  uint32_t capacity;
+  int32_t x0_total, act_total;
+  size_t total;
+};
+
+bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string* why, mtp_status* code) {
+  if (cfgs == nullptr || n < 1 || n > 65536) {
+    if (why) *why = "need 1..65536 configs";
+    if (code) *code = MTP_ERR_INVALID_ARG;
+    return false;
+  }
+  L->lays.clear();
+  L->capacity = 0;
+  L->x0_total = 0;
+  L->act_total = 0;
+  for (int i = 0; i < n; ++i) {
+    std::string w;
+    if (!validate_config(&cfgs[i], &w, code)) {
+      if (why) *why = "config " + std::to_string(i) + ": " + w;
+      return false;
+    }
+    L->lays.push_back(compute_layout(cfgs[i]));
+    L->capacity += items_for(cfgs[i], 0, cfgs[i].n_iters);
+    L->x0_total += cfgs[i].state_dim;
+    L->act_total += cfgs[i].ctrl_dim;
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+  L->ctl = take(sizeof(BatchCtl));
+  L->descs = take(sizeof(PlanDesc) * n);
+  L->ictl = take(sizeof(InstCtl) * n);
+  L->order = take(sizeof(int32_t) * n);
+  L->out = take(sizeof(float) * (L->act_total + 4));
+  L->queue = take(sizeof(BatchItem) * L->capacity);
+  L->ready = take(sizeof(uint32_t) * L->capacity);
+  L->inst0 = off;
+  L->res.resize(n);
+  L->tr.resize(n);
+  for (int i = 0; i < n; ++i) {
+    L->res[i] = take(L->lays[i].resident);
+    L->tr[i] = take(L->lays[i].transient);
+  }
+  L->total = off;
+  return true;
+}
+
+}  // namespace
+
+struct mtp_batch {
+  int n = 0;
+  std::vector<mtp_config> cfgs;
+  std::vector<std::vector<float>> task, sparams;
+  BatchLayout lay;
+  std::vector<PlanDesc> descs;
+  uint8_t* base = nullptr;
+  hipStream_t stream = nullptr;
+  // device views
+  BatchCtl* d_ctl = nullptr;
+  PlanDesc* d_descs = nullptr;
+  InstCtl* d_ictl = nullptr;
+  int32_t* d_order = nullptr;
+  float* d_out = nullptr;
+  BatchItem* d_queue = nullptr;
+  uint32_t* d_ready = nullptr;
+  // pinned staging
+  InstCtl* h_ictl = nullptr;
+  int32_t* h_order = nullptr;
+  float* h_out = nullptr;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  // schedule
+  int cu_count = 1, max_occ = 1, wg_per_cu = 0, order_mode = 1, grid = 1;
+  std::vector<int32_t> order_natural, order_longest;
+  uint64_t wait_ticks = 0;
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int last_active = 0;
+  uint32_t next_r = 0;
+  bool sticky = false;
+  std::string err;
+};
+
+static mtp_status bdev(mtp_batch* b, hipError_t e, const char* where) {
+  b->sticky = true;
+  b->err = std::string(where) + ": " + hipGetErrorString(e);
+  return MTP_ERR_DEVICE;
+}
+
+#define BCHK(b, expr, where)                     \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return bdev(b, e_, where); \
+  } while (0)
+
+static void drop_graph(mtp_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+static BatchLaunch launch_of(mtp_batch* b, int32_t n_active, uint32_t total, const float* x0) {
+  BatchLaunch L;
+  L.descs = b->d_descs;
+  L.ictl = b->d_ictl;
+  L.ctl = b->d_ctl;
+  L.queue = b->d_queue;
+  L.ready = b->d_ready;
+  L.order = b->d_order;
+  L.n_active = n_active;
+  L.total = total;
+  L.x0_packed = x0;
+  L.wait_ticks = b->wait_ticks;
+  return L;
+}
+
+static void apply_schedule(mtp_batch* b) {
+  const int per_cu = b->wg_per_cu > 0 ? std::min(b->wg_per_cu, b->max_occ) : b->max_occ;
+  b->grid = std::max(1, per_cu * b->cu_count);
+}
+
+static mtp_status ensure_graph(mtp_batch* b) {
+  if (b->exec) return MTP_OK;
+  if (!b->cap_stream) BCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "stream create");
+  BCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  const BatchLaunch L = launch_of(b, 0, 0, nullptr);
+  hipError_t e = launch_batch_persistent(L, b->grid, b->cap_stream);
+  if (e == hipSuccess) e = launch_batch_pack(L, b->d_out, b->n, b->lay.act_total, b->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+  if (e != hipSuccess) { if (g) hipGraphDestroy(g); return bdev(b, e, "capture"); }
+  if (e2 != hipSuccess) return bdev(b, e2, "end capture");
+  b->graph = g;
+  BCHK(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  return MTP_OK;
+}
+
+// Stage per-launch parameters (pinned -> device) and run one persistent launch.
+static mtp_status run_launch(mtp_batch* b, int32_t n_active, uint32_t total, const float* d_x0) {
+  if (b->staged_pending) BCHK(b, hipEventSynchronize(b->staged), "staging wait");
+  BCHK(b, hipMemcpyAsync(b->d_ictl, b->h_ictl, sizeof(InstCtl) * b->n, hipMemcpyHostToDevice, b->stream), "ictl copy");
+  BCHK(b, hipMemcpyAsync(b->d_order, b->h_order, sizeof(int32_t) * n_active, hipMemcpyHostToDevice, b->stream),
+       "order copy");
+  BCHK(b, hipEventRecord(b->staged, b->stream), "event");
+  b->staged_pending = true;
+  const BatchLaunch L = launch_of(b, n_active, total, d_x0);
+  BCHK(b, launch_batch_prepare(L, b->stream), "prepare");
+  if (b->use_graph) {
+    const mtp_status s = ensure_graph(b);
+    if (s != MTP_OK) return s;
+    BCHK(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
+  } else {
+    BCHK(b, launch_batch_persistent(L, b->grid, b->stream), "persistent");
+    BCHK(b, launch_batch_pack(L, b->d_out, b->n, b->lay.act_total, b->stream), "pack");
+  }
+  b->last_active = n_active;
+  return MTP_OK;
+}
+
+static mtp_status reset_instances(mtp_batch* b) {
+  for (int i = 0; i < b->n; ++i) {
+    const mtp_status s = upload_plan_tables(b->cfgs[i], b->descs[i], b->task[i].data(),
+                                            b->sparams[i].empty() ? nullptr : b->sparams[i].data(), b->stream,
+                                            &b->err);
+    if (s != MTP_OK) {
+      b->sticky = true;
+      return s;
+    }
+  }
+  b->next_r = 0;
+  return MTP_OK;
+}
+
+extern "C" {
+
+size_t mtp_batch_workspace_bytes(const mtp_config* cfgs, int32_t n) {
+  BatchLayout L;
+  if (!batch_layout(cfgs, n, &L, nullptr, nullptr)) return 0;
+  return L.total;
+}
+
+mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                            mtp_batch** out) {
+  if (out == nullptr) return MTP_ERR_INVALID_ARG;
+  *out = nullptr;
+  BatchLayout lay;
+  std::string why;
+  mtp_status code = MTP_OK;
+  if (!batch_layout(cfgs, n, &lay, &why, &code)) return code;
+  if (d_workspace == nullptr || ws_bytes < lay.total || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
+    return MTP_ERR_WORKSPACE;
+  mtp_batch* b = new (std::nothrow) mtp_batch();
+  if (b == nullptr) return MTP_ERR_INVALID_ARG;
+  b->n = n;
+  b->lay = lay;
+  b->base = static_cast<uint8_t*>(d_workspace);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->cfgs.assign(cfgs, cfgs + n);
+  b->task.resize(n);
+  b->sparams.resize(n);
+  b->descs.resize(n);
+  for (int i = 0; i < n; ++i) {
+    mtp_config& c = b->cfgs[i];
+    b->task[i].assign(c.task_params, c.task_params + c.n_task_params);
+    c.task_params = b->task[i].data();
+    if (c.dynamics == MTP_DYN_CHAIN_CONTACT) {
+      const size_t B = static_cast<size_t>(c.n_tensor) + c.n_gauss;
+      b->sparams[i].assign(c.sample_params, c.sample_params + B * (c.ctrl_dim + 1));
+      c.sample_params = b->sparams[i].data();
+    } else {
+      c.sample_params = nullptr;
+    }
+    b->descs[i] = make_desc(c, lay.lays[i], b->base + lay.res[i], b->base + lay.tr[i]);
+  }
+  b->d_ctl = reinterpret_cast<BatchCtl*>(b->base + lay.ctl);
+  b->d_descs = reinterpret_cast<PlanDesc*>(b->base + lay.descs);
+  b->d_ictl = reinterpret_cast<InstCtl*>(b->base + lay.ictl);
+  b->d_order = reinterpret_cast<int32_t*>(b->base + lay.order);
+  b->d_out = reinterpret_cast<float*>(b->base + lay.out);
+  b->d_queue = reinterpret_cast<BatchItem*>(b->base + lay.queue);
+  b->d_ready = reinterpret_cast<uint32_t*>(b->base + lay.ready);
+
+  auto fail = [&](hipError_t e, const char* where) {
+    mtp_batch_destroy(b);
+    (void)e;
+    (void)where;
+    return MTP_ERR_DEVICE;
+  };
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_ictl), sizeof(InstCtl) * n, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_order), sizeof(int32_t) * n, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(float) * (lay.act_total + 4), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e != hipSuccess) return fail(e, "host alloc");
+
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  int cus = 0, clk_khz = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return fail(e, "device query");
+  b->cu_count = std::max(1, cus);
+  b->max_occ = std::max(1, batch_max_blocks_per_cu());
+  // every wait of the persistent kernel gives up after 10 s of wall clock
+  if (clk_khz <= 0) clk_khz = 100000;   // the constant-rate counter runs at 100 MHz on this family
+  b->wait_ticks = static_cast<uint64_t>(clk_khz) * 1000ull * 10ull;
+  apply_schedule(b);
+
+  b->order_natural.resize(n);
+  std::iota(b->order_natural.begin(), b->order_natural.end(), 0);
+  b->order_longest = b->order_natural;
+  std::stable_sort(b->order_longest.begin(), b->order_longest.end(), [&](int a, int c) {
+    return work_estimate(b->cfgs[a]) > work_estimate(b->cfgs[c]);
+  });
+
+  // device tables and control block
+  BatchCtl ctl{};
+  ctl.capacity = lay.capacity;
+  e = hipMemcpyAsync(b->d_descs, b->descs.data(), sizeof(PlanDesc) * n, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_ready, 0, sizeof(uint32_t) * lay.capacity, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(e, "tables");
+  if (reset_instances(b) != MTP_OK) {
+    mtp_batch_destroy(b);
+    return MTP_ERR_DEVICE;
+  }
+  *out = b;
+  return MTP_OK;
+}
+
+mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_active, const int32_t* h_k_begin,
+                          const int32_t* h_k_end, const int32_t* h_shift, const uint32_t* h_r,
+                          const float* d_x0_packed) {
+  if (b == nullptr) return MTP_ERR_INVALID_ARG;
+  if (b->sticky) return MTP_ERR_DEVICE;
+  if (n_active < 0 || n_active > b->n || (n_active > 0 && (h_active == nullptr || h_k_begin == nullptr ||
+                                                           h_k_end == nullptr || h_r == nullptr))) {
+    b->err = "bad step arguments";
+    return MTP_ERR_INVALID_ARG;
+  }
+  if (n_active == 0) return MTP_OK;
+  if (b->staged_pending) BCHK(b, hipEventSynchronize(b->staged), "staging wait");
+  b->staged_pending = false;
+  std::vector<char> seen(b->n, 0);
+  uint32_t total = 0;
+  int x0_off = 0;
+  std::vector<int32_t> x0_offsets(b->n);
+  std::vector<int32_t> act_offsets(b->n);
+  int act_off = 0;
+  for (int i = 0; i < b->n; ++i) {
+    x0_offsets[i] = x0_off;
+    act_offsets[i] = act_off;
+    x0_off += b->cfgs[i].state_dim;
+    act_off += b->cfgs[i].ctrl_dim;
+  }
+  for (int i = 0; i < b->n; ++i) {
+    InstCtl& c = b->h_ictl[i];
+    std::memset(&c, 0, sizeof(c));
+    c.x0_off = -1;
+    c.act_off = act_offsets[i];
+  }
+  for (int a = 0; a < n_active; ++a) {
+    const int i = h_active[a];
+    if (i < 0 || i >= b->n || seen[i]) {
+      b->err = "active list has a bad or repeated instance";
+      return MTP_ERR_INVALID_ARG;
+    }
+    seen[i] = 1;
+    const int kb = h_k_begin[a], ke = h_k_end[a];
+    if (kb < 0 || ke <= kb || ke > 65535) {
+      b->err = "bad iteration range";
+      return MTP_ERR_INVALID_ARG;
+    }
+    const int sh = h_shift ? h_shift[a] : 0;
+    if (sh < 0) {
+      b->err = "negative shift";
+      return MTP_ERR_INVALID_ARG;
+    }
+    InstCtl& c = b->h_ictl[i];
+    c.k_begin = static_cast<uint32_t>(kb);
+    c.k_end = static_cast<uint32_t>(ke);
+    c.r = h_r[a];
+    c.shift = sh;
+    c.x0_off = (d_x0_packed != nullptr && kb == 0) ? x0_offsets[i] : -1;
+    b->h_order[a] = i;
+    total += items_for(b->cfgs[i], kb, ke);
+  }
+  if (total > b->lay.capacity) {
+    b->err = "step needs more queue items than the batch was sized for";
+    return MTP_ERR_INVALID_ARG;
+  }
+  return run_launch(b, n_active, total, d_x0_packed);
+}
+
+mtp_status mtp_batch_replan(mtp_batch* b, const float* d_x0_packed, const int32_t* h_shift) {
+  if (b == nullptr) return MTP_ERR_INVALID_ARG;
+  if (d_x0_packed == nullptr) {
+    b->err = "d_x0_packed is NULL";
+    return MTP_ERR_INVALID_ARG;
+  }
+  const std::vector<int32_t>& ord = b->order_mode == 1 ? b->order_longest : b->order_natural;
+  std::vector<int32_t> kb(b->n, 0), ke(b->n), sh(b->n, 0);
+  std::vector<uint32_t> rr(b->n, b->next_r);
+  for (int a = 0; a < b->n; ++a) {
+    const int i = ord[a];
+    ke[a] = b->cfgs[i].n_iters;
+    sh[a] = h_shift ? h_shift[i] : 0;
+  }
+  const mtp_status s = mtp_batch_step(b, b->n, ord.data(), kb.data(), ke.data(), sh.data(), rr.data(), d_x0_packed);
+  if (s == MTP_OK) b->next_r += 1;
+  return s;
+}
+
+mtp_status mtp_batch_get_actions(mtp_batch* b, float* h_u_packed) {
+  if (b == nullptr || h_u_packed == nullptr) return MTP_ERR_INVALID_ARG;
+  if (b->sticky) return MTP_ERR_DEVICE;
+  const size_t bytes = sizeof(float) * (b->lay.act_total + 4);
+  BCHK(b, hipMemcpyAsync(b->h_out, b->d_out, bytes, hipMemcpyDeviceToHost, b->stream), "actions copy");
+  BCHK(b, hipStreamSynchronize(b->stream), "sync");
+  uint32_t st[3];
+  std::memcpy(st, b->h_out + b->lay.act_total, sizeof(st));
+  if (st[0] != 0u) {
+    b->sticky = true;
+    b->err = st[0] & 2u ? "persistent launch: queue overflow" : "persistent launch: a queue wait timed out";
+    return MTP_ERR_DEVICE;
+  }
+  if (st[1] != static_cast<uint32_t>(b->last_active)) {
+    b->sticky = true;
+    b->err = "persistent launch: not every instance finished";
+    return MTP_ERR_DEVICE;
+  }
+  std::memcpy(h_u_packed, b->h_out, sizeof(float) * b->lay.act_total);
+  return MTP_OK;
+}
+
+mtp_status mtp_batch_get_buffers(const mtp_batch* b, int32_t i, mtp_buffers* out) {
+  if (b == nullptr || out == nullptr || i < 0 || i >= b->n) return MTP_ERR_INVALID_ARG;
+  const PlanDesc& P = b->descs[i];
+  out->Z = P.Z; out->I = P.I; out->U = P.U; out->cost = P.cost; out->elite_idx = P.eidx;
+  out->elite_cost = P.ecost; out->weights = P.w; out->mu = P.mu; out->sigma = P.sigma; out->x0 = P.x0;
+  out->action = P.action; out->X_dbg = P.X; out->ld_U = static_cast<size_t>(P.ldU);
+  return MTP_OK;
+}
+
+mtp_status mtp_batch_set_state(mtp_batch* b, int32_t i, const float* d_mu, const float* d_sigma) {
+  if (b == nullptr || i < 0 || i >= b->n || d_mu == nullptr || d_sigma == nullptr) return MTP_ERR_INVALID_ARG;
+  if (b->sticky) return MTP_ERR_DEVICE;
+  const size_t bytes = sizeof(float) * b->cfgs[i].horizon * b->cfgs[i].ctrl_dim;
+  BCHK(b, hipMemcpyAsync(b->descs[i].mu, d_mu, bytes, hipMemcpyDeviceToDevice, b->stream), "mu copy");
+  BCHK(b, hipMemcpyAsync(b->descs[i].sigma, d_sigma, bytes, hipMemcpyDeviceToDevice, b->stream), "sigma copy");
+  return MTP_OK;
+}
+
+mtp_status mtp_batch_set_schedule(mtp_batch* b, int32_t wg_per_cu, int32_t order) {
+  if (b == nullptr || wg_per_cu < 0 || order < 0 || order > 1) return MTP_ERR_INVALID_ARG;
+  b->wg_per_cu = wg_per_cu;
+  b->order_mode = order;
+  const int old = b->grid;
+  apply_schedule(b);
+  if (b->grid != old) drop_graph(b);
+  return MTP_OK;
+}
+
+mtp_status mtp_batch_set_graph_mode(mtp_batch* b, int32_t use_graph) {
+  if (b == nullptr) return MTP_ERR_INVALID_ARG;
+  b->use_graph = use_graph != 0;
+  return MTP_OK;
+}
+
+mtp_status mtp_batch_autotune(mtp_batch* b, int32_t reps, int32_t* h_choice, float* h_ms) {
+  if (b == nullptr || reps < 1) return MTP_ERR_INVALID_ARG;
+  if (b->sticky) return MTP_ERR_DEVICE;
+  // x0 of every instance as it stands: stage nothing (x0_packed NULL keeps it)
+  hipEvent_t e0, e1;
+  BCHK(b, hipEventCreate(&e0), "event");
+  BCHK(b, hipEventCreate(&e1), "event");
+  float best = -1.0f;
+  int best_wg = b->wg_per_cu, best_order = b->order_mode;
+  for (int order = 0; order <= 1; ++order) {
+    for (int wg = 1; wg <= b->max_occ; ++wg) {
+      mtp_batch_set_schedule(b, wg, order);
+      const std::vector<int32_t>& ord = order == 1 ? b->order_longest : b->order_natural;
+      std::vector<int32_t> kb(b->n, 0), ke(b->n), sh(b->n, 0);
+      std::vector<uint32_t> rr(b->n, 0);
+      for (int a = 0; a < b->n; ++a) ke[a] = b->cfgs[ord[a]].n_iters;
+      mtp_status s = mtp_batch_step(b, b->n, ord.data(), kb.data(), ke.data(), sh.data(), rr.data(), nullptr);
+      if (s != MTP_OK) return s;
+      BCHK(b, hipEventRecord(e0, b->stream), "event");
+      for (int r = 0; r < reps && s == MTP_OK; ++r)
+        s = mtp_batch_step(b, b->n, ord.data(), kb.data(), ke.data(), sh.data(), rr.data(), nullptr);
+      if (s != MTP_OK) return s;
+      BCHK(b, hipEventRecord(e1, b->stream), "event");
+      BCHK(b, hipEventSynchronize(e1), "event sync");
+      float ms = 0.0f;
+      BCHK(b, hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      ms /= static_cast<float>(reps);
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        best_wg = wg;
+        best_order = order;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // verify the last launch completed cleanly
+  std::vector<float> acts(b->lay.act_total);
+  const mtp_status s = mtp_batch_get_actions(b, acts.data());
+  if (s != MTP_OK) return s;
+  mtp_batch_set_schedule(b, best_wg, best_order);
+  if (h_choice) {
+    h_choice[0] = best_wg;
+    h_choice[1] = best_order;
+  }
+  if (h_ms) *h_ms = best;
+  return reset_instances(b);
+}
+
+mtp_status mtp_batch_destroy(mtp_batch* b) {
+  if (b == nullptr) return MTP_ERR_INVALID_ARG;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  if (b->h_ictl) (void)hipHostFree(b->h_ictl);
+  if (b->h_order) (void)hipHostFree(b->h_order);
+  if (b->h_out) (void)hipHostFree(b->h_out);
+  delete b;
+  return MTP_OK;
+}
+
+const char* mtp_batch_last_error(const mtp_batch* b) { return b ? b->err.c_str() : "no batch"; }
+
+}  // extern "C"

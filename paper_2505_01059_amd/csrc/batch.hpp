@@ -1,0 +1,68 @@
+// Persistent batched launch: queue items, control blocks and host launchers.
+#pragma once
+
+#include "mtp_device.hpp"
+
+namespace mtp {
+
+constexpr int kBatchThreads = 256;       // workgroup of the persistent kernel
+constexpr int kUpdOutputsPerTile = 64;   // refit outputs per queue item
+
+enum : uint32_t { kPhShift = 0, kPhCand = 1, kPhRoll = 2, kPhTopk = 3, kPhUpd = 4 };
+
+struct BatchItem {
+  uint32_t inst, phase, k, tile;
+};
+
+struct BatchCtl {
+  uint32_t head;       // next queue position to take
+  uint32_t tail;       // next queue position to publish
+  uint32_t total;      // items this launch will run
+  uint32_t epoch;      // ready-flag value of this launch
+  uint32_t finished;   // instances that completed their iterations
+  uint32_t error;      // bit 0: a wait timed out, bit 1: queue overflow
+  uint32_t capacity;   // queue length
+  uint32_t pad;
+};
+
+struct InstCtl {
+  uint32_t done;       // tiles of the current phase completed
+  uint32_t k_begin;    // first CEM iteration this launch runs
+  uint32_t k_end;      // one past the last
+  uint32_t r;          // Philox replan index
+  int32_t shift;       // warm-start shift applied when k_begin == 0
+  int32_t x0_off;      // offset of this instance's x0 in the packed input (-1: keep)
+  int32_t act_off;     // offset of its action in the packed output
+  int32_t pad;
+};
+
+struct BatchLaunch {
+  const PlanDesc* descs;
+  InstCtl* ictl;
+  BatchCtl* ctl;
+  BatchItem* queue;
+  uint32_t* ready;
+  const int32_t* order;
+  int32_t n_active;
+  uint32_t total;
+  const float* x0_packed;
+  uint64_t wait_ticks;
+};
+
+hipError_t launch_batch_prepare(const BatchLaunch& L, hipStream_t st);
+hipError_t launch_batch_persistent(const BatchLaunch& L, int grid, hipStream_t st);
+hipError_t launch_batch_pack(const BatchLaunch& L, float* out, int32_t n_inst, int32_t status_off, hipStream_t st);
+int batch_max_blocks_per_cu();
+
+// host mirror of the per-phase tile counts
+inline uint32_t host_phase_tiles(int B, int T, int n, uint32_t phase) {
+  switch (phase) {
+    case kPhShift: return 1u;
+    case kPhCand: return static_cast<uint32_t>((B + kCandThreads - 1) / kCandThreads);
+    case kPhRoll: return static_cast<uint32_t>((B + kBatchThreads - 1) / kBatchThreads);
+    case kPhTopk: return 1u;
+    default: return static_cast<uint32_t>((T * n + kUpdOutputsPerTile - 1) / kUpdOutputsPerTile);
+  }
+}
+
+}  // namespace mtp

@@ -43,9 +43,6 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(PlanDesc P) {
 
 // ---------------------------------------------------------------- dispatch
 
-#define MTP_CHAIN_LINKS(X) X(2) X(3) X(4) X(7) X(12) X(24)
-#define MTP_CONTACT_LINKS(X) X(4) X(7) X(24)
-
 static const int kChainLinks[] = {
 #define X(N) N,
     MTP_CHAIN_LINKS(X)

@@ -19,6 +19,11 @@ constexpr int kTopkThreads = 1024;  // top-E: one workgroup per plan
 constexpr int kUpdThreads = 256;    // refit tile: 4 waves, one (t, j) output per wave
 
 enum Dyn : int32_t { kPointMass = 0, kChain = 1, kChainContact = 2 };
+
+// Chain lengths the rollout is instantiated for (compile-time link count keeps
+// the per-link state in registers).
+#define MTP_CHAIN_LINKS(X) X(2) X(3) X(4) X(7) X(12) X(24)
+#define MTP_CONTACT_LINKS(X) X(4) X(7) X(24)
 enum Interp : int32_t { kBspline = 0, kAkima = 1 };
 
 // Everything a stage needs, by value in kernel arguments (or in a device table
@@ -501,6 +506,12 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
   P.cost[b] = finite_or_inf(cost);
 }
 
+__device__ __forceinline__ float wave_sum64(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // ------------------------------------------------------------------ top-E
 // 64-bit keys (order-preserving image of the float cost) << 32 | index are all
 // distinct, so an 8-pass byte-wise radix select finds the E-th smallest key
@@ -610,14 +621,18 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     P.w[e] = z;
     part += z;
   }
-  // deterministic block sum: fixed wave shuffles, then wave totals in order
-  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-  if ((tid & 63) == 0) sm.red[tid >> 6] = part;
+  (void)part;
+  // normalisation sum in an order fixed by E alone (independent of the block
+  // size): lane l of wave 0 adds e = l, l+64, ... in turn, then a butterfly.
   __syncthreads();
-  float tot = 0.0f;
-  for (int wv = 0; wv < BS / 64; ++wv) tot += sm.red[wv];
-  const float inv = 1.0f / tot;
+  if (tid < 64) {
+    float acc = 0.0f;
+    for (int e = tid; e < E; e += 64) acc += P.w[e];
+    acc = wave_sum64(acc);
+    if (tid == 0) sm.red[0] = acc;
+  }
   __syncthreads();
+  const float inv = 1.0f / sm.red[0];
   for (int e = tid; e < E; e += BS) P.w[e] *= inv;
   if (tid == 0 && !(s0 < INFINITY)) atomicOr(&P.ctrl[2], 1u);
 }
@@ -625,11 +640,6 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
 // ------------------------------------------------------------------ refit
 // One wave per output (t, j): lanes stride over the elites, fixed-order
 // butterfly reduction, then the sigma floor and exponential smoothing.
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
   const int lane = threadIdx.x & 63;
@@ -637,13 +647,13 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
   const float* row = P.U + static_cast<size_t>(o) * ld;
   float m = 0.0f;
   for (int e = lane; e < P.E; e += 64) m = fmaf(P.w[e], row[P.eidx[e]], m);
-  m = wave_sum(m);
+  m = wave_sum64(m);
   float v = 0.0f;
   for (int e = lane; e < P.E; e += 64) {
     const float dv = row[P.eidx[e]] - m;
     v = fmaf(P.w[e], dv * dv, v);
   }
-  v = wave_sum(v);
+  v = wave_sum64(v);
   if (lane == 0) {
     const float sd = fmaxf(sqrtf(v), P.sigma_min);
     const float mu_old = P.mu[o], sg_old = P.sigma[o];

@@ -124,6 +124,8 @@ Layout compute_layout(const mtp_config& c) {
   L.span = take(T * 4);
   L.task = take(static_cast<size_t>(c.n_task_params) * 4);
   L.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? take(B * (n + 1) * 4) : 0;
+  L.resident = off;
+  off = 0;
   L.Z = take(static_cast<size_t>(c.n_layers) * c.n_width * n * 4);
   L.I = take(static_cast<size_t>(c.n_layers) * (c.n_tensor > 0 ? c.n_tensor : 1));
   L.U = take(T * n * L.ldU * 4);
@@ -132,7 +134,8 @@ Layout compute_layout(const mtp_config& c) {
   L.ecost = take(static_cast<size_t>(c.n_elites) * 4);
   L.w = take(static_cast<size_t>(c.n_elites) * 4);
   L.X = c.n_debug_states > 0 ? take(T * d * static_cast<size_t>(c.n_debug_states) * 4) : 0;
-  L.total = off;
+  L.transient = off;
+  L.total = L.resident + L.transient;
   return L;
 }
 
@@ -234,7 +237,18 @@ static mtp_status device_err(mtp_plan* p, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return device_err(p, e_, where); \
   } while (0)
 
-static PlanDesc make_desc(const mtp_config& c, const Layout& L, uint8_t* base) {
+void mtp::set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* tb) {
+  P->Z = reinterpret_cast<float*>(tb + L.Z);
+  P->I = tb + L.I;
+  P->U = reinterpret_cast<float*>(tb + L.U);
+  P->cost = reinterpret_cast<float*>(tb + L.cost);
+  P->eidx = reinterpret_cast<int32_t*>(tb + L.eidx);
+  P->ecost = reinterpret_cast<float*>(tb + L.ecost);
+  P->w = reinterpret_cast<float*>(tb + L.w);
+  P->X = c.n_debug_states > 0 ? reinterpret_cast<float*>(tb + L.X) : nullptr;
+}
+
+PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uint8_t* tb) {
   PlanDesc P{};
   P.dyn = c.dynamics; P.interp = c.interp; P.n_links = c.n_links; P.d = c.state_dim; P.n = c.ctrl_dim;
   P.T = c.horizon; P.L = c.n_layers; P.W = c.n_width; P.P = c.n_tensor; P.G = c.n_gauss;
@@ -255,14 +269,7 @@ static PlanDesc make_desc(const mtp_config& c, const Layout& L, uint8_t* base) {
   P.span = reinterpret_cast<const int32_t*>(base + L.span);
   P.task = reinterpret_cast<const float*>(base + L.task);
   P.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? reinterpret_cast<const float*>(base + L.sparams) : nullptr;
-  P.Z = reinterpret_cast<float*>(base + L.Z);
-  P.I = base + L.I;
-  P.U = reinterpret_cast<float*>(base + L.U);
-  P.cost = reinterpret_cast<float*>(base + L.cost);
-  P.eidx = reinterpret_cast<int32_t*>(base + L.eidx);
-  P.ecost = reinterpret_cast<float*>(base + L.ecost);
-  P.w = reinterpret_cast<float*>(base + L.w);
-  P.X = c.n_debug_states > 0 ? reinterpret_cast<float*>(base + L.X) : nullptr;
+  if (tb != nullptr) set_transient(&P, c, L, tb);
   return P;
 }
 
@@ -390,7 +397,8 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
   p->cfg.sample_params = p->sparams.empty() ? nullptr : p->sparams.data();
   p->lay = lay;
   p->stream = static_cast<hipStream_t>(hip_stream);
-  p->P = make_desc(p->cfg, lay, static_cast<uint8_t*>(d_workspace));
+  p->P = make_desc(p->cfg, lay, static_cast<uint8_t*>(d_workspace),
+                   static_cast<uint8_t*>(d_workspace) + lay.resident);
   const mtp_status s = upload_plan_tables(p->cfg, p->P, p->task.data(), p->cfg.sample_params, p->stream, &p->err);
   if (s != MTP_OK) {
     delete p;

@@ -11,11 +11,18 @@
 
 namespace mtp {
 
-// Byte offsets of every buffer of one plan inside its workspace (256-aligned).
+// Byte offsets of every buffer of one plan (256-aligned).  The resident part
+// (control block, start state, warm start, tables) lives as long as the plan;
+// the transient part (graph, paths, candidates, costs, elites) is only needed
+// while a replan runs, so a server can lend it from a shared pool.  Resident
+// offsets are relative to the resident base, transient ones to the transient
+// base; a single plan places the transient part right after the resident one.
 struct Layout {
   size_t ldU;
-  size_t ctrl, x0, mu, sigma, tmp, action, basis, span, task, sparams, Z, I, U, cost, eidx, ecost, w, X;
-  size_t total;
+  size_t ctrl, x0, mu, sigma, tmp, action, basis, span, task, sparams;   // resident
+  size_t Z, I, U, cost, eidx, ecost, w, X;                               // transient
+  size_t resident, transient;
+  size_t total;   // resident + transient
 };
 
 bool validate_config(const mtp_config* c, std::string* why, mtp_status* code);
@@ -24,5 +31,8 @@ void build_tables(const mtp_config& c, std::vector<float>* basis, std::vector<in
 mtp_status upload_plan_tables(const mtp_config& c, const PlanDesc& P, const float* task, const float* sparams,
                               hipStream_t st, std::string* err);
 hipError_t enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStream_t st);
+PlanDesc make_desc(const mtp_config& c, const Layout& L, uint8_t* resident, uint8_t* transient);
+// Point a descriptor's transient buffers at a new base.
+void set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* transient);
 
 }  // namespace mtp

@@ -1,0 +1,130 @@
+"""Persistent batched launch: every instance's result equals running it alone.
+
+Per-instance reductions have an order fixed by the instance, so the batched
+mean, std and action must match a standalone plan bit for bit, whatever the
+other instances are and whichever workgroups ran the tiles."""
+import sys
+
+import numpy as np
+import pytest
+
+import mtp_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def small_mix():
+    return [
+        W.point_mass_config(name="b_pm", n_tensor=300, n_gauss=45, horizon=37, n_layers=5, n_width=7,
+                            n_elites=20, n_iters=3, seed=1),
+        W.chain_config(name="b_c7", n_tensor=700, n_gauss=101, horizon=66, n_elites=40, n_iters=2, seed=2),
+        W.point_mass_config(name="b_pm_ak", interp=W.AKIMA, n_tensor=260, n_gauss=33, horizon=50,
+                            n_layers=6, n_width=9, n_elites=16, n_iters=4, seed=3),
+        W.chain_config(name="b_c2", n_links=2, n_tensor=200, n_gauss=57, horizon=30, n_layers=4, n_width=5,
+                       n_elites=10, n_iters=3, seed=4),
+        W.chain_config(name="b_c12", n_links=12, interp=W.BSPLINE, n_tensor=250, n_gauss=70, horizon=32,
+                       n_layers=9, n_width=40, n_elites=30, n_iters=2, seed=5),
+        W.chain_config(name="b_c24", n_links=24, interp=W.AKIMA, n_tensor=130, n_gauss=70, horizon=24,
+                       n_layers=12, n_width=64, n_elites=16, n_iters=2, seed=6),
+        W.chain_contact_config(name="b_k24", n_tensor=200, n_gauss=56, horizon=48, n_elites=16, n_iters=2,
+                               seed=7),
+    ]
+
+
+def standalone(cfg, x0, replans, shift=1):
+    import torch
+    import paper_2505_01059_amd as mtp
+    p = mtp.Plan(cfg, device="cuda:0")
+    for r in range(replans):
+        p.replan(x0, shift=shift, replan_idx=r)
+    torch.cuda.synchronize()
+    b = p.buffers()
+    out = (b["mu"].cpu().numpy().copy(), b["sigma"].cpu().numpy().copy(), p.action())
+    p.close()
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_equals_standalone(use_graph):
+    import torch
+    import paper_2505_01059_amd as mtp
+    cfgs = small_mix()
+    x0s = [W.initial_state(c, seed=i) for i, c in enumerate(cfgs)]
+    _log(f"[batch] {len(cfgs)} instances, graph={use_graph}")
+    bt = mtp.Batch(cfgs, device="cuda:0", use_graph=use_graph)
+    xp = bt.pack_x0(x0s)
+    for r in range(2):
+        bt.replan(xp, shift=1)
+    acts = bt.actions()
+    for i, c in enumerate(cfgs):
+        mu, sg, a = standalone(c, x0s[i], 2)
+        b = bt.buffers(i)
+        assert np.array_equal(b["mu"].cpu().numpy(), mu), c.name
+        assert np.array_equal(b["sigma"].cpu().numpy(), sg), c.name
+        assert np.array_equal(acts[i], a), c.name
+    bt.close()
+
+
+def test_batch_step_split_iterations_and_subsets():
+    """Running iterations [0, 1) and then [1, K) of a replan, in launches that
+    include other instances or not, gives the same bits as one replan."""
+    import torch
+    import paper_2505_01059_amd as mtp
+    cfgs = small_mix()[:4]
+    x0s = [W.initial_state(c, seed=10 + i) for i, c in enumerate(cfgs)]
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    xp = bt.pack_x0(x0s)
+    # launch 1: instances 0 and 2 do their first iteration, 1 does the whole replan
+    bt.step([0, 2, 1], [0, 0, 0], [1, 1, cfgs[1].n_iters], [1, 1, 1], [0, 0, 0], xp)
+    # launch 2: 0 and 2 finish, 3 does everything
+    bt.step([2, 3, 0], [1, 0, 1], [cfgs[2].n_iters, cfgs[3].n_iters, cfgs[0].n_iters], [0, 1, 0], [0, 0, 0], xp)
+    acts = bt.actions()
+    torch.cuda.synchronize()
+    for i, c in enumerate(cfgs):
+        mu, sg, a = standalone(c, x0s[i], 1)
+        b = bt.buffers(i)
+        assert np.array_equal(b["mu"].cpu().numpy(), mu), c.name
+        assert np.array_equal(b["sigma"].cpu().numpy(), sg), c.name
+        if i in (0, 2, 3):
+            assert np.array_equal(acts[i], a), c.name
+    bt.close()
+
+
+def test_batch_autotune_and_reset():
+    import paper_2505_01059_amd as mtp
+    cfgs = small_mix()[:3]
+    x0s = [W.initial_state(c) for c in cfgs]
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    wg, order, ms = bt.autotune(reps=1)
+    _log(f"[autotune] wg/CU={wg} order={order} {ms:.3f} ms")
+    assert wg >= 1 and order in (0, 1) and ms > 0
+    xp = bt.pack_x0(x0s)
+    bt.replan(xp, shift=1)                       # replan index 0 after the reset
+    acts = bt.actions()
+    for i, c in enumerate(cfgs):
+        mu, sg, a = standalone(c, x0s[i], 1)
+        assert np.array_equal(acts[i], a)
+    bt.close()
+
+
+def test_mix_of_256_sampled_against_standalone():
+    """The full uneven mix in one launch; a sample of instances checked bit for bit."""
+    import torch
+    import paper_2505_01059_amd as mtp
+    cfgs = W.mix(256)
+    x0s = [W.initial_state(c, seed=i) for i, c in enumerate(cfgs)]
+    _log(f"[mix] total candidates {sum(c.n_samples for c in cfgs)}")
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    xp = bt.pack_x0(x0s)
+    bt.replan(xp, shift=1)
+    acts = bt.actions()
+    for i in (0, 1, 5, 77, 128, 255):
+        mu, sg, a = standalone(cfgs[i], x0s[i], 1)
+        b = bt.buffers(i)
+        assert np.array_equal(b["mu"].cpu().numpy(), mu), cfgs[i].name
+        assert np.array_equal(acts[i], a), cfgs[i].name
+    bt.close()
