@@ -38,6 +38,7 @@ def workloads():
         "point_mass_bspline": W.c0,
         "chain24_contact_bspline": W.c4,
         "mix256": lambda: W.mix(256),
+        "serve512": lambda: ("serve", W.robot_fleet(512)),
     }
 
 
@@ -95,6 +96,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="chain7_akima", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, nargs="+", default=[2000.0],
+                    help="serving: Poisson request rates (req/s) to run, one after another")
+    ap.add_argument("--duration", type=float, default=20.0, help="serving: measured seconds per rate")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="serving: device-memory budget of the pool")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -108,6 +113,8 @@ def main():
     from paper_2505_01059_amd import roofline as RF
 
     cfg = workloads()[args.workload]()
+    if isinstance(cfg, tuple):
+        return bench_serve(args, cfg[1])
     if isinstance(cfg, list):
         return bench_mix(args, cfg)
     x0 = W.initial_state(cfg)
@@ -269,6 +276,85 @@ def bench_mix(args, cfgs):
                      "traffic": None, "kernel": "persistent batched replan (all stages, rollout flops)",
                      "launch_ms": round(launch_ms, 3)},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, robots):
+    """Poisson replan requests from many robots through the continuous-batching server."""
+    import numpy as np
+    import torch
+    import mtp_workloads as W
+    import paper_2505_01059_amd as mtp
+    dev = torch.device("cuda:0")
+    x0s = [W.initial_state(c, seed=i) for i, c in enumerate(robots)]
+    pool = int(args.budget_gb * (1 << 30))
+    srv = mtp.Server(robots, pool_bytes=pool, iters_per_launch=1, max_inflight=2, device=dev)
+    work = {i: c.n_samples * c.horizon * c.n_iters for i, c in enumerate(robots)}
+    # warm up: one request per robot
+    for i in range(len(robots)):
+        srv.submit(i, x0s[i], shift=0)
+    n = 0
+    while n < len(robots):
+        srv.pump(wait_us=1000)
+        n += len(srv.poll())
+    results = []
+    for rate in args.rate:
+        rng = np.random.Generator(np.random.PCG64(0))
+        warm, dur = 2.0, float(args.duration)
+        n_req = int(rate * (warm + dur) * 1.2) + 16
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        t_rel = np.cumsum(gaps)
+        t_rel = t_rel[t_rel < warm + dur]
+        who = rng.integers(0, len(robots), size=len(t_rel))
+        t0 = srv.now_ns() + 1_000_000
+        arrivals = (t0 + (t_rel * 1e9)).astype(np.int64)
+        i_next = 0
+        done = []
+        print(f"[bench] serving {rate:.0f} req/s for {warm + dur:.0f} s ({len(arrivals)} requests)",
+              file=sys.stderr, flush=True)
+        t_stop = t0 + int((warm + dur) * 1e9)
+        last_print = t0
+        while True:
+            now = srv.now_ns()
+            while i_next < len(arrivals) and arrivals[i_next] <= now:
+                srv.submit(int(who[i_next]), x0s[int(who[i_next])], shift=1, t_arrival_ns=int(arrivals[i_next]))
+                i_next += 1
+            srv.pump(wait_us=200)
+            done += srv.poll()
+            if now - last_print > 2_000_000_000:
+                st = srv.stats()
+                print(f"[bench]   t={(now - t0) / 1e9:5.1f}s done={len(done)} queued={st['queued']} "
+                      f"in_flight={st['in_flight']}", file=sys.stderr, flush=True)
+                last_print = now
+            if now >= t_stop:
+                break
+        st = srv.stats()
+        meas = [d for d in done if d["t_arrival_ns"] >= t0 + int(warm * 1e9)]
+        lat = np.array([(d["t_done_ns"] - d["t_arrival_ns"]) / 1e6 for d in meas]) if meas else np.array([np.nan])
+        t_lo, t_hi = t0 + int(warm * 1e9), t_stop
+        completed_in_window = [d for d in done if t_lo <= d["t_done_ns"] <= t_hi]
+        rps = len(completed_in_window) / dur
+        steps = sum(work[d["robot"]] for d in completed_in_window) / dur
+        results.append({"offered_req_per_s": rate, "replans_per_s": rps, "rollout_steps_per_s": steps,
+                        "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+                        "completed_measured": len(meas), "queued_at_end": st["queued"],
+                        "pool_peak_gb": st["pool_peak"] / (1 << 30)})
+        # drain what is left before the next rate
+        while srv.stats()["queued"] + srv.stats()["in_flight"] > 0:
+            srv.pump(wait_us=1000)
+            srv.poll()
+    main_r = results[0]
+    out = {
+        "metric": METRIC, "value": main_r["rollout_steps_per_s"], "unit": "rollout steps/s", "n_gpus": 1,
+        "steps": len(args.rate), "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serve512", "robots": len(robots), "budget_gb": args.budget_gb,
+                   "iters_per_launch": 1, "max_inflight": 2, "duration_s": args.duration},
+        "replans_per_s": main_r["replans_per_s"], "latency_ms_p50": main_r["latency_ms_p50"],
+        "latency_ms_p99": main_r["latency_ms_p99"], "load_sweep": results,
+        "resident_mb": srv.stats()["resident_bytes"] / (1 << 20),
+    }
+    srv.close()
     print(json.dumps(out), flush=True)
 
 

@@ -248,6 +248,66 @@ mtp_status mtp_batch_set_graph_mode(mtp_batch* b, int32_t use_graph);
 mtp_status mtp_batch_destroy(mtp_batch* b);
 const char* mtp_batch_last_error(const mtp_batch* b);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop for many robots.  Each robot has a fixed config and keeps its
+ * warm-start mean/std, start state, tables and replan counter resident on the
+ * device.  A request (robot, x0, shift) waits in an arrival-ordered queue; it is
+ * admitted when its robot has no request in flight and a transient slab (graph,
+ * paths, candidates, costs, elites) fits in the device-memory pool, whose size is
+ * the HBM budget.  Admitted requests run as continuous batches: every launch is
+ * one persistent batched launch that advances each admitted request by up to
+ * iters_per_launch CEM iterations from wherever it stands, so requests that
+ * arrive while others are on the GPU join at the next iteration boundary.  Up
+ * to max_inflight launches are queued on the stream ahead of the GPU.  A
+ * request's result is bit-identical to the same replan run alone.
+ *
+ * Threading: submit, poll and stats may be called from any thread; pump from
+ * one thread at a time.  Clock: mtp_server_now_ns (steady, nanoseconds). */
+typedef struct mtp_server mtp_server;
+
+typedef struct {
+  uint64_t ticket;
+  int32_t robot;
+  int32_t status;            /* MTP_OK, or MTP_ERR_DEVICE if its launch failed */
+  uint64_t t_arrival_ns;     /* as given to submit */
+  uint64_t t_admit_ns;       /* when a slab was granted */
+  uint64_t t_done_ns;        /* when pump saw the result on the host */
+  uint32_t replan_idx;       /* the robot's replan counter used */
+  int32_t n;                 /* valid entries of u (ctrl_dim <= 32) */
+  float u[32];
+} mtp_completion;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, launches, deferred_for_budget;
+  uint64_t pool_bytes, pool_in_use, pool_peak, resident_bytes;
+  int32_t queued, in_flight;
+} mtp_server_stats;
+
+size_t mtp_server_workspace_bytes(const mtp_config* robots, int32_t n_robots, size_t pool_bytes,
+                                  int32_t iters_per_launch);
+mtp_status mtp_server_create(const mtp_config* robots, int32_t n_robots, void* d_workspace, size_t ws_bytes,
+                             size_t pool_bytes, int32_t iters_per_launch, int32_t max_inflight, void* hip_stream,
+                             mtp_server** out);
+/* Same scheduler driving a host-only stand-in for the device (no GPU needed): a
+ * launch takes 20 us plus ns_per_sample_step per candidate-step it advances and
+ * returns zero actions.  For testing admission, budget and batching logic. */
+mtp_status mtp_server_create_simulated(const mtp_config* robots, int32_t n_robots, size_t pool_bytes,
+                                       int32_t iters_per_launch, int32_t max_inflight, double ns_per_sample_step,
+                                       mtp_server** out);
+/* Queue a replan of `robot` from host state h_x0 (state_dim floats, copied). */
+mtp_status mtp_server_submit(mtp_server* s, int32_t robot, const float* h_x0, int32_t shift,
+                             uint64_t t_arrival_ns, uint64_t* ticket);
+/* One scheduling round: retire finished launches (their completed requests become
+ * pollable and free their slabs), admit waiting requests, enqueue the next launch if
+ * there is work and room.  If wait_us > 0 and nothing could be retired, block up to
+ * wait_us for the oldest launch first. */
+mtp_status mtp_server_pump(mtp_server* s, int32_t wait_us, int32_t* n_completed);
+mtp_status mtp_server_poll(mtp_server* s, mtp_completion* out, int32_t max, int32_t* n_out);
+mtp_status mtp_server_get_stats(const mtp_server* s, mtp_server_stats* out);
+uint64_t mtp_server_now_ns(void);
+mtp_status mtp_server_destroy(mtp_server* s);
+const char* mtp_server_last_error(const mtp_server* s);
+
 /* Chain lengths the rollout kernel is instantiated for (writes up to `cap`, returns the count). */
 int32_t mtp_supported_chain_links(int32_t* out, int32_t cap);
 

@@ -95,6 +95,17 @@ def load():
         "mtp_batch_set_graph_mode": (c_int32, [P, c_int32]),
         "mtp_batch_destroy": (c_int32, [P]),
         "mtp_batch_last_error": (c_char_p, [P]),
+        "mtp_server_workspace_bytes": (c_size_t, [P, c_int32, c_size_t, c_int32]),
+        "mtp_server_create": (c_int32, [P, c_int32, P, c_size_t, c_size_t, c_int32, c_int32, P, POINTER(P)]),
+        "mtp_server_create_simulated": (c_int32, [P, c_int32, c_size_t, c_int32, c_int32, ctypes.c_double,
+                                                  POINTER(P)]),
+        "mtp_server_submit": (c_int32, [P, c_int32, P, c_int32, c_uint64, POINTER(c_uint64)]),
+        "mtp_server_pump": (c_int32, [P, c_int32, POINTER(c_int32)]),
+        "mtp_server_poll": (c_int32, [P, P, c_int32, POINTER(c_int32)]),
+        "mtp_server_get_stats": (c_int32, [P, P]),
+        "mtp_server_now_ns": (c_uint64, []),
+        "mtp_server_destroy": (c_int32, [P]),
+        "mtp_server_last_error": (c_char_p, [P]),
         "mtp_get_stage_times": (c_int32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -445,5 +456,100 @@ class Batch:
         return int(choice[0]), int(choice[1]), float(ms.value)
 
 
+class mtp_completion(ctypes.Structure):
+    _fields_ = [("ticket", c_uint64), ("robot", c_int32), ("status", c_int32), ("t_arrival_ns", c_uint64),
+                ("t_admit_ns", c_uint64), ("t_done_ns", c_uint64), ("replan_idx", c_uint32), ("n", c_int32),
+                ("u", c_float * 32)]
+
+
+class mtp_server_stats(ctypes.Structure):
+    _fields_ = [(name, c_uint64) for name in
+                ("submitted", "admitted", "completed", "launches", "deferred_for_budget", "pool_bytes",
+                 "pool_in_use", "pool_peak", "resident_bytes")] + [("queued", c_int32), ("in_flight", c_int32)]
+
+
 class Server:
-    pass
+    """Continuous-batching request loop over many robots (mtp_server).
+
+    simulated=True drives the same scheduler with a host-only stand-in for the
+    device (no GPU, zero actions, synthetic launch times)."""
+
+    def __init__(self, robots, pool_bytes, iters_per_launch=1, max_inflight=2, device="cuda",
+                 simulated=False, ns_per_sample_step=0.0):
+        self.lib = load()
+        self.cfgs = list(robots)
+        self.n = len(self.cfgs)
+        structs = [config_struct(c) for c in self.cfgs]
+        self._keep = [k for _, k in structs]
+        self._arr = (mtp_config * self.n)(*[c for c, _ in structs])
+        h = c_void_p()
+        self.workspace = None
+        if simulated:
+            st = self.lib.mtp_server_create_simulated(self._arr, self.n, int(pool_bytes), int(iters_per_launch),
+                                                      int(max_inflight), float(ns_per_sample_step), byref(h))
+        else:
+            torch = _torch()
+            nbytes = int(self.lib.mtp_server_workspace_bytes(self._arr, self.n, int(pool_bytes),
+                                                             int(iters_per_launch)))
+            if nbytes == 0:
+                raise MtpError(1, "server workspace size: invalid robots or pool")
+            self.device = torch.device(device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+            st = self.lib.mtp_server_create(self._arr, self.n, c_void_p(self.workspace.data_ptr()), nbytes,
+                                            int(pool_bytes), int(iters_per_launch), int(max_inflight),
+                                            c_void_p(self.stream.cuda_stream), byref(h))
+        _check(self.lib, st)
+        self.handle = h
+        self._buf = (mtp_completion * 1024)()
+
+    def _err(self, st):
+        if st != 0:
+            raise MtpError(st, self.lib.mtp_status_str(st).decode() + ": " +
+                           self.lib.mtp_server_last_error(self.handle).decode())
+
+    def now_ns(self):
+        return int(self.lib.mtp_server_now_ns())
+
+    def submit(self, robot, x0, shift=1, t_arrival_ns=None):
+        x = np.ascontiguousarray(np.asarray(x0, np.float32))
+        t = self.now_ns() if t_arrival_ns is None else int(t_arrival_ns)
+        tk = c_uint64()
+        self._err(self.lib.mtp_server_submit(self.handle, int(robot), x.ctypes.data_as(c_void_p), int(shift), t,
+                                             byref(tk)))
+        return int(tk.value)
+
+    def pump(self, wait_us=0):
+        n = c_int32()
+        self._err(self.lib.mtp_server_pump(self.handle, int(wait_us), byref(n)))
+        return int(n.value)
+
+    def poll(self):
+        out = []
+        while True:
+            n = c_int32()
+            self._err(self.lib.mtp_server_poll(self.handle, self._buf, 1024, byref(n)))
+            for i in range(n.value):
+                c = self._buf[i]
+                out.append(dict(ticket=int(c.ticket), robot=int(c.robot), status=int(c.status),
+                                t_arrival_ns=int(c.t_arrival_ns), t_admit_ns=int(c.t_admit_ns),
+                                t_done_ns=int(c.t_done_ns), replan_idx=int(c.replan_idx),
+                                u=np.array(c.u[:c.n], np.float32)))
+            if n.value < 1024:
+                return out
+
+    def stats(self):
+        st = mtp_server_stats()
+        self._err(self.lib.mtp_server_get_stats(self.handle, byref(st)))
+        return {name: getattr(st, name) for name, _ in mtp_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.mtp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

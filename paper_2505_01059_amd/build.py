@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmtp.so")
 
-SOURCES = ["kernels.hip", "plan.cpp", "batch.hip", "batch.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "batch.hip", "batch.cpp", "server.cpp"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off: plain float code only

@@ -44,10 +44,12 @@ struct BatchLayout {
   std::vector<Layout> lays;
   uint32_t capacity;
   int32_t x0_total, act_total;
+  size_t pool, pool_bytes;   // pooled mode: transient slabs are lent from [pool, pool + pool_bytes)
   size_t total;
 };
 
-bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string* why, mtp_status* code) {
+bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string* why, mtp_status* code,
+                  size_t pool_bytes = 0, int max_iters_per_launch = 0) {
   if (cfgs == nullptr || n < 1 || n > 65536) {
     if (why) *why = "need 1..65536 configs";
     if (code) *code = MTP_ERR_INVALID_ARG;
@@ -64,7 +66,8 @@ bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string
       return false;
     }
     L->lays.push_back(compute_layout(cfgs[i]));
-    L->capacity += items_for(cfgs[i], 0, cfgs[i].n_iters);
+    const int k_cap = max_iters_per_launch > 0 ? std::min(max_iters_per_launch, cfgs[i].n_iters) : cfgs[i].n_iters;
+    L->capacity += items_for(cfgs[i], 0, k_cap);
     L->x0_total += cfgs[i].state_dim;
     L->act_total += cfgs[i].ctrl_dim;
   }
@@ -82,8 +85,10 @@ bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string
   L->tr.resize(n);
   for (int i = 0; i < n; ++i) {
     L->res[i] = take(L->lays[i].resident);
-    L->tr[i] = take(L->lays[i].transient);
+    L->tr[i] = pool_bytes > 0 ? 0 : take(L->lays[i].transient);
   }
+  L->pool = pool_bytes > 0 ? take(pool_bytes) : 0;
+  L->pool_bytes = pool_bytes;
   L->total = off;
   return true;
 }
@@ -122,6 +127,9 @@ struct mtp_batch {
   hipGraphExec_t exec = nullptr;
   int last_active = 0;
   uint32_t next_r = 0;
+  bool pooled = false;
+  bool descs_dirty = false;
+  PlanDesc* h_descs = nullptr;   // pinned staging of the descriptor table (pooled mode)
   bool sticky = false;
   std::string err;
 };
@@ -184,6 +192,15 @@ static mtp_status ensure_graph(mtp_batch* b) {
 // Stage per-launch parameters (pinned -> device) and run one persistent launch.
 static mtp_status run_launch(mtp_batch* b, int32_t n_active, uint32_t total, const float* d_x0) {
   if (b->staged_pending) BCHK(b, hipEventSynchronize(b->staged), "staging wait");
+  if (b->descs_dirty) {
+    if (b->h_descs == nullptr)
+      BCHK(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_descs), sizeof(PlanDesc) * b->n, hipHostMallocDefault),
+           "desc staging");
+    std::memcpy(b->h_descs, b->descs.data(), sizeof(PlanDesc) * b->n);
+    BCHK(b, hipMemcpyAsync(b->d_descs, b->h_descs, sizeof(PlanDesc) * b->n, hipMemcpyHostToDevice, b->stream),
+         "desc copy");
+    b->descs_dirty = false;
+  }
   BCHK(b, hipMemcpyAsync(b->d_ictl, b->h_ictl, sizeof(InstCtl) * b->n, hipMemcpyHostToDevice, b->stream), "ictl copy");
   BCHK(b, hipMemcpyAsync(b->d_order, b->h_order, sizeof(int32_t) * n_active, hipMemcpyHostToDevice, b->stream),
        "order copy");
@@ -225,14 +242,26 @@ size_t mtp_batch_workspace_bytes(const mtp_config* cfgs, int32_t n) {
   return L.total;
 }
 
-mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes, void* hip_stream,
-                            mtp_batch** out) {
+}  // extern "C"
+
+size_t mtp::batch_workspace_bytes_pooled(const mtp_config* cfgs, int32_t n, size_t pool_bytes, int max_iters) {
+  BatchLayout L;
+  if (!batch_layout(cfgs, n, &L, nullptr, nullptr, pool_bytes, max_iters)) return 0;
+  return L.total;
+}
+
+mtp_status mtp::batch_create_internal(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes,
+                                      void* hip_stream, size_t pool_bytes, int max_iters, mtp_batch** out,
+                                      std::string* why_out) {
   if (out == nullptr) return MTP_ERR_INVALID_ARG;
   *out = nullptr;
   BatchLayout lay;
   std::string why;
   mtp_status code = MTP_OK;
-  if (!batch_layout(cfgs, n, &lay, &why, &code)) return code;
+  if (!batch_layout(cfgs, n, &lay, &why, &code, pool_bytes, max_iters)) {
+    if (why_out) *why_out = why;
+    return code;
+  }
   if (d_workspace == nullptr || ws_bytes < lay.total || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
     return MTP_ERR_WORKSPACE;
   mtp_batch* b = new (std::nothrow) mtp_batch();
@@ -256,8 +285,9 @@ mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace
     } else {
       c.sample_params = nullptr;
     }
-    b->descs[i] = make_desc(c, lay.lays[i], b->base + lay.res[i], b->base + lay.tr[i]);
+    b->descs[i] = make_desc(c, lay.lays[i], b->base + lay.res[i], pool_bytes > 0 ? nullptr : b->base + lay.tr[i]);
   }
+  b->pooled = pool_bytes > 0;
   b->d_ctl = reinterpret_cast<BatchCtl*>(b->base + lay.ctl);
   b->d_descs = reinterpret_cast<PlanDesc*>(b->base + lay.descs);
   b->d_ictl = reinterpret_cast<InstCtl*>(b->base + lay.ictl);
@@ -315,6 +345,37 @@ mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace
   return MTP_OK;
 }
 
+uint8_t* mtp::batch_pool_base(mtp_batch* b) { return b->base + b->lay.pool; }
+size_t mtp::batch_transient_bytes(const mtp_batch* b, int i) { return b->lay.lays[i].transient; }
+size_t mtp::batch_resident_bytes(const mtp_batch* b) {
+  size_t s = 0;
+  for (const auto& L : b->lay.lays) s += L.resident;
+  return s;
+}
+
+void mtp::batch_set_transient(mtp_batch* b, int i, uint8_t* base) {
+  set_transient(&b->descs[i], b->cfgs[i], b->lay.lays[i], base);
+  b->descs_dirty = true;
+}
+
+mtp_status mtp::batch_enqueue_readback(mtp_batch* b, float* h_dst, hipEvent_t done) {
+  const size_t bytes = sizeof(float) * (b->lay.act_total + 4);
+  BCHK(b, hipMemcpyAsync(h_dst, b->d_out, bytes, hipMemcpyDeviceToHost, b->stream), "readback");
+  BCHK(b, hipEventRecord(done, b->stream), "event");
+  return MTP_OK;
+}
+
+int mtp::batch_act_total(const mtp_batch* b) { return b->lay.act_total; }
+const char* mtp::batch_error(const mtp_batch* b) { return b->err.c_str(); }
+hipStream_t mtp::batch_stream(const mtp_batch* b) { return b->stream; }
+
+extern "C" {
+
+mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                            mtp_batch** out) {
+  return batch_create_internal(cfgs, n, d_workspace, ws_bytes, hip_stream, 0, 0, out, nullptr);
+}
+
 mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_active, const int32_t* h_k_begin,
                           const int32_t* h_k_end, const int32_t* h_shift, const uint32_t* h_r,
                           const float* d_x0_packed) {
@@ -353,6 +414,10 @@ mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_activ
       return MTP_ERR_INVALID_ARG;
     }
     seen[i] = 1;
+    if (b->descs[i].U == nullptr) {
+      b->err = "instance has no transient workspace assigned";
+      return MTP_ERR_INVALID_ARG;
+    }
     const int kb = h_k_begin[a], ke = h_k_end[a];
     if (kb < 0 || ke <= kb || ke > 65535) {
       b->err = "bad iteration range";
@@ -512,6 +577,7 @@ mtp_status mtp_batch_destroy(mtp_batch* b) {
   if (b->h_ictl) (void)hipHostFree(b->h_ictl);
   if (b->h_order) (void)hipHostFree(b->h_order);
   if (b->h_out) (void)hipHostFree(b->h_out);
+  if (b->h_descs) (void)hipHostFree(b->h_descs);
   delete b;
   return MTP_OK;
 }

@@ -1,6 +1,9 @@
 // Persistent batched launch: queue items, control blocks and host launchers.
 #pragma once
 
+#include <string>
+
+#include "../../include/mtp.h"
 #include "mtp_device.hpp"
 
 namespace mtp {
@@ -53,6 +56,26 @@ hipError_t launch_batch_prepare(const BatchLaunch& L, hipStream_t st);
 hipError_t launch_batch_persistent(const BatchLaunch& L, int grid, hipStream_t st);
 hipError_t launch_batch_pack(const BatchLaunch& L, float* out, int32_t n_inst, int32_t status_off, hipStream_t st);
 int batch_max_blocks_per_cu();
+
+}  // namespace mtp
+
+struct mtp_batch;
+
+namespace mtp {
+
+// Internal batch API used by the server (pooled transient workspaces).
+size_t batch_workspace_bytes_pooled(const mtp_config* cfgs, int32_t n, size_t pool_bytes, int max_iters);
+mtp_status batch_create_internal(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes,
+                                 void* hip_stream, size_t pool_bytes, int max_iters, mtp_batch** out,
+                                 std::string* why);
+uint8_t* batch_pool_base(mtp_batch* b);
+size_t batch_transient_bytes(const mtp_batch* b, int i);
+size_t batch_resident_bytes(const mtp_batch* b);
+void batch_set_transient(mtp_batch* b, int i, uint8_t* base);
+mtp_status batch_enqueue_readback(mtp_batch* b, float* h_dst, hipEvent_t done);
+int batch_act_total(const mtp_batch* b);
+const char* batch_error(const mtp_batch* b);
+hipStream_t batch_stream(const mtp_batch* b);
 
 // host mirror of the per-phase tile counts
 inline uint32_t host_phase_tiles(int B, int T, int n, uint32_t phase) {
