@@ -302,27 +302,57 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
 // O(n) work, no n x n matrix, same equations of motion as the Lagrangian form.
 template <int N>
 struct ChainConsts {
-  float l[N], invl[N], im[N];
+  float l[N], invl[N];
+  float im[N];                      // inverse masses (per sample with contact)
   float g, wg, wu, tx, ty;
   float yg, kc, dc, inv_vs, muf;   // contact only
 };
 
+// Long chains recompute per-link products instead of keeping them, to stay
+// within the register file.
+template <int N>
+struct ChainLean {
+  static constexpr bool value = N > 12;
+};
+
+// tanh from the hardware base-2 exponential: 1 - 2 / (1 + e^{2x}); saturates
+// to +-1 without overflow trouble.
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);   // e^{2x}
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// (u_k - u_{k+1}) / l_k: torque difference across link k over its length
+template <int N>
+__device__ __forceinline__ float chain_q(const float (&u)[N], const ChainConsts<N>& K, int k) {
+  return (u[k] - ((k + 1 < N) ? u[k + 1] : 0.0f)) * K.invl[k];
+}
+
 template <int N, bool CONTACT>
 __device__ __forceinline__ void chain_accel(const float (&s)[N], const float (&c)[N], const float (&om)[N],
-                                            const float (&q)[N], const ChainConsts<N>& K, float (&acc)[N]) {
-  float cp[N], dp[N], Cn[N], Sn[N], ndf[N];
+                                            const float (&u)[N], const ChainConsts<N>& K, float (&acc)[N]) {
+  constexpr bool lean = ChainLean<N>::value;
+  float cp[N], dp[N];
+  float ndf[CONTACT ? N : 1];
+  float qs[lean ? 1 : N], Cs[lean ? 1 : N], Ss[lean ? 1 : N];
   float im_prev = 0.0f, Cn_prev = 0.0f, Sn_prev = 0.0f, cp_prev = 0.0f, dp_prev = 0.0f;
   float fx_prev = 0.0f, fy_prev = 0.0f;
   float px = 0.0f, py = 0.0f, vx = 0.0f, vy = 0.0f;
+  float q_prev = 0.0f;
+  float qk = chain_q<N>(u, K, 0);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    float Cnk = 0.0f, Snk = 0.0f;
+    float Cnk = 0.0f, Snk = 0.0f, qn = 0.0f;
     if (k + 1 < N) {
       Cnk = fmaf(c[k], c[k + 1], s[k] * s[k + 1]);   // cos(phi_k - phi_{k+1})
       Snk = fmaf(s[k], c[k + 1], -c[k] * s[k + 1]);  // sin(phi_k - phi_{k+1})
+      qn = chain_q<N>(u, K, k + 1);
     }
-    Cn[k] = Cnk;
-    Sn[k] = Snk;
+    if constexpr (!lean) {
+      Cs[k] = Cnk;
+      Ss[k] = Snk;
+      qs[k] = qk;
+    }
     const float imk = K.im[k];
     float dfx, dfy;   // change of the non-constraint acceleration from mass k-1 to mass k
     if constexpr (CONTACT) {
@@ -335,7 +365,7 @@ __device__ __forceinline__ void chain_accel(const float (&s)[N], const float (&c
       float fx = 0.0f, fy = 0.0f;
       if (pen > 0.0f) {
         const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vy), 0.0f);
-        const float ft = -K.muf * fn * tanhf(vx * K.inv_vs);
+        const float ft = -K.muf * fn * fast_tanh(vx * K.inv_vs);
         fx = ft * imk;
         fy = fn * imk;
       }
@@ -344,12 +374,11 @@ __device__ __forceinline__ void chain_accel(const float (&s)[N], const float (&c
       fx_prev = fx;
       fy_prev = fy;
       if (k == 0) dfy -= K.g;
+      ndf[k] = fmaf(c[k], dfx, s[k] * dfy);
     } else {
       dfx = 0.0f;
       dfy = (k == 0) ? -K.g : 0.0f;
     }
-    const float qn = (k + 1 < N) ? q[k + 1] : 0.0f;
-    const float qp = (k > 0) ? q[k - 1] : 0.0f;
     const float D = imk + im_prev;
     const float Up = -imk * Cnk;
     const float Lo = -im_prev * Cn_prev;
@@ -357,34 +386,54 @@ __device__ __forceinline__ void chain_accel(const float (&s)[N], const float (&c
     rhs = fmaf(s[k], dfx, rhs);
     rhs = fmaf(-c[k], dfy, rhs);
     rhs = fmaf(-imk * qn, Snk, rhs);
-    rhs = fmaf(im_prev * qp, Sn_prev, rhs);
+    rhs = fmaf(im_prev * q_prev, Sn_prev, rhs);
     const float inv = __builtin_amdgcn_rcpf(fmaf(-Lo, cp_prev, D));
     cp_prev = Up * inv;
     dp_prev = fmaf(-Lo, dp_prev, rhs) * inv;
     cp[k] = cp_prev;
     dp[k] = dp_prev;
-    ndf[k] = fmaf(c[k], dfx, s[k] * dfy);
     im_prev = imk;
     Cn_prev = Cnk;
     Sn_prev = Snk;
+    q_prev = qk;
+    qk = qn;
   }
   // back substitution: dp[k] becomes the tension of link k
 #pragma unroll
   for (int k = N - 2; k >= 0; --k) dp[k] = fmaf(-cp[k], dp[k + 1], dp[k]);
+  // link accelerations
+  float Cp = 0.0f, Sp = 0.0f, qp = 0.0f;
+  float qc = lean ? chain_q<N>(u, K, 0) : qs[0];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
+    float Cn = 0.0f, Sn = 0.0f, qn = 0.0f;
+    if (k + 1 < N) {
+      if constexpr (lean) {
+        Cn = fmaf(c[k], c[k + 1], s[k] * s[k + 1]);
+        Sn = fmaf(s[k], c[k + 1], -c[k] * s[k + 1]);
+        qn = chain_q<N>(u, K, k + 1);
+      } else {
+        Cn = Cs[k];
+        Sn = Ss[k];
+        qn = qs[k + 1];
+      }
+    }
     const float Tn = (k + 1 < N) ? dp[k + 1] : 0.0f;
     const float Tp = (k > 0) ? dp[k - 1] : 0.0f;
-    const float qn = (k + 1 < N) ? q[k + 1] : 0.0f;
-    const float qp = (k > 0) ? q[k - 1] : 0.0f;
     const float imp = (k > 0) ? K.im[k - 1] : 0.0f;
-    const float Cp = (k > 0) ? Cn[k - 1] : 0.0f;
-    const float Sp = (k > 0) ? Sn[k - 1] : 0.0f;
-    float a = (K.im[k] + imp) * q[k];
-    a = fmaf(-K.im[k], fmaf(Tn, Sn[k], qn * Cn[k]), a);
+    float a = (K.im[k] + imp) * qc;
+    a = fmaf(-K.im[k], fmaf(Tn, Sn, qn * Cn), a);
     a = fmaf(-imp, fmaf(-Tp, Sp, qp * Cp), a);
-    a += ndf[k];
+    if constexpr (CONTACT) {
+      a += ndf[k];
+    } else {
+      if (k == 0) a = fmaf(-K.g, s[0], a);
+    }
     acc[k] = a * K.invl[k];
+    Cp = Cn;
+    Sp = Sn;
+    qp = qc;
+    qc = qn;
   }
 }
 
@@ -429,56 +478,38 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     const bool more = (t + 1 < P.T);
 #pragma unroll
     for (int k = 0; k < N; ++k) un[k] = more ? ub[((t + 1) * N + k) * ld] : 0.0f;
-    float q[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) q[k] = (u[k] - ((k + 1 < N) ? u[k + 1] : 0.0f)) * K.invl[k];
 
-    float a[N], aph[N], aom[N], sph[N], som[N];
-    // stage 1
-    chain_accel<N, CONTACT>(s, c, om, q, K, a);
+    // classical RK4 with the control held: stage s evaluates at
+    // phi_s = phi + c_s dt omega_{s-1},  omega_s = omega + c_s dt k_{s-1}
+    float kk[N], oms[N], aph[N], aom[N];
+    chain_accel<N, CONTACT>(s, c, om, u, K, kk);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      aph[k] = om[k]; aom[k] = a[k];
-      sph[k] = fmaf(hdt, om[k], ph[k]); som[k] = fmaf(hdt, a[k], om[k]);
+      aph[k] = om[k];
+      aom[k] = kk[k];
+      oms[k] = om[k];
     }
-    // stage 2
-    {
+#pragma unroll 1
+    for (int stage = 1; stage < 4; ++stage) {
+      const float h = (stage == 3) ? dt : hdt;
       float s2[N], c2[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) hw_sincos(sph[k], &s2[k], &c2[k]);
-      chain_accel<N, CONTACT>(s2, c2, som, q, K, a);
+      for (int k = 0; k < N; ++k) {
+        hw_sincos(fmaf(h, oms[k], ph[k]), &s2[k], &c2[k]);
+        oms[k] = fmaf(h, kk[k], om[k]);
+      }
+      chain_accel<N, CONTACT>(s2, c2, oms, u, K, kk);
+      const float wgt = (stage == 3) ? 1.0f : 2.0f;
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        aph[k] = fmaf(2.0f, som[k], aph[k]); aom[k] = fmaf(2.0f, a[k], aom[k]);
-        const float w = som[k];
-        sph[k] = fmaf(hdt, w, ph[k]); som[k] = fmaf(hdt, a[k], om[k]);
+        aph[k] = fmaf(wgt, oms[k], aph[k]);
+        aom[k] = fmaf(wgt, kk[k], aom[k]);
       }
     }
-    // stage 3
-    {
-      float s3[N], c3[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) hw_sincos(sph[k], &s3[k], &c3[k]);
-      chain_accel<N, CONTACT>(s3, c3, som, q, K, a);
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        aph[k] = fmaf(2.0f, som[k], aph[k]); aom[k] = fmaf(2.0f, a[k], aom[k]);
-        const float w = som[k];
-        sph[k] = fmaf(dt, w, ph[k]); som[k] = fmaf(dt, a[k], om[k]);
-      }
-    }
-    // stage 4
-    {
-      float s4[N], c4[N];
-#pragma unroll
-      for (int k = 0; k < N; ++k) hw_sincos(sph[k], &s4[k], &c4[k]);
-      chain_accel<N, CONTACT>(s4, c4, som, q, K, a);
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        aph[k] += som[k]; aom[k] += a[k];
-        ph[k] = fmaf(dt6, aph[k], ph[k]);
-        om[k] = fmaf(dt6, aom[k], om[k]);
-      }
+    for (int k = 0; k < N; ++k) {
+      ph[k] = fmaf(dt6, aph[k], ph[k]);
+      om[k] = fmaf(dt6, aom[k], om[k]);
     }
     // cost of the new state (its sin/cos also start the next step)
     float ex = 0.0f, ey = 0.0f, uu = 0.0f;
@@ -506,6 +537,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
   P.cost[b] = finite_or_inf(cost);
 }
 
+// ------------------------------------------------------------------ reductions
 __device__ __forceinline__ float wave_sum64(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
