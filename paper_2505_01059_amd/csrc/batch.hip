@@ -22,7 +22,10 @@ __device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phas
   switch (phase) {
     case kPhShift: return 1u;
     case kPhCand: return static_cast<uint32_t>((P.B + kCandThreads - 1) / kCandThreads);
-    case kPhRoll: return static_cast<uint32_t>((P.B + kBatchThreads - 1) / kBatchThreads);
+    case kPhRoll: {
+      const int per = is_quad_chain(P.dyn, P.n_links) ? kBatchThreads / 4 : kBatchThreads;
+      return static_cast<uint32_t>((P.B + per - 1) / per);
+    }
     case kPhTopk: return 1u;
     default: return static_cast<uint32_t>((P.T * P.n + kUpdOutputsPerTile - 1) / kUpdOutputsPerTile);
   }
@@ -49,6 +52,16 @@ __device__ __forceinline__ void run_rollout_tile(const PlanDesc& P, uint32_t til
     __syncthreads();
     if (b < P.B) rollout_point_mass(P, b, sm.pm);
     return;
+  }
+  if (is_quad_chain(P.dyn, P.n_links)) {
+    const int bq = static_cast<int>(tile) * (kBatchThreads / 4) + static_cast<int>(threadIdx.x >> 2);
+    if (bq >= P.B) return;
+    switch (P.n_links) {
+#define X(N) case N: if constexpr (quad_chain_links<N>()) rollout_chain_quad<N>(P, bq, threadIdx.x & 3); return;
+      MTP_CHAIN_LINKS(X)
+#undef X
+      default: return;
+    }
   }
   if (b >= P.B) return;
   if (P.dyn == kChain) {

@@ -78,11 +78,14 @@ const char* batch_error(const mtp_batch* b);
 hipStream_t batch_stream(const mtp_batch* b);
 
 // host mirror of the per-phase tile counts
-inline uint32_t host_phase_tiles(int B, int T, int n, uint32_t phase) {
+inline uint32_t host_phase_tiles(int B, int T, int n, uint32_t phase, bool quad) {
   switch (phase) {
     case kPhShift: return 1u;
     case kPhCand: return static_cast<uint32_t>((B + kCandThreads - 1) / kCandThreads);
-    case kPhRoll: return static_cast<uint32_t>((B + kBatchThreads - 1) / kBatchThreads);
+    case kPhRoll: {
+      const int per = quad ? kBatchThreads / 4 : kBatchThreads;
+      return static_cast<uint32_t>((B + per - 1) / per);
+    }
     case kPhTopk: return 1u;
     default: return static_cast<uint32_t>((T * n + kUpdOutputsPerTile - 1) / kUpdOutputsPerTile);
   }

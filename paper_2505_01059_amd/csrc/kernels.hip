@@ -31,6 +31,13 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_chain(PlanDesc P) {
   if (b < P.B) rollout_chain<N, CONTACT>(P, b);
 }
 
+template <int N>
+__global__ __launch_bounds__(kRollThreads) void k_rollout_chain_quad(PlanDesc P) {
+  const int g = blockIdx.x * kRollThreads + threadIdx.x;
+  const int b = g >> 2;
+  if (b < P.B) rollout_chain_quad<N>(P, b, g & 3);
+}
+
 __global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {
   __shared__ TopkSmem sm;
   topk_block<kTopkThreads>(P, sm);
@@ -74,6 +81,16 @@ static hipError_t launch_rollout(const PlanDesc& P, hipStream_t st) {
   if (P.dyn == kPointMass) {
     k_rollout_point_mass<<<grid, kRollThreads, 0, st>>>(P);
     return hipGetLastError();
+  }
+  if (is_quad_chain(P.dyn, P.n_links)) {
+    const dim3 qgrid((4 * P.B + kRollThreads - 1) / kRollThreads);
+    switch (P.n_links) {
+#define X(N) case N: if constexpr (quad_chain_links<N>()) { k_rollout_chain_quad<N><<<qgrid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+      MTP_CHAIN_LINKS(X)
+#undef X
+      default: break;
+    }
+    return hipErrorInvalidValue;
   }
   if (P.dyn == kChain) {
     switch (P.n_links) {

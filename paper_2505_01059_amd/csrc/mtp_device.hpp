@@ -110,10 +110,15 @@ __device__ __forceinline__ void hw_sincos(float x, float* s, float* c) {
 // The tile regenerates column j of the graph Z in LDS from Philox; the tile
 // holding the first tensor path also stores it to Z, and tiles of joint 0
 // store the path indices I.
+constexpr int kTChunk = 128;   // horizon steps whose tables are staged in LDS at a time
+
 struct CandSmem {
   float z[kMaxLayers * kMaxWidth];                // Z[l][w] for this joint
   float ctrl[kMaxLayers][kCandThreads];          // per-thread control points
   float slope[kMaxLayers][kCandThreads];         // per-thread Akima slopes (unit spacing)
+  float tb[kTChunk * kBasisStride];              // spline weights of the staged steps
+  int32_t ts[kTChunk];                           // their span / interval index
+  float tmu[kTChunk], tsg[kTChunk];              // mean and std of joint j at those steps
 };
 
 __device__ __forceinline__ void akima_slopes_thread(int L, int tid, CandSmem& sm) {
@@ -143,6 +148,7 @@ __device__ __forceinline__ void akima_slopes_thread(int L, int tid, CandSmem& sm
   }
 }
 
+// Every thread of the tile must call this (it synchronises the workgroup).
 __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, int j, int b0,
                                           CandSmem& sm) {
   const int tid = threadIdx.x;
@@ -153,6 +159,9 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
   const bool z_writer = tile_has_tensor && (b0 <= tens_lo);
   const float lo = P.u_min, hi = P.u_max;
   const size_t ld = static_cast<size_t>(P.ldU);
+  const bool live = b < P.B;
+  const bool is_local = live && b < G1;
+  const bool is_tensor = live && b >= tens_lo && b < tens_hi;
 
   if (tile_has_tensor) {
     const float span = hi - lo;
@@ -167,27 +176,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
     }
   }
   __syncthreads();
-  if (b >= P.B) return;
-
-  if (b < G1) {
-    // local sample g = b: u = clip(mu + sigma * eps)
-    const int Tq = (P.T + 3) >> 2;
-    for (int tq = 0; tq < Tq; ++tq) {
-      const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
-                              stream_c3(kTagEps, k), P.key0, P.key1);
-      float z[4];
-      box_muller(q.w[0], q.w[1], z[0], z[1]);
-      box_muller(q.w[2], q.w[3], z[2], z[3]);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int t = 4 * tq + c;
-        if (t < P.T) {
-          const int o = t * P.n + j;
-          P.U[o * ld + b] = clampf(fmaf(P.sigma[o], z[c], P.mu[o]), lo, hi);
-        }
-      }
-    }
-  } else if (b < tens_hi) {
+  if (is_tensor) {
     const int pp = b - G1;
     for (int l4 = 0; l4 < P.L; l4 += 4) {
       const Words4 q = philox(static_cast<uint32_t>(l4 >> 2), static_cast<uint32_t>(pp), r,
@@ -202,33 +191,62 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
         }
       }
     }
-    if (P.interp == kBspline) {
-      const int np1 = P.p + 1;
-      for (int t = 0; t < P.T; ++t) {
-        const int s0 = P.span[t];
-        const float* bw = P.basis + t * kBasisStride;
-        float v = 0.0f;
-        for (int q = 0; q < np1; ++q) v = fmaf(bw[q], sm.ctrl[s0 + q][tid], v);
-        P.U[(t * P.n + j) * ld + b] = clampf(v, lo, hi);
-      }
-    } else {
-      akima_slopes_thread(P.L, tid, sm);
-      for (int t = 0; t < P.T; ++t) {
-        const int i = P.span[t];
-        const float* h = P.basis + t * kBasisStride;
-        float v = h[0] * sm.ctrl[i][tid];
-        v = fmaf(h[1], sm.slope[i][tid], v);
-        v = fmaf(h[2], sm.ctrl[i + 1][tid], v);
-        v = fmaf(h[3], sm.slope[i + 1][tid], v);
-        P.U[(t * P.n + j) * ld + b] = clampf(v, lo, hi);
-      }
+    if (P.interp == kAkima) akima_slopes_thread(P.L, tid, sm);
+  }
+  const int Tq = (P.T + 3) >> 2;
+  for (int t0 = 0; t0 < P.T; t0 += kTChunk) {
+    const int tn = min(kTChunk, P.T - t0);
+    for (int i = tid; i < tn; i += kCandThreads) {
+      const int o = (t0 + i) * P.n + j;
+      sm.ts[i] = P.span[t0 + i];
+      sm.tmu[i] = P.mu[o];
+      sm.tsg[i] = P.sigma[o];
     }
-  } else {
-    // nominal mean
-    for (int t = 0; t < P.T; ++t) {
-      const int o = t * P.n + j;
-      P.U[o * ld + b] = clampf(P.mu[o], lo, hi);
+    for (int i = tid; i < tn * kBasisStride; i += kCandThreads) sm.tb[i] = P.basis[t0 * kBasisStride + i];
+    __syncthreads();
+    if (is_local) {
+      // local sample g = b: u = clip(mu + sigma * eps), four steps per Philox block
+      for (int tq = t0 >> 2; tq < ((t0 + tn + 3) >> 2); ++tq) {
+        const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
+                                stream_c3(kTagEps, k), P.key0, P.key1);
+        float z[4];
+        box_muller(q.w[0], q.w[1], z[0], z[1]);
+        box_muller(q.w[2], q.w[3], z[2], z[3]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int t = 4 * tq + c;
+          if (t < t0 + tn) {
+            const int i = t - t0;
+            P.U[(t * P.n + j) * ld + b] = clampf(fmaf(sm.tsg[i], z[c], sm.tmu[i]), lo, hi);
+          }
+        }
+      }
+    } else if (is_tensor) {
+      if (P.interp == kBspline) {
+        const int np1 = P.p + 1;
+        for (int i = 0; i < tn; ++i) {
+          const int s0 = sm.ts[i];
+          const float* bw = sm.tb + i * kBasisStride;
+          float v = 0.0f;
+          for (int q = 0; q < np1; ++q) v = fmaf(bw[q], sm.ctrl[s0 + q][tid], v);
+          P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
+        }
+      } else {
+        for (int i = 0; i < tn; ++i) {
+          const int iv = sm.ts[i];
+          const float* h = sm.tb + i * kBasisStride;
+          float v = h[0] * sm.ctrl[iv][tid];
+          v = fmaf(h[1], sm.slope[iv][tid], v);
+          v = fmaf(h[2], sm.ctrl[iv + 1][tid], v);
+          v = fmaf(h[3], sm.slope[iv + 1][tid], v);
+          P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
+        }
+      }
+    } else if (live) {
+      // nominal mean
+      for (int i = 0; i < tn; ++i) P.U[((t0 + i) * P.n + j) * ld + b] = clampf(sm.tmu[i], lo, hi);
     }
+    __syncthreads();
   }
 }
 
@@ -537,6 +555,202 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
   P.cost[b] = finite_or_inf(cost);
 }
 
+// ------------------------------------------------------------------ quad-lane chain
+// Chains of 5..8 links: four lanes share one candidate, each owning two
+// consecutive links (rows 2s and 2s+1 of the tension system; rows past the
+// chain end are identity rows).  The tridiagonal solve is one level of cyclic
+// reduction inside the lane (eliminating the even rows), a two-level parallel
+// cyclic reduction of the four odd rows across the quad, and back-substitution
+// of the even rows.  Cross-lane values move with quad-permute DPP, which never
+// leaves the four lanes of a candidate.  Four times as many lanes as the
+// one-lane form for the same candidates, at about 60% of its instructions per lane.
+
+constexpr int qperm_ctrl(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+constexpr int kQNext1 = qperm_ctrl(1, 2, 3, 3);
+constexpr int kQPrev1 = qperm_ctrl(0, 0, 1, 2);
+constexpr int kQNext2 = qperm_ctrl(2, 3, 2, 3);
+constexpr int kQPrev2 = qperm_ctrl(0, 1, 0, 1);
+constexpr int kQXor1 = qperm_ctrl(1, 0, 3, 2);
+constexpr int kQXor2 = qperm_ctrl(2, 3, 0, 1);
+
+template <int CTRL>
+__device__ __forceinline__ float qperm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float quad_sum(float v) {
+  v += qperm<kQXor1>(v);
+  return v + qperm<kQXor2>(v);
+}
+
+template <int N>
+constexpr bool quad_chain_links() { return N >= 5 && N <= 8; }
+
+__host__ __device__ constexpr bool is_quad_chain(int dyn, int n) { return dyn == kChain && n >= 5 && n <= 8; }
+
+struct QuadChain {
+  float l0, l1, invl0, invl1, im0, im1, imp;   // own links r0 = 2s, r1 = 2s+1; imp: link r0-1
+  bool v0, v1;                                  // rows inside the chain
+  bool nxt1;                                    // link r1+1 exists
+  int s;                                        // lane within the quad
+  float g;
+};
+
+// Accelerations of the lane's two links from the stage angles' sin/cos, the
+// stage angular velocities and the per-step torque terms
+// q0, q1 (own links), qp (link r0-1), qn (link r1+1).
+__device__ __forceinline__ void quad_accel(float s0, float c0, float s1, float c1, float w0, float w1, float q0,
+                                           float q1, float qp, float qn, const QuadChain& K, float& a0, float& a1) {
+  const int s = K.s;
+  const float sN = qperm<kQNext1>(s0), cN = qperm<kQNext1>(c0);
+  const float Cn0 = K.v1 ? fmaf(c0, c1, s0 * s1) : 0.0f;
+  const float Sn0 = K.v1 ? fmaf(s0, c1, -c0 * s1) : 0.0f;
+  const float Cn1 = K.nxt1 ? fmaf(c1, cN, s1 * sN) : 0.0f;
+  const float Sn1 = K.nxt1 ? fmaf(s1, cN, -c1 * sN) : 0.0f;
+  const float Cp0 = qperm<kQPrev1>(Cn1), Sp0 = qperm<kQPrev1>(Sn1);
+  const float Cp = (s > 0) ? Cp0 : 0.0f, Sp = (s > 0) ? Sp0 : 0.0f;   // link r0-1 against r0
+  // tension rows r0 (even) and r1 (odd): Lo x_{r-1} + D x_r + Up x_{r+1} = R
+  float De = K.im0 + K.imp, Ue = -K.im0 * Cn0, Le = -K.imp * Cp;
+  float Re = fmaf(K.l0 * w0, w0, fmaf(-K.im0 * q1, Sn0, K.imp * qp * Sp));
+  if (s == 0) Re = fmaf(K.g, c0, Re);
+  float Do = K.im1 + K.im0, Uo = -K.im1 * Cn1, Lo = -K.im0 * Cn0;
+  float Ro = fmaf(K.l1 * w1, w1, fmaf(-K.im1 * qn, Sn1, K.im0 * q0 * Sn0));
+  if (!K.v0) { De = 1.0f; Ue = 0.0f; Le = 0.0f; Re = 0.0f; }
+  if (!K.v1) { Do = 1.0f; Uo = 0.0f; Lo = 0.0f; Ro = 0.0f; }
+  // eliminate the even unknowns from the odd rows
+  const float iDe = __builtin_amdgcn_rcpf(De);
+  const float Le2 = qperm<kQNext1>(Le), iDe2 = qperm<kQNext1>(iDe), Ue2 = qperm<kQNext1>(Ue),
+              Re2 = qperm<kQNext1>(Re);
+  const float al = Lo * iDe;
+  const float ga = (s < 3) ? Uo * iDe2 : 0.0f;
+  float A = -al * Le;
+  float Bv = fmaf(-ga, Le2, fmaf(-al, Ue, Do));
+  float C = (s < 3) ? -ga * Ue2 : 0.0f;
+  float R = fmaf(-ga, Re2, fmaf(-al, Re, Ro));
+  // parallel cyclic reduction of the four odd rows, distance 1
+  {
+    const float iB = __builtin_amdgcn_rcpf(Bv);
+    const float Ap = qperm<kQPrev1>(A), iBp = qperm<kQPrev1>(iB), Cp1 = qperm<kQPrev1>(C), Rp = qperm<kQPrev1>(R);
+    const float An = qperm<kQNext1>(A), iBn = qperm<kQNext1>(iB), Cn = qperm<kQNext1>(C), Rn = qperm<kQNext1>(R);
+    const float x1 = (s > 0) ? -A * iBp : 0.0f;
+    const float y1 = (s < 3) ? -C * iBn : 0.0f;
+    Bv = fmaf(y1, An, fmaf(x1, Cp1, Bv));
+    R = fmaf(y1, Rn, fmaf(x1, Rp, R));
+    A = (s > 0) ? x1 * Ap : 0.0f;
+    C = (s < 3) ? y1 * Cn : 0.0f;
+  }
+  // distance 2
+  {
+    const float iB = __builtin_amdgcn_rcpf(Bv);
+    const float iBp = qperm<kQPrev2>(iB), Cp2 = qperm<kQPrev2>(C), Rp = qperm<kQPrev2>(R);
+    const float iBn = qperm<kQNext2>(iB), An = qperm<kQNext2>(A), Rn = qperm<kQNext2>(R);
+    const float x2 = (s >= 2) ? -A * iBp : 0.0f;
+    const float y2 = (s <= 1) ? -C * iBn : 0.0f;
+    Bv = fmaf(y2, An, fmaf(x2, Cp2, Bv));
+    R = fmaf(y2, Rn, fmaf(x2, Rp, R));
+  }
+  const float xo = R * __builtin_amdgcn_rcpf(Bv);              // tension of link r1
+  const float xop = qperm<kQPrev1>(xo);
+  const float xo_prev = (s > 0) ? xop : 0.0f;                   // tension of link r0-1
+  const float xe = fmaf(-Le, xo_prev, fmaf(-Ue, xo, Re)) * iDe; // tension of link r0
+  const float xen = qperm<kQNext1>(xe);
+  const float xe_next = (s < 3) ? xen : 0.0f;                   // tension of link r1+1
+  float A0 = (K.im0 + K.imp) * q0;
+  A0 = fmaf(-K.im0, fmaf(xo, Sn0, q1 * Cn0), A0);
+  A0 = fmaf(-K.imp, fmaf(-xo_prev, Sp, qp * Cp), A0);
+  if (s == 0) A0 = fmaf(-K.g, s0, A0);
+  float A1 = (K.im1 + K.im0) * q1;
+  A1 = fmaf(-K.im1, fmaf(xe_next, Sn1, qn * Cn1), A1);
+  A1 = fmaf(-K.im0, fmaf(-xe, Sn0, q0 * Cn0), A1);
+  a0 = K.v0 ? A0 * K.invl0 : 0.0f;
+  a1 = K.v1 ? A1 * K.invl1 : 0.0f;
+}
+
+// One candidate b per quad; s is the lane within the quad.  All four lanes of a
+// quad must run this together.
+template <int N>
+__device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int s) {
+  static_assert(N >= 5 && N <= 8, "quad-lane chain covers 5..8 links");
+  const float* tk = P.task;
+  QuadChain K;
+  K.s = s;
+  const int r0 = 2 * s, r1 = 2 * s + 1;
+  K.v0 = r0 < N;
+  K.v1 = r1 < N;
+  K.nxt1 = r1 + 1 < N;
+  K.g = tk[0];
+  const float wg = tk[1], wu = tk[2], tx = tk[3], ty = tk[4];
+  K.l0 = K.v0 ? tk[5 + N + r0] : 1.0f;
+  K.l1 = K.v1 ? tk[5 + N + r1] : 1.0f;
+  K.invl0 = 1.0f / K.l0;
+  K.invl1 = 1.0f / K.l1;
+  K.im0 = K.v0 ? 1.0f / tk[5 + r0] : 0.0f;
+  K.im1 = K.v1 ? 1.0f / tk[5 + r1] : 0.0f;
+  K.imp = (r0 > 0 && r0 - 1 < N) ? 1.0f / tk[5 + r0 - 1] : 0.0f;
+  const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
+  float ph0 = K.v0 ? P.x0[r0] : 0.0f, ph1 = K.v1 ? P.x0[r1] : 0.0f;
+  float om0 = K.v0 ? P.x0[N + r0] : 0.0f, om1 = K.v1 ? P.x0[N + r1] : 0.0f;
+  float s0, c0, s1, c1;
+  hw_sincos(ph0, &s0, &c0);
+  hw_sincos(ph1, &s1, &c1);
+  const size_t ld = static_cast<size_t>(P.ldU);
+  const float* ub = P.U + b;
+  float u0 = K.v0 ? ub[r0 * ld] : 0.0f, u1 = K.v1 ? ub[r1 * ld] : 0.0f;
+  float cost = 0.0f;
+  for (int t = 0; t < P.T; ++t) {
+    const bool more = (t + 1 < P.T);
+    const float un0 = (more && K.v0) ? ub[((t + 1) * N + r0) * ld] : 0.0f;
+    const float un1 = (more && K.v1) ? ub[((t + 1) * N + r1) * ld] : 0.0f;
+    // torque terms of this step
+    const float u0n = qperm<kQNext1>(u0);
+    const float q0 = (u0 - u1) * K.invl0;
+    const float q1 = (u1 - (K.nxt1 ? u0n : 0.0f)) * K.invl1;
+    const float qpv = qperm<kQPrev1>(q1), qnv = qperm<kQNext1>(q0);
+    const float qp = (s > 0) ? qpv : 0.0f, qn = (K.nxt1 && s < 3) ? qnv : 0.0f;
+
+    float k0, k1;
+    quad_accel(s0, c0, s1, c1, om0, om1, q0, q1, qp, qn, K, k0, k1);
+    float aph0 = om0, aph1 = om1, aom0 = k0, aom1 = k1, oms0 = om0, oms1 = om1;
+#pragma unroll 1
+    for (int stage = 1; stage < 4; ++stage) {
+      const float h = (stage == 3) ? dt : hdt;
+      float ss0, cc0, ss1, cc1;
+      hw_sincos(fmaf(h, oms0, ph0), &ss0, &cc0);
+      hw_sincos(fmaf(h, oms1, ph1), &ss1, &cc1);
+      oms0 = fmaf(h, k0, om0);
+      oms1 = fmaf(h, k1, om1);
+      quad_accel(ss0, cc0, ss1, cc1, oms0, oms1, q0, q1, qp, qn, K, k0, k1);
+      const float wgt = (stage == 3) ? 1.0f : 2.0f;
+      aph0 = fmaf(wgt, oms0, aph0);
+      aph1 = fmaf(wgt, oms1, aph1);
+      aom0 = fmaf(wgt, k0, aom0);
+      aom1 = fmaf(wgt, k1, aom1);
+    }
+    if (K.v0) { ph0 = fmaf(dt6, aph0, ph0); om0 = fmaf(dt6, aom0, om0); }
+    if (K.v1) { ph1 = fmaf(dt6, aph1, ph1); om1 = fmaf(dt6, aom1, om1); }
+    hw_sincos(ph0, &s0, &c0);
+    hw_sincos(ph1, &s1, &c1);
+    float ex = 0.0f, ey = 0.0f;
+    if (K.v0) { ex = K.l0 * s0; ey = -K.l0 * c0; }
+    if (K.v1) { ex = fmaf(K.l1, s1, ex); ey = fmaf(-K.l1, c1, ey); }
+    const float uu = fmaf(u0, u0, u1 * u1);
+    ex = quad_sum(ex);
+    ey = quad_sum(ey);
+    const float uus = quad_sum(uu);
+    const float dx = ex - tx, dy = ey - ty;
+    cost += fmaf(wg, fmaf(dx, dx, dy * dy), wu * uus);
+    if (b < P.n_dbg) {
+      float* X = P.X + b;
+      const size_t ldx = static_cast<size_t>(P.n_dbg);
+      if (K.v0) { X[(t * 2 * N + r0) * ldx] = ph0; X[(t * 2 * N + N + r0) * ldx] = om0; }
+      if (K.v1) { X[(t * 2 * N + r1) * ldx] = ph1; X[(t * 2 * N + N + r1) * ldx] = om1; }
+    }
+    u0 = un0;
+    u1 = un1;
+  }
+  if (s == 0) P.cost[b] = finite_or_inf(cost);
+}
+
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ float wave_sum64(float v) {
 #pragma unroll
@@ -557,67 +771,111 @@ __device__ __forceinline__ uint32_t cost_order(float c) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+constexpr int kTopkBins = 2048;   // 11-bit digits over the 32-bit cost image
+
 struct TopkSmem {
   unsigned long long keys[kMaxElites];
-  uint32_t hist[256];
-  uint32_t wave_sum[kTopkThreads / 64];
+  uint32_t hist[kTopkBins];
   unsigned long long prefix;
   uint32_t rank;
   uint32_t count;
+  uint32_t sel_count;
   float red[kTopkThreads / 64];
 };
+
+__device__ __forceinline__ unsigned long long topk_key(const PlanDesc& P, int b) {
+  return (static_cast<unsigned long long>(cost_order(P.cost[b])) << 32) | static_cast<uint32_t>(b);
+}
+
+// Wave 0 finds the digit whose bin holds the rank-th key (1-based) of the
+// histogram hist[0..nbins); writes the digit, the rank left inside that bin and
+// the bin's size to shared memory.
+__device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t rank, unsigned long long prefix,
+                                              int shift) {
+  const int lane = threadIdx.x;
+  if (lane >= 64) return;
+  const int per = nbins / 64;
+  uint32_t tot = 0;
+  for (int i = 0; i < per; ++i) tot += sm.hist[lane * per + i];
+  uint32_t inc = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  const uint32_t exc = inc - tot;
+  if (exc < rank && rank <= inc) {
+    uint32_t rr = rank - exc;
+    int d = lane * per;
+    for (int i = 0; i < per; ++i) {
+      const uint32_t h = sm.hist[lane * per + i];
+      if (rr <= h) { d = lane * per + i; sm.sel_count = h; break; }
+      rr -= h;
+    }
+    sm.prefix = prefix | (static_cast<unsigned long long>(d) << shift);
+    sm.rank = rr;
+  }
+}
 
 template <int BS>
 __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const int tid = threadIdx.x;
   const int B = P.B, E = P.E;
+  // Radix select over the 32-bit cost image with 11/11/10-bit digits: finds the
+  // image c* of the E-th smallest cost and how many of the keys equal to c* are
+  // needed.  If all of them are (no tie straddles the elite boundary), the elites
+  // are exactly the keys with image <= c*.  Otherwise continue the radix select
+  // over the full 64-bit key (image, index), which orders ties by index.
   unsigned long long prefix = 0ull, mask = 0ull;
-  uint32_t rank = static_cast<uint32_t>(E);   // 1-based rank of the wanted key among the candidates
-  for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 56 - 8 * pass;
-    for (int i = tid; i < 256; i += BS) sm.hist[i] = 0u;
+  uint32_t rank = static_cast<uint32_t>(E);
+  for (int pass = 0; pass < 3; ++pass) {
+    const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0), nb = pass == 2 ? 1024 : 2048;
+    for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
     __syncthreads();
     for (int b = tid; b < B; b += BS) {
-      const unsigned long long key = (static_cast<unsigned long long>(cost_order(P.cost[b])) << 32) |
-                                     static_cast<uint32_t>(b);
-      if ((key & mask) == prefix) atomicAdd(&sm.hist[(key >> shift) & 0xFFull], 1u);
+      const uint32_t o = cost_order(P.cost[b]);
+      if ((static_cast<unsigned long long>(o) & mask) == prefix) atomicAdd(&sm.hist[(o >> sh) & (nb - 1)], 1u);
     }
     __syncthreads();
-    if (tid < 64) {
-      // lane l owns bins 4l..4l+3; inclusive wave scan of the lane totals
-      const uint32_t h0 = sm.hist[4 * tid], h1 = sm.hist[4 * tid + 1], h2 = sm.hist[4 * tid + 2],
-                     h3 = sm.hist[4 * tid + 3];
-      const uint32_t tot = h0 + h1 + h2 + h3;
-      uint32_t inc = tot;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t v = __shfl_up(inc, o, 64);
-        if (tid >= o) inc += v;
-      }
-      const uint32_t exc = inc - tot;
-      if (exc < rank && rank <= inc) {
-        uint32_t rr = rank - exc, d = 4u * tid;
-        if (rr > h0) { rr -= h0; d += 1; if (rr > h1) { rr -= h1; d += 1; if (rr > h2) { rr -= h2; d += 1; } } }
-        sm.prefix = prefix | (static_cast<unsigned long long>(d) << shift);
-        sm.rank = rr;
-      }
-    }
+    topk_find_bin(sm, nb, rank, prefix, sh);
     __syncthreads();
     prefix = sm.prefix;
     rank = sm.rank;
-    mask |= 0xFFull << shift;
+    mask |= static_cast<unsigned long long>(nb - 1) << sh;
     __syncthreads();
   }
-  // prefix is now the E-th smallest key: gather the E keys <= prefix
+  unsigned long long limit;   // elites are the keys <= limit
+  if (rank == sm.sel_count) {
+    limit = (prefix << 32) | 0xFFFFFFFFull;
+  } else {
+    // ties at the boundary: radix over the index bits of the keys with image c*
+    unsigned long long kp = prefix << 32, km = 0xFFFFFFFF00000000ull;
+    for (int pass = 0; pass < 3; ++pass) {
+      const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0), nb = pass == 2 ? 1024 : 2048;
+      for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
+      __syncthreads();
+      for (int b = tid; b < B; b += BS) {
+        const unsigned long long key = topk_key(P, b);
+        if ((key & km) == kp) atomicAdd(&sm.hist[(key >> sh) & static_cast<unsigned long long>(nb - 1)], 1u);
+      }
+      __syncthreads();
+      topk_find_bin(sm, nb, rank, kp, sh);
+      __syncthreads();
+      kp = sm.prefix;
+      rank = sm.rank;
+      km |= static_cast<unsigned long long>(nb - 1) << sh;
+      __syncthreads();
+    }
+    limit = kp;
+  }
   int M = 1;
   while (M < E) M <<= 1;
   if (tid == 0) sm.count = 0u;
   for (int i = tid; i < M; i += BS) sm.keys[i] = ~0ull;
   __syncthreads();
   for (int b = tid; b < B; b += BS) {
-    const unsigned long long key = (static_cast<unsigned long long>(cost_order(P.cost[b])) << 32) |
-                                   static_cast<uint32_t>(b);
-    if (key <= prefix) {
+    const unsigned long long key = topk_key(P, b);
+    if (key <= limit) {
       const uint32_t slot = atomicAdd(&sm.count, 1u);
       if (slot < static_cast<uint32_t>(M)) sm.keys[slot] = key;
     }
@@ -641,7 +899,6 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const uint32_t i0 = static_cast<uint32_t>(sm.keys[0]);
   const float s0 = P.cost[i0 < static_cast<uint32_t>(B) ? i0 : 0u];
   const bool uniform = !(P.lam < INFINITY) || !(s0 < INFINITY);
-  float part = 0.0f;
   for (int e = tid; e < E; e += BS) {
     uint32_t uidx = static_cast<uint32_t>(sm.keys[e]);
     if (uidx >= static_cast<uint32_t>(B)) { uidx = 0u; atomicOr(&P.ctrl[2], 2u); }   // never expected
@@ -649,11 +906,8 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     const float ce = P.cost[idx];
     P.eidx[e] = idx;
     P.ecost[e] = ce;
-    const float z = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
-    P.w[e] = z;
-    part += z;
+    P.w[e] = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
   }
-  (void)part;
   // normalisation sum in an order fixed by E alone (independent of the block
   // size): lane l of wave 0 adds e = l, l+64, ... in turn, then a butterfly.
   __syncthreads();
