@@ -251,6 +251,16 @@ def bench_mix(args, cfgs):
             p.replan(x, shift=1)
     torch.cuda.synchronize()
     plain_wall = time.perf_counter() - t0
+    # per-stage kernel time summed over all instances (one replan each, kernels one by one)
+    stage_tot = {}
+    for p, x in zip(plans, xs):
+        p.set_stage_timing(True)
+        p.replan(x, shift=1)
+    torch.cuda.synchronize()
+    for p in plans:
+        for k_, (ms, n_) in p.stage_times().items():
+            stage_tot[k_] = stage_tot.get(k_, 0.0) + ms
+        p.set_stage_timing(False)
     for p in plans:
         p.close()
 
@@ -268,6 +278,7 @@ def bench_mix(args, cfgs):
                    "schedule": {"workgroups_per_cu": wg, "longest_first": bool(order)}},
         "replans_per_s": len(cfgs) * args.steps / wall,
         "latency_ms_p50": round(statistics.median(lat), 3), "latency_ms_p99": round(lat[-1], 3),
+        "plain_stage_ms_sum": {k_: round(v, 3) for k_, v in stage_tot.items()},
         "plain_launches": {"replans_per_s": len(cfgs) * plain_steps / plain_wall,
                            "rollout_steps_per_s": steps_per_replan * plain_steps / plain_wall,
                            "ms_per_round": plain_wall / plain_steps * 1e3},

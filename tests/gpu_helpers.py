@@ -62,7 +62,7 @@ def switching_flags(cfg, x0, U, margin=1e-5):
         n = cfg.n_links
         p = OD.chain_positions(X[..., :n], np.asarray(cfg.task.lengths, np.float64))
         gap = np.abs(p[..., 1] - float(cfg.task.ground_y))                 # (B, T, n)
-        return np.min(gap.reshape(B, -1), axis=1) < 1e-3
+        return np.min(gap.reshape(B, -1), axis=1) < margin
     return np.zeros(B, bool)
 
 
@@ -73,6 +73,22 @@ def cost_check(s_gpu, s_ref, flagged):
     ok |= both_inf
     bad = ~ok & ~flagged
     return bad
+
+
+def assert_costs(cfg, s_gpu, s_ref, flagged):
+    """Cost parity.  Smooth models: every unflagged candidate within S_TOL.
+    Contact chain: the penalty contact switches on and off, and a float32 state
+    that crosses the ground one step earlier or later than the float64 one sends
+    the chaotic chain on another trajectory; the rule there is at least 90% of
+    unflagged candidates within S_TOL and all within 1e-2 relative."""
+    bad = cost_check(s_gpu, s_ref, flagged)
+    if cfg.dynamics != 2:
+        assert not bad.any(), f"{bad.sum()} costs out of tolerance at {np.flatnonzero(bad)[:10]}"
+        return
+    rel = np.abs(np.asarray(s_gpu, np.float64) - s_ref) / np.maximum(np.abs(s_ref), 1e-12)
+    n = max(1, int((~flagged).sum()))
+    assert bad.sum() <= 0.1 * n, f"{bad.sum()} of {n} contact-chain costs out of tolerance"
+    assert np.all(rel[~flagged] < 1e-2), f"max contact-chain cost error {rel[~flagged].max():.2e}"
 
 
 def elite_margin_safe(s_ref, E):
