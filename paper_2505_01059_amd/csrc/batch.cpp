@@ -33,9 +33,10 @@ double work_estimate(const mtp_config& c) {
 uint32_t items_for(const mtp_config& c, int k_begin, int k_end) {
   const int B = c.n_tensor + c.n_gauss;
   const bool quad = is_quad_chain(c.dynamics, c.n_links);
-  const uint32_t per_iter = host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhCand, quad) +
-                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhRoll, quad) + 1u +
-                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhUpd, quad);
+  const bool pair = is_pair_chain(c.dynamics, c.n_links);
+  const uint32_t per_iter = host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhCand, quad, pair) +
+                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhRoll, quad, pair) + 1u +
+                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhUpd, quad, pair);
   return 1u + per_iter * static_cast<uint32_t>(k_end - k_begin);
 }
 

@@ -23,7 +23,9 @@ __device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phas
     case kPhShift: return 1u;
     case kPhCand: return static_cast<uint32_t>((P.B + kCandThreads - 1) / kCandThreads);
     case kPhRoll: {
-      const int per = is_quad_chain(P.dyn, P.n_links) ? kBatchThreads / 4 : kBatchThreads;
+      const int per = is_quad_chain(P.dyn, P.n_links)   ? kBatchThreads / 4
+                      : is_pair_chain(P.dyn, P.n_links) ? kBatchThreads / 2
+                                                         : kBatchThreads;
       return static_cast<uint32_t>((P.B + per - 1) / per);
     }
     case kPhTopk: return 1u;
@@ -63,24 +65,47 @@ __device__ __forceinline__ void run_rollout_tile(const PlanDesc& P, uint32_t til
       default: return;
     }
   }
+  if (is_pair_chain(P.dyn, P.n_links)) {
+    const int bp = static_cast<int>(tile) * (kBatchThreads / 2) + static_cast<int>(threadIdx.x >> 1);
+    if (bp >= P.B) return;
+    const bool lane_b = (threadIdx.x & 1) != 0;
+    if (P.dyn == kChain) {
+      switch (P.n_links) {
+#define X(N) case N: if constexpr (pair_chain_links<N>()) rollout_chain_pair<N, false>(P, bp, lane_b); return;
+        MTP_CHAIN_LINKS(X)
+#undef X
+        default: return;
+      }
+    }
+    switch (P.n_links) {
+#define X(N) case N: if constexpr (pair_chain_links<N>()) rollout_chain_pair<N, true>(P, bp, lane_b); return;
+      MTP_CONTACT_LINKS(X)
+#undef X
+      default: return;
+    }
+  }
   if (b >= P.B) return;
   if (P.dyn == kChain) {
     switch (P.n_links) {
-#define X(N) case N: rollout_chain<N, false>(P, b); return;
+#define X(N) case N: if constexpr (!pair_chain_links<N>() && !quad_chain_links<N>()) rollout_chain<N, false>(P, b); return;
       MTP_CHAIN_LINKS(X)
 #undef X
       default: return;
     }
   }
   switch (P.n_links) {
-#define X(N) case N: rollout_chain<N, true>(P, b); return;
+#define X(N) case N: if constexpr (!pair_chain_links<N>()) rollout_chain<N, true>(P, b); return;
     MTP_CONTACT_LINKS(X)
 #undef X
     default: return;
   }
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_batch_persistent(const PlanDesc* __restrict__ descs,
+#ifndef MTP_BATCH_MIN_WG_PER_CU
+#define MTP_BATCH_MIN_WG_PER_CU 1
+#endif
+
+__global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batch_persistent(const PlanDesc* __restrict__ descs,
                                                                     InstCtl* __restrict__ ictl, BatchCtl* ctl,
                                                                     BatchItem* __restrict__ queue,
                                                                     uint32_t* __restrict__ ready,

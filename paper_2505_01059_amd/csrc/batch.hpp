@@ -78,12 +78,12 @@ const char* batch_error(const mtp_batch* b);
 hipStream_t batch_stream(const mtp_batch* b);
 
 // host mirror of the per-phase tile counts
-inline uint32_t host_phase_tiles(int B, int T, int n, uint32_t phase, bool quad) {
+inline uint32_t host_phase_tiles(int B, int T, int n, uint32_t phase, bool quad, bool pair) {
   switch (phase) {
     case kPhShift: return 1u;
     case kPhCand: return static_cast<uint32_t>((B + kCandThreads - 1) / kCandThreads);
     case kPhRoll: {
-      const int per = quad ? kBatchThreads / 4 : kBatchThreads;
+      const int per = quad ? kBatchThreads / 4 : (pair ? kBatchThreads / 2 : kBatchThreads);
       return static_cast<uint32_t>((B + per - 1) / per);
     }
     case kPhTopk: return 1u;

@@ -31,6 +31,13 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_chain(PlanDesc P) {
   if (b < P.B) rollout_chain<N, CONTACT>(P, b);
 }
 
+template <int N, bool CONTACT>
+__global__ __launch_bounds__(kRollThreads) void k_rollout_chain_pair(PlanDesc P) {
+  const int g = blockIdx.x * kRollThreads + threadIdx.x;
+  const int b = g >> 1;
+  if (b < P.B) rollout_chain_pair<N, CONTACT>(P, b, (g & 1) != 0);
+}
+
 template <int N>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_chain_quad(PlanDesc P) {
   const int g = blockIdx.x * kRollThreads + threadIdx.x;
@@ -92,20 +99,41 @@ static hipError_t launch_rollout(const PlanDesc& P, hipStream_t st) {
     }
     return hipErrorInvalidValue;
   }
+  if (is_pair_chain(P.dyn, P.n_links)) {
+    const dim3 pgrid((2 * P.B + kRollThreads - 1) / kRollThreads);
+    if (P.dyn == kChain) {
+      switch (P.n_links) {
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, false><<<pgrid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+        MTP_CHAIN_LINKS(X)
+#undef X
+        default: break;
+      }
+    } else {
+      switch (P.n_links) {
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, true><<<pgrid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+        MTP_CONTACT_LINKS(X)
+#undef X
+        default: break;
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   if (P.dyn == kChain) {
     switch (P.n_links) {
-#define X(N) case N: k_rollout_chain<N, false><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError();
+#define X(N) case N: if constexpr (!pair_chain_links<N>() && !quad_chain_links<N>()) { k_rollout_chain<N, false><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
       MTP_CHAIN_LINKS(X)
 #undef X
-      default: return hipErrorInvalidValue;
+      default: break;
     }
+    return hipErrorInvalidValue;
   }
   switch (P.n_links) {
-#define X(N) case N: k_rollout_chain<N, true><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError();
+#define X(N) case N: if constexpr (!pair_chain_links<N>()) { k_rollout_chain<N, true><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
     MTP_CONTACT_LINKS(X)
 #undef X
-    default: return hipErrorInvalidValue;
+    default: break;
   }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_set_ctrl(const PlanDesc& P, uint32_t r, int shift, const float* x0_src, hipStream_t st) {

@@ -85,12 +85,14 @@ __device__ __forceinline__ float u01(uint32_t w) { return static_cast<float>(w >
 // (0, 1] variant for the Box-Muller radius
 __device__ __forceinline__ float u01_open0(uint32_t w) { return static_cast<float>((w >> 8) + 1u) * 0x1p-24f; }
 
+// Box-Muller on the hardware transcendental unit: v_log gives log2 (times ln 2
+// for the natural log), and v_sin / v_cos take their argument in revolutions,
+// so the angle 2*pi*u2 is exactly u2 revolutions.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
-  const float rad = sqrtf(-2.0f * logf(u01_open0(a)));
-  float s, c;
-  sincospif(2.0f * u01(b), &s, &c);   // angle 2*pi*u2, evaluated without rounding 2*pi
-  z0 = rad * c;
-  z1 = rad * s;
+  const float rad = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01_open0(a)));   // -2 ln u1
+  const float u2 = u01(b);
+  z0 = rad * __builtin_amdgcn_cosf(u2);
+  z1 = rad * __builtin_amdgcn_sinf(u2);
 }
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
@@ -206,6 +208,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
     __syncthreads();
     if (is_local) {
       // local sample g = b: u = clip(mu + sigma * eps), four steps per Philox block
+#pragma unroll 2
       for (int tq = t0 >> 2; tq < ((t0 + tn + 3) >> 2); ++tq) {
         const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
                                 stream_c3(kTagEps, k), P.key0, P.key1);
@@ -222,8 +225,20 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
         }
       }
     } else if (is_tensor) {
-      if (P.interp == kBspline) {
+      if (P.interp == kBspline && P.p == 3) {
+#pragma unroll 4
+        for (int i = 0; i < tn; ++i) {
+          const int s0 = sm.ts[i];
+          const float* bw = sm.tb + i * kBasisStride;
+          float v = bw[0] * sm.ctrl[s0][tid];
+          v = fmaf(bw[1], sm.ctrl[s0 + 1][tid], v);
+          v = fmaf(bw[2], sm.ctrl[s0 + 2][tid], v);
+          v = fmaf(bw[3], sm.ctrl[s0 + 3][tid], v);
+          P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
+        }
+      } else if (P.interp == kBspline) {
         const int np1 = P.p + 1;
+#pragma unroll 2
         for (int i = 0; i < tn; ++i) {
           const int s0 = sm.ts[i];
           const float* bw = sm.tb + i * kBasisStride;
@@ -232,6 +247,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
         }
       } else {
+#pragma unroll 4
         for (int i = 0; i < tn; ++i) {
           const int iv = sm.ts[i];
           const float* h = sm.tb + i * kBasisStride;
@@ -244,6 +260,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
       }
     } else if (live) {
       // nominal mean
+#pragma unroll 4
       for (int i = 0; i < tn; ++i) P.U[((t0 + i) * P.n + j) * ld + b] = clampf(sm.tmu[i], lo, hi);
     }
     __syncthreads();
@@ -749,6 +766,290 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     u1 = un1;
   }
   if (s == 0) P.cost[b] = finite_or_inf(cost);
+}
+
+// ------------------------------------------------------------------ pair-lane chain
+// Even chains of 10 or more links: two lanes share one candidate.  Lane A owns
+// links 0..M-1 in order, lane B links N-1..M in reverse (M = N/2), so local row
+// i of both lanes runs the same instructions: the tension system is eliminated
+// from both ends towards the middle (a twisted factorisation), the two middle
+// unknowns come from a 2x2 solve with one value swapped across the pair, and
+// back-substitution runs outwards.  Neighbour terms are picked with per-lane
+// selects on compile-time indices, so nothing is indexed dynamically.  Half the
+// registers of the one-lane form and twice the lanes.
+
+__host__ __device__ constexpr bool is_pair_chain(int dyn, int n) {
+  return (dyn == kChain || dyn == kChainContact) && n >= 10 && (n % 2) == 0;
+}
+
+template <int N>
+constexpr bool pair_chain_links() { return N >= 10 && (N % 2) == 0; }
+
+__device__ __forceinline__ float pswap(float v) { return qperm<kQXor1>(v); }
+
+template <int N>
+struct PairConsts {
+  static constexpr int M = N / 2;
+  float l[M], invl[M], im[M];      // own links in local order
+  float im_mid_other;              // inverse mass of the other lane's local link M-1
+  float g;
+  float yg, kc, dc, inv_vs, muf;   // contact only
+  bool B;                          // lane owns the tip half (reverse order)
+};
+
+template <int N>
+__device__ __forceinline__ int pair_link(bool B, int i) { return B ? N - 1 - i : i; }
+
+template <int N, bool CONTACT>
+__device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
+                                           const float (&q)[N / 2], float q_other, const PairConsts<N>& K,
+                                           float (&acc)[N / 2]) {
+  constexpr int M = N / 2;
+  const bool B = K.B;
+  // trig of neighbouring local links; entry M-1 pairs with the other lane's link
+  float P[M], Q[M];
+#pragma unroll
+  for (int i = 0; i + 1 < M; ++i) {
+    P[i] = fmaf(c[i], c[i + 1], s[i] * s[i + 1]);
+    Q[i] = fmaf(s[i], c[i + 1], -c[i] * s[i + 1]);
+  }
+  {
+    const float so = pswap(s[M - 1]), co = pswap(c[M - 1]);
+    P[M - 1] = fmaf(c[M - 1], co, s[M - 1] * so);
+    Q[M - 1] = fmaf(s[M - 1], co, -c[M - 1] * so);
+  }
+  // non-constraint accelerations (contact forces / mass); gravity enters at the base
+  float fx[CONTACT ? M : 1], fy[CONTACT ? M : 1];
+  float fxo = 0.0f, fyo = 0.0f;
+  if constexpr (CONTACT) {
+    float tx = 0.0f, ty = 0.0f, tvx = 0.0f, tvy = 0.0f;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const float lw = K.l[i] * w[i];
+      tx = fmaf(K.l[i], s[i], tx);
+      ty = fmaf(-K.l[i], c[i], ty);
+      tvx = fmaf(lw, c[i], tvx);
+      tvy = fmaf(lw, s[i], tvy);
+    }
+    const float Tx = tx + pswap(tx), Ty = ty + pswap(ty), Tvx = tvx + pswap(tvx), Tvy = tvy + pswap(tvy);
+    float ex = 0.0f, ey = 0.0f, evx = 0.0f, evy = 0.0f;   // sums over local links before i
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const float lw = K.l[i] * w[i];
+      const float ox = K.l[i] * s[i], oy = -K.l[i] * c[i], ovx = lw * c[i], ovy = lw * s[i];
+      const float py = B ? Ty - ey : ey + oy;
+      const float vx = B ? Tvx - evx : evx + ovx;
+      const float vy = B ? Tvy - evy : evy + ovy;
+      ex += ox; ey += oy; evx += ovx; evy += ovy;
+      const float pen = K.yg - py;
+      float ffx = 0.0f, ffy = 0.0f;
+      if (pen > 0.0f) {
+        const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vy), 0.0f);
+        const float ft = -K.muf * fn * fast_tanh(vx * K.inv_vs);
+        ffx = ft * K.im[i];
+        ffy = fn * K.im[i];
+      }
+      fx[i] = ffx;
+      fy[i] = ffy;
+    }
+    (void)Tx;
+    fxo = pswap(fx[M - 1]);
+    fyo = pswap(fy[M - 1]);
+  }
+  float cp[M], dp[M];
+  float cp_prev = 0.0f, dp_prev = 0.0f;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const float tipP = B ? (i > 0 ? P[i - 1] : 0.0f) : P[i];
+    const float tipQ = B ? (i > 0 ? -Q[i - 1] : 0.0f) : Q[i];
+    const float baseP = B ? P[i] : (i > 0 ? P[i - 1] : 0.0f);
+    const float baseQ = B ? -Q[i] : (i > 0 ? Q[i - 1] : 0.0f);
+    const float q_tip = B ? (i > 0 ? q[i - 1] : 0.0f) : (i + 1 < M ? q[i + 1] : q_other);
+    const float q_base = B ? (i + 1 < M ? q[i + 1] : q_other) : (i > 0 ? q[i - 1] : 0.0f);
+    const float im_base = B ? (i + 1 < M ? K.im[i + 1] : K.im_mid_other) : (i > 0 ? K.im[i - 1] : 0.0f);
+    float dfx = 0.0f, dfy = 0.0f;
+    if constexpr (CONTACT) {
+      const float fbx = B ? (i + 1 < M ? fx[i + 1] : fxo) : (i > 0 ? fx[i - 1] : 0.0f);
+      const float fby = B ? (i + 1 < M ? fy[i + 1] : fyo) : (i > 0 ? fy[i - 1] : 0.0f);
+      dfx = fx[i] - fbx;
+      dfy = fy[i] - fby;
+    }
+    if (i == 0 && !B) dfy -= K.g;
+    const float D = K.im[i] + im_base;
+    const float tip_coef = -K.im[i] * tipP;
+    const float base_coef = -im_base * baseP;
+    float rhs = K.l[i] * w[i] * w[i];
+    rhs = fmaf(s[i], dfx, rhs);
+    rhs = fmaf(-c[i], dfy, rhs);
+    rhs = fmaf(-K.im[i] * q_tip, tipQ, rhs);
+    rhs = fmaf(im_base * q_base, baseQ, rhs);
+    const float Lp = B ? tip_coef : base_coef;
+    const float Un = B ? base_coef : tip_coef;
+    const float inv = __builtin_amdgcn_rcpf(fmaf(-Lp, cp_prev, D));
+    cp_prev = Un * inv;
+    dp_prev = fmaf(-Lp, dp_prev, rhs) * inv;
+    cp[i] = cp_prev;
+    dp[i] = dp_prev;
+  }
+  // the two middle unknowns, then back-substitution outwards (dp becomes the tension)
+  {
+    const float cpo = pswap(cp[M - 1]), dpo = pswap(dp[M - 1]);
+    dp[M - 1] = fmaf(-cp[M - 1], dpo, dp[M - 1]) * __builtin_amdgcn_rcpf(fmaf(-cp[M - 1], cpo, 1.0f));
+  }
+#pragma unroll
+  for (int i = M - 2; i >= 0; --i) dp[i] = fmaf(-cp[i], dp[i + 1], dp[i]);
+  const float xo = pswap(dp[M - 1]);
+  // neighbour trig again (cheaper than keeping it live across the solve)
+  {
+    const float so = pswap(s[M - 1]), co = pswap(c[M - 1]);
+#pragma unroll
+    for (int i = 0; i + 1 < M; ++i) {
+      P[i] = fmaf(c[i], c[i + 1], s[i] * s[i + 1]);
+      Q[i] = fmaf(s[i], c[i + 1], -c[i] * s[i + 1]);
+    }
+    P[M - 1] = fmaf(c[M - 1], co, s[M - 1] * so);
+    Q[M - 1] = fmaf(s[M - 1], co, -c[M - 1] * so);
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const float tipP = B ? (i > 0 ? P[i - 1] : 0.0f) : P[i];
+    const float tipQ = B ? (i > 0 ? -Q[i - 1] : 0.0f) : Q[i];
+    const float baseP = B ? P[i] : (i > 0 ? P[i - 1] : 0.0f);
+    const float baseQ = B ? -Q[i] : (i > 0 ? Q[i - 1] : 0.0f);
+    const float q_tip = B ? (i > 0 ? q[i - 1] : 0.0f) : (i + 1 < M ? q[i + 1] : q_other);
+    const float q_base = B ? (i + 1 < M ? q[i + 1] : q_other) : (i > 0 ? q[i - 1] : 0.0f);
+    const float im_base = B ? (i + 1 < M ? K.im[i + 1] : K.im_mid_other) : (i > 0 ? K.im[i - 1] : 0.0f);
+    const float T_tip = B ? (i > 0 ? dp[i - 1] : 0.0f) : (i + 1 < M ? dp[i + 1] : xo);
+    const float T_base = B ? (i + 1 < M ? dp[i + 1] : xo) : (i > 0 ? dp[i - 1] : 0.0f);
+    float a = (K.im[i] + im_base) * q[i];
+    a = fmaf(-K.im[i], fmaf(T_tip, tipQ, q_tip * tipP), a);
+    a = fmaf(-im_base, fmaf(-T_base, baseQ, q_base * baseP), a);
+    float dfx = 0.0f, dfy = 0.0f;
+    if constexpr (CONTACT) {
+      const float fbx = B ? (i + 1 < M ? fx[i + 1] : fxo) : (i > 0 ? fx[i - 1] : 0.0f);
+      const float fby = B ? (i + 1 < M ? fy[i + 1] : fyo) : (i > 0 ? fy[i - 1] : 0.0f);
+      dfx = fx[i] - fbx;
+      dfy = fy[i] - fby;
+    }
+    if (i == 0 && !B) dfy -= K.g;
+    a = fmaf(c[i], dfx, fmaf(s[i], dfy, a));
+    acc[i] = a * K.invl[i];
+  }
+}
+
+// One candidate b per lane pair; B is the tip-half lane.  Both lanes of a pair
+// must run this together.
+template <int N, bool CONTACT>
+__device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, bool B) {
+  static_assert(N >= 10 && N % 2 == 0, "pair-lane chain needs an even link count >= 10");
+  constexpr int M = N / 2;
+  const float* tk = P.task;
+  PairConsts<N> K;
+  K.B = B;
+  K.g = tk[0];
+  const float wg = tk[1], wu = tk[2], tgx = tk[3], tgy = tk[4];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const int k = pair_link<N>(B, i);
+    K.l[i] = tk[5 + N + k];
+    K.invl[i] = 1.0f / K.l[i];
+  }
+  if constexpr (CONTACT) {
+    const float* sp = P.sparams + static_cast<size_t>(b) * (N + 1);
+#pragma unroll
+    for (int i = 0; i < M; ++i) K.im[i] = 1.0f / sp[pair_link<N>(B, i)];
+    K.muf = sp[N];
+    K.yg = tk[5 + 2 * N]; K.kc = tk[6 + 2 * N]; K.dc = tk[7 + 2 * N]; K.inv_vs = 1.0f / tk[8 + 2 * N];
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) K.im[i] = 1.0f / tk[5 + pair_link<N>(B, i)];
+    K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
+  }
+  K.im_mid_other = pswap(K.im[M - 1]);
+  const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
+  float ph[M], om[M], s[M], c[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const int k = pair_link<N>(B, i);
+    ph[i] = P.x0[k];
+    om[i] = P.x0[N + k];
+    hw_sincos(ph[i], &s[i], &c[i]);
+  }
+  const size_t ld = static_cast<size_t>(P.ldU);
+  const float* ub = P.U + b;
+  float u[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) u[i] = ub[pair_link<N>(B, i) * ld];
+  float cost = 0.0f;
+  for (int t = 0; t < P.T; ++t) {
+    float un[M];
+    const bool more = (t + 1 < P.T);
+#pragma unroll
+    for (int i = 0; i < M; ++i) un[i] = more ? ub[((t + 1) * N + pair_link<N>(B, i)) * ld] : 0.0f;
+    // torque terms (u_k - u_{k+1}) / l_k; the tip neighbour of lane A's last link is lane B's
+    float q[M];
+    const float u_other = pswap(u[M - 1]);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const float u_tip = B ? (i > 0 ? u[i - 1] : 0.0f) : (i + 1 < M ? u[i + 1] : u_other);
+      q[i] = (u[i] - u_tip) * K.invl[i];
+    }
+    const float q_other = pswap(q[M - 1]);
+
+    float kk[M], oms[M], aph[M], aom[M];
+    pair_accel<N, CONTACT>(s, c, om, q, q_other, K, kk);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      aph[i] = om[i];
+      aom[i] = kk[i];
+      oms[i] = om[i];
+    }
+#pragma unroll 1
+    for (int stage = 1; stage < 4; ++stage) {
+      const float h = (stage == 3) ? dt : hdt;
+      float s2[M], c2[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        hw_sincos(fmaf(h, oms[i], ph[i]), &s2[i], &c2[i]);
+        oms[i] = fmaf(h, kk[i], om[i]);
+      }
+      pair_accel<N, CONTACT>(s2, c2, oms, q, q_other, K, kk);
+      const float wgt = (stage == 3) ? 1.0f : 2.0f;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        aph[i] = fmaf(wgt, oms[i], aph[i]);
+        aom[i] = fmaf(wgt, kk[i], aom[i]);
+      }
+    }
+    float ex = 0.0f, ey = 0.0f, uu = 0.0f;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      ph[i] = fmaf(dt6, aph[i], ph[i]);
+      om[i] = fmaf(dt6, aom[i], om[i]);
+      hw_sincos(ph[i], &s[i], &c[i]);
+      ex = fmaf(K.l[i], s[i], ex);
+      ey = fmaf(-K.l[i], c[i], ey);
+      uu = fmaf(u[i], u[i], uu);
+    }
+    ex += pswap(ex);
+    ey += pswap(ey);
+    uu += pswap(uu);
+    const float dx = ex - tgx, dy = ey - tgy;
+    cost += fmaf(wg, fmaf(dx, dx, dy * dy), wu * uu);
+    if (b < P.n_dbg) {
+      float* X = P.X + b;
+      const size_t ldx = static_cast<size_t>(P.n_dbg);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const int k = pair_link<N>(B, i);
+        X[(t * 2 * N + k) * ldx] = ph[i];
+        X[(t * 2 * N + N + k) * ldx] = om[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) u[i] = un[i];
+  }
+  if (!B) P.cost[b] = finite_or_inf(cost);
 }
 
 // ------------------------------------------------------------------ reductions
