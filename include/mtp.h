@@ -59,7 +59,11 @@ typedef enum {
   MTP_ERR_NOT_READY = 6     /* no result available yet                             */
 } mtp_status;
 
-typedef enum { MTP_INTERP_BSPLINE = 0, MTP_INTERP_AKIMA = 1 } mtp_interp;
+typedef enum {
+  MTP_INTERP_BSPLINE = 0,  /* Def. 2, degree bspline_degree, uniform knots                  */
+  MTP_INTERP_AKIMA = 1,    /* Def. 3, knots i/L                                             */
+  MTP_INTERP_LINEAR = 2    /* straight lines between waypoints on knots i/(L-1) (Thm. 1)   */
+} mtp_interp;
 
 typedef enum {
   MTP_DYN_POINT_MASS = 0,    /* planar double integrator, d=4, n=2, semi-implicit Euler */
@@ -90,7 +94,7 @@ typedef struct {
   int32_t state_dim;         /* d */
   int32_t ctrl_dim;          /* n */
   int32_t horizon;           /* T >= 1 */
-  int32_t n_layers;          /* L: >= degree+1 (B-spline), >= 2 (Akima), <= 16 */
+  int32_t n_layers;          /* L: >= degree+1 (B-spline), >= 2 (Akima, linear), <= 16 */
   int32_t n_width;           /* W: 1..256 */
   int32_t n_tensor;          /* P >= 0 */
   int32_t n_gauss;           /* G >= 1 */
@@ -201,7 +205,8 @@ const char* mtp_last_error(const mtp_plan* p);
  * horizon*8 floats, span gets horizon ints.  B-spline row t holds the degree+1
  * weights of control points span[t] .. span[t]+degree; Akima row t holds the
  * cubic Hermite weights (value i, slope i, value i+1, slope i+1) of interval
- * span[t], slopes in units of the knot spacing. */
+ * span[t], slopes in units of the knot spacing; linear row t holds the two
+ * weights of waypoints span[t] and span[t]+1. */
 mtp_status mtp_interp_table(const mtp_config* cfg, float* h_basis, int32_t* h_span);
 
 /* ---------------------------------------------------------------- batching

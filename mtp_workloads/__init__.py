@@ -27,10 +27,10 @@ from typing import Optional
 import numpy as np
 
 POINT_MASS, CHAIN, CHAIN_CONTACT = 0, 1, 2
-BSPLINE, AKIMA = 0, 1
+BSPLINE, AKIMA, LINEAR = 0, 1, 2
 
 DYN_NAMES = {POINT_MASS: "point_mass", CHAIN: "chain", CHAIN_CONTACT: "chain_contact"}
-INTERP_NAMES = {BSPLINE: "bspline", AKIMA: "akima"}
+INTERP_NAMES = {BSPLINE: "bspline", AKIMA: "akima", LINEAR: "linear"}
 
 f32 = np.float32
 

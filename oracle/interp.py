@@ -13,6 +13,10 @@ recursion below runs in knot-index units (knot i at i) and evaluates at
 tau_j = p + (L - p) j / T.  Which half-open interval contains tau_j is
 decided with integers, so knot hits are exact.
 
+Linear paths (Section 3.1, "straight-line interpolation"; Thm. 1).  The L
+waypoints sit on equally spaced knots t_i = i/(L-1) spanning [0, 1], as in the
+statement of Thm. 1, and the path is sampled at t_j = j/T.
+
 Akima spline (Eq. 5-7 and Def. 3).  Knots t_i = i/L for the L waypoints and
 evaluation points t_j = j/T.  Slopes follow Eq. 6 with the paper's end rules;
 when both weights of Eq. 6 vanish (e.g. on linear data) the slope is the mean
@@ -133,3 +137,18 @@ def akima_eval(A, horizon):
 
 def akima_interp(C, horizon):
     return akima_eval(akima_coefficients(C), horizon)
+
+
+# ---------------------------------------------------------------- linear
+
+def linear_interp(C, horizon):
+    """Piecewise-linear path through the waypoints (knots i/(L-1)) at t_j = j/T."""
+    C = np.asarray(C, dtype=np.float64)
+    P_, L, n = C.shape
+    knots = np.linspace(0.0, 1.0, L)
+    t = np.arange(horizon, dtype=np.float64) / horizon
+    out = np.empty((P_, horizon, n))
+    for p in range(P_):
+        for j in range(n):
+            out[p, :, j] = np.interp(t, knots, C[p, :, j])
+    return out

@@ -70,8 +70,10 @@ def tensor_samples(cfg, r, k):
     C = sampling.gather(Z, I).astype(np.float64)
     if cfg.interp == 0:
         UG = interp.bspline_interp(C, cfg.bspline_degree, cfg.horizon)
-    else:
+    elif cfg.interp == 1:
         UG = interp.akima_interp(C, cfg.horizon)
+    else:
+        UG = interp.linear_interp(C, cfg.horizon)
     return Z, I, UG
 
 

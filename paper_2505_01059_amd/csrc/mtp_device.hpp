@@ -24,7 +24,7 @@ enum Dyn : int32_t { kPointMass = 0, kChain = 1, kChainContact = 2 };
 // the per-link state in registers).
 #define MTP_CHAIN_LINKS(X) X(2) X(3) X(4) X(7) X(12) X(24)
 #define MTP_CONTACT_LINKS(X) X(4) X(7) X(24)
-enum Interp : int32_t { kBspline = 0, kAkima = 1 };
+enum Interp : int32_t { kBspline = 0, kAkima = 1, kLinear = 2 };
 
 // Everything a stage needs, by value in kernel arguments (or in a device table
 // for the batched kernel).  Pointers address the caller's workspace.
@@ -236,8 +236,8 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           v = fmaf(bw[3], sm.ctrl[s0 + 3][tid], v);
           P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
         }
-      } else if (P.interp == kBspline) {
-        const int np1 = P.p + 1;
+      } else if (P.interp != kAkima) {
+        const int np1 = P.interp == kLinear ? 2 : P.p + 1;
 #pragma unroll 2
         for (int i = 0; i < tn; ++i) {
           const int s0 = sm.ts[i];

@@ -40,7 +40,7 @@ bool validate_config(const mtp_config* c, std::string* why, mtp_status* code) {
   if (c == nullptr) return fail(MTP_ERR_INVALID_ARG, "config is NULL");
   if (c->abi_version != MTP_ABI_VERSION) return fail(MTP_ERR_INVALID_ARG, "abi_version mismatch");
   if (c->dynamics < 0 || c->dynamics > 2) return fail(MTP_ERR_INVALID_ARG, "unknown dynamics");
-  if (c->interp < 0 || c->interp > 1) return fail(MTP_ERR_INVALID_ARG, "unknown interpolation");
+  if (c->interp < 0 || c->interp > 2) return fail(MTP_ERR_INVALID_ARG, "unknown interpolation");
   if (c->dynamics == MTP_DYN_POINT_MASS) {
     if (c->state_dim != 4 || c->ctrl_dim != 2) return fail(MTP_ERR_INVALID_ARG, "point mass needs state_dim 4, ctrl_dim 2");
   } else {
@@ -55,7 +55,7 @@ bool validate_config(const mtp_config* c, std::string* why, mtp_status* code) {
     if (c->bspline_degree < 1 || c->bspline_degree > 5) return fail(MTP_ERR_INVALID_ARG, "bspline_degree must be in 1..5");
     if (c->n_layers < c->bspline_degree + 1) return fail(MTP_ERR_INVALID_ARG, "B-spline needs n_layers >= degree + 1");
   } else if (c->n_layers < 2) {
-    return fail(MTP_ERR_INVALID_ARG, "Akima needs n_layers >= 2");
+    return fail(MTP_ERR_INVALID_ARG, "Akima and linear paths need n_layers >= 2");
   }
   if (c->n_tensor < 0) return fail(MTP_ERR_INVALID_ARG, "n_tensor must be >= 0");
   if (c->n_gauss < 1) return fail(MTP_ERR_INVALID_ARG, "n_gauss must be >= 1 (it holds the nominal mean)");
@@ -175,6 +175,14 @@ void build_tables(const mtp_config& c, std::vector<float>* basis, std::vector<in
       bspline_span_basis(p, s, tau, N);
       for (int q = 0; q <= p; ++q) row[q] = static_cast<float>(N[q]);
       (*span)[j] = s - p;
+    } else if (c.interp == MTP_INTERP_LINEAR) {
+      // knots i/(L-1) over [0, 1], sample at j/T: weights 1-xi, xi in interval i
+      const long long num = static_cast<long long>(L - 1) * j;
+      const int i = static_cast<int>(num / T);
+      const double xi = static_cast<double>(num - static_cast<long long>(i) * T) / T;
+      row[0] = static_cast<float>(1.0 - xi);
+      row[1] = static_cast<float>(xi);
+      (*span)[j] = i;
     } else {
       // Akima knots at i/L, sample at j/T; cubic Hermite weights in xi = L j / T - i
       const long long num = static_cast<long long>(L) * j;

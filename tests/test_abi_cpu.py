@@ -160,3 +160,16 @@ def test_akima_table_reproduces_oracle_akima(L, T):
         h = basis[j, :4].astype(np.float64)
         v = h[0] * z[:, i] + h[1] * hs[:, i] + h[2] * z[:, i + 1] + h[3] * hs[:, i + 1]
         np.testing.assert_allclose(v, U[:, j], atol=2e-6)
+
+
+@pytest.mark.parametrize("L,T", [(5, 64), (2, 10), (8, 37)])
+def test_linear_table_matches_oracle(L, T):
+    from oracle import interp as OI
+    cfg = W.point_mass_config(interp=W.LINEAR, n_layers=L, horizon=T)
+    basis, span = N.interp_table(cfg)
+    rng = np.random.default_rng(L)
+    C = rng.uniform(-1, 1, size=(3, L, 1))
+    U = OI.linear_interp(C, T)
+    for j in range(T):
+        v = basis[j, 0] * C[:, span[j]] + basis[j, 1] * C[:, span[j] + 1]
+        np.testing.assert_allclose(v, U[:, j], atol=1e-6)

@@ -136,3 +136,16 @@ def test_akima_small_L():
     t = interp.akima_knots(2)
     z = np.array([[[0.0], [1.0]]])
     np.testing.assert_allclose(interp.akima_interp(z, 10)[0, :, 0], np.arange(10) / 10 * 2)
+
+
+def test_linear_paths_through_waypoints_and_straight_between():
+    """Thm. 1's straight-line paths: waypoints on equally spaced knots over [0, 1]."""
+    L, T = 5, 64                     # knots at j = 16 i
+    rng = np.random.default_rng(9)
+    C = rng.uniform(-1, 1, size=(7, L, 2))
+    U = interp.linear_interp(C, T)
+    for i in range(L - 1):
+        np.testing.assert_allclose(U[:, 16 * i], C[:, i], atol=1e-14)
+        seg = U[:, 16 * i:16 * (i + 1)]
+        np.testing.assert_allclose(np.diff(seg, 2, axis=1), 0.0, atol=1e-13)
+    np.testing.assert_allclose(U[:, 63], C[:, 3] + (C[:, 4] - C[:, 3]) * 15 / 16, atol=1e-14)
