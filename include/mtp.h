@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define MTP_ABI_VERSION 1
+#define MTP_ABI_VERSION 2
 
 typedef enum {
   MTP_OK = 0,
@@ -83,8 +83,10 @@ typedef enum {
  *                   mass_1..mass_n, length_1..length_n]
  *   CHAIN_CONTACT: CHAIN's layout followed by [ground_y, k_contact, d_contact, v_slip];
  *                  its masses are ignored in favour of sample_params.
- * sample_params (host, copied at create; CHAIN_CONTACT only): B rows of
- *   [mass_1..mass_n, friction_coefficient], row b for candidate b.
+ * sample_params (host, copied at create; CHAIN_CONTACT only): R*B rows of
+ *   [mass_1..mass_n, friction_coefficient], row r*B + b for candidate b under
+ *   randomised model r; the candidate's cost is the mean over its R rollouts
+ *   (online domain randomisation, Section 4).
  */
 typedef struct {
   uint32_t abi_version;      /* MTP_ABI_VERSION */
@@ -112,6 +114,8 @@ typedef struct {
   int32_t n_task_params;
   const float* sample_params;  /* host, CHAIN_CONTACT only, B*(n+1) floats */
   int32_t n_debug_states;    /* record x_{t+1} of candidates 0..n_debug_states-1 (0 = off) */
+  int32_t n_replicas;        /* R >= 1 randomised models per candidate (R > 1: CHAIN_CONTACT only);
+                                0 is read as 1 */
 } mtp_config;
 
 /*
@@ -127,7 +131,7 @@ typedef struct {
  *   mu, sigma  float [T][n]
  *   x0         float [d]              start state of the current replan
  *   action     float [n]
- *   X_dbg      float [T][d][n_debug_states] or NULL
+ *   X_dbg      float [T][d][n_debug_states] or NULL (model 0 when R > 1)
  */
 typedef struct {
   void *Z, *I, *U, *cost, *elite_idx, *elite_cost, *weights, *mu, *sigma, *x0, *action, *X_dbg;

@@ -90,7 +90,8 @@ class Config:
     dt: np.float32
     seed: int
     task: object
-    sample_params: Optional[np.ndarray] = None   # (B, n+1) float32: link masses, friction
+    sample_params: Optional[np.ndarray] = None   # (R*B, n+1) float32: link masses, friction
+    n_replicas: int = 1                          # R randomised models per candidate (contact chain)
 
     @property
     def n_samples(self) -> int:
@@ -206,7 +207,9 @@ def chain_contact_config(name="chain24_contact_c4", *, n_links=24, horizon=256,
                          n_layers=12, n_width=64, n_tensor=65536, n_gauss=4096,
                          n_elites=512, n_iters=6, interp=BSPLINE, bspline_degree=3,
                          seed=0, temperature=0.1, smoothing=0.0, dt=0.005,
-                         u_max=5.0) -> Config:
+                         u_max=5.0, n_replicas=1) -> Config:
+    """Contact chain; with n_replicas = R every candidate is rolled out under R
+    randomised models (rows r*B + b of sample_params) and its cost averaged."""
     task = chain_contact_task(seed, n_links)
     B = n_tensor + n_gauss
     return Config(name=name, dynamics=CHAIN_CONTACT, interp=interp, n_links=n_links,
@@ -217,7 +220,8 @@ def chain_contact_config(name="chain24_contact_c4", *, n_links=24, horizon=256,
                   smoothing=f32(smoothing), sigma_min=f32(0.05 * u_max),
                   sigma_init=f32(0.5 * u_max), u_min=f32(-u_max), u_max=f32(u_max),
                   dt=f32(dt), seed=seed, task=task,
-                  sample_params=domain_randomisation(seed, B, n_links, task.masses))
+                  sample_params=domain_randomisation(seed, n_replicas * B, n_links, task.masses),
+                  n_replicas=n_replicas)
 
 
 def c0() -> Config:

@@ -88,7 +88,22 @@ def candidates(cfg, mu, sigma, r, k):
 
 
 def rollout(cfg, x0, U, sample_index=None, keep_states=False):
-    """Costs s[b] = sum_t S[b, t]; optionally the states X[b, t] = x_{t+1}."""
+    """Costs s[b] = sum_t S[b, t]; optionally the states X[b, t] = x_{t+1}.
+
+    With R > 1 randomised models (online domain randomisation, Section 4
+    "Practical Settings") each candidate is rolled out under every model and
+    its cost is the mean over the R rollouts; states are those of model 0."""
+    R = int(getattr(cfg, "n_replicas", 1))
+    if R > 1:
+        B = cfg.n_samples
+        idx = np.arange(U.shape[0]) if sample_index is None else np.asarray(sample_index)
+        outs = [rollout(cfg.replace(n_replicas=1), x0, U, r * B + idx, keep_states and r == 0)
+                for r in range(R)]
+        if keep_states:
+            s = sum(o[0] if isinstance(o, tuple) else o for o in outs) / R
+            return np.where(np.isfinite(s), s, np.inf), outs[0][1]
+        s = sum(outs) / R
+        return np.where(np.isfinite(s), s, np.inf)
     model = dynamics.Model(cfg, sample_index)
     Bn = U.shape[0]
     x = np.broadcast_to(np.asarray(x0, np.float64), (Bn, len(x0))).copy()

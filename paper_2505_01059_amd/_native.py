@@ -27,7 +27,7 @@ class MtpError(RuntimeError):
 
 
 STAGE_CANDIDATES, STAGE_ROLLOUT, STAGE_TOPK, STAGE_UPDATE, STAGE_ALL = range(5)
-MTP_ABI_VERSION = 1
+MTP_ABI_VERSION = 2
 
 
 class mtp_config(ctypes.Structure):
@@ -41,6 +41,7 @@ class mtp_config(ctypes.Structure):
         ("seed", c_uint64),
         ("task_params", POINTER(c_float)), ("n_task_params", c_int32),
         ("sample_params", POINTER(c_float)), ("n_debug_states", c_int32),
+        ("n_replicas", c_int32),
     ]
 
 
@@ -167,6 +168,7 @@ def config_struct(cfg, n_debug_states=0):
         keep.append(sp)
         c.sample_params = sp.ctypes.data_as(POINTER(c_float))
     c.n_debug_states = int(n_debug_states)
+    c.n_replicas = int(getattr(cfg, "n_replicas", 1))
     return c, keep
 
 

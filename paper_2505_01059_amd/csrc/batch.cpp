@@ -282,7 +282,7 @@ mtp_status mtp::batch_create_internal(const mtp_config* cfgs, int32_t n, void* d
     c.task_params = b->task[i].data();
     if (c.dynamics == MTP_DYN_CHAIN_CONTACT) {
       const size_t B = static_cast<size_t>(c.n_tensor) + c.n_gauss;
-      b->sparams[i].assign(c.sample_params, c.sample_params + B * (c.ctrl_dim + 1));
+      b->sparams[i].assign(c.sample_params, c.sample_params + B * (c.ctrl_dim + 1) * static_cast<size_t>(c.n_replicas > 1 ? c.n_replicas : 1));
       c.sample_params = b->sparams[i].data();
     } else {
       c.sample_params = nullptr;

@@ -31,6 +31,7 @@ enum Interp : int32_t { kBspline = 0, kAkima = 1, kLinear = 2 };
 struct PlanDesc {
   int32_t dyn, interp, n_links, d, n, T, L, W, P, G, B, E, K, p, n_dbg, n_task;
   int32_t ldU;
+  int32_t R;             // randomised models per candidate (contact chain), cost averaged
   float lam, alpha, sigma_min, sigma_init, u_min, u_max, dt;
   uint32_t key0, key1;
   uint32_t* ctrl;        // [0] replan index r, [1] shift, [2] flags (bit 0: all elites +inf, bit 1: selection fault)
@@ -484,10 +485,6 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     K.invl[k] = 1.0f / K.l[k];
   }
   if constexpr (CONTACT) {
-    const float* sp = P.sparams + static_cast<size_t>(b) * (N + 1);
-#pragma unroll
-    for (int k = 0; k < N; ++k) K.im[k] = 1.0f / sp[k];
-    K.muf = sp[N];
     K.yg = tk[5 + 2 * N]; K.kc = tk[6 + 2 * N]; K.dc = tk[7 + 2 * N]; K.inv_vs = 1.0f / tk[8 + 2 * N];
   } else {
 #pragma unroll
@@ -495,6 +492,17 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
   }
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
+  // randomised models: the candidate's cost is the mean over R rollouts
+  const int R = CONTACT ? P.R : 1;
+  float total = 0.0f;
+#pragma unroll 1
+  for (int rep = 0; rep < R; ++rep) {
+  if constexpr (CONTACT) {
+    const float* sp = P.sparams + (static_cast<size_t>(rep) * P.B + b) * (N + 1);
+#pragma unroll
+    for (int k = 0; k < N; ++k) K.im[k] = 1.0f / sp[k];
+    K.muf = sp[N];
+  }
   float ph[N], om[N], s[N], c[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -557,7 +565,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     }
     const float dx = ex - K.tx, dy = ey - K.ty;
     cost += fmaf(K.wg, fmaf(dx, dx, dy * dy), K.wu * uu);
-    if (b < P.n_dbg) {
+    if (rep == 0 && b < P.n_dbg) {
       float* X = P.X + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
 #pragma unroll
@@ -569,7 +577,9 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
 #pragma unroll
     for (int k = 0; k < N; ++k) u[k] = un[k];
   }
-  P.cost[b] = finite_or_inf(cost);
+  total += cost;
+  }
+  P.cost[b] = finite_or_inf(R == 1 ? total : total / static_cast<float>(R));
 }
 
 // ------------------------------------------------------------------ quad-lane chain
@@ -955,18 +965,26 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     K.invl[i] = 1.0f / K.l[i];
   }
   if constexpr (CONTACT) {
-    const float* sp = P.sparams + static_cast<size_t>(b) * (N + 1);
-#pragma unroll
-    for (int i = 0; i < M; ++i) K.im[i] = 1.0f / sp[pair_link<N>(B, i)];
-    K.muf = sp[N];
     K.yg = tk[5 + 2 * N]; K.kc = tk[6 + 2 * N]; K.dc = tk[7 + 2 * N]; K.inv_vs = 1.0f / tk[8 + 2 * N];
   } else {
 #pragma unroll
     for (int i = 0; i < M; ++i) K.im[i] = 1.0f / tk[5 + pair_link<N>(B, i)];
     K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
+    K.im_mid_other = pswap(K.im[M - 1]);
   }
-  K.im_mid_other = pswap(K.im[M - 1]);
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
+  // randomised models: the candidate's cost is the mean over R rollouts
+  const int R = CONTACT ? P.R : 1;
+  float total = 0.0f;
+#pragma unroll 1
+  for (int rep = 0; rep < R; ++rep) {
+  if constexpr (CONTACT) {
+    const float* sp = P.sparams + (static_cast<size_t>(rep) * P.B + b) * (N + 1);
+#pragma unroll
+    for (int i = 0; i < M; ++i) K.im[i] = 1.0f / sp[pair_link<N>(B, i)];
+    K.muf = sp[N];
+    K.im_mid_other = pswap(K.im[M - 1]);
+  }
   float ph[M], om[M], s[M], c[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
@@ -1036,7 +1054,7 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     uu += pswap(uu);
     const float dx = ex - tgx, dy = ey - tgy;
     cost += fmaf(wg, fmaf(dx, dx, dy * dy), wu * uu);
-    if (b < P.n_dbg) {
+    if (rep == 0 && b < P.n_dbg) {
       float* X = P.X + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
 #pragma unroll
@@ -1049,7 +1067,9 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
 #pragma unroll
     for (int i = 0; i < M; ++i) u[i] = un[i];
   }
-  if (!B) P.cost[b] = finite_or_inf(cost);
+  total += cost;
+  }
+  if (!B) P.cost[b] = finite_or_inf(R == 1 ? total : total / static_cast<float>(R));
 }
 
 // ------------------------------------------------------------------ reductions

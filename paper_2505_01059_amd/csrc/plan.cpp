@@ -72,9 +72,11 @@ bool validate_config(const mtp_config* c, std::string* why, mtp_status* code) {
     return fail(MTP_ERR_INVALID_ARG, "need finite u_min < u_max");
   if (!(c->dt > 0.0f) || !std::isfinite(c->dt)) return fail(MTP_ERR_INVALID_ARG, "dt must be finite and > 0");
   if (c->n_debug_states < 0 || c->n_debug_states > B) return fail(MTP_ERR_INVALID_ARG, "n_debug_states must be in 0..B");
+  if (c->n_replicas < 0 || c->n_replicas > 64) return fail(MTP_ERR_INVALID_ARG, "n_replicas must be in 0..64");
   if (c->n_task_params < 0 || (c->n_task_params > 0 && c->task_params == nullptr))
     return fail(MTP_ERR_INVALID_ARG, "task_params missing");
   if (c->dynamics == MTP_DYN_POINT_MASS) {
+    if (c->n_replicas > 1) return fail(MTP_ERR_INVALID_ARG, "randomised replicas need the contact chain");
     if (c->n_task_params < 6) return fail(MTP_ERR_INVALID_ARG, "point mass task needs >= 6 parameters");
     const float nobs = c->task_params[5];
     if (!(nobs >= 0.0f) || nobs != std::floor(nobs) || nobs > static_cast<float>(kMaxObstacles) ||
@@ -91,12 +93,14 @@ bool validate_config(const mtp_config* c, std::string* why, mtp_status* code) {
     if (c->dynamics == MTP_DYN_CHAIN_CONTACT) {
       if (c->sample_params == nullptr) return fail(MTP_ERR_INVALID_ARG, "contact chain needs sample_params");
       if (!(c->task_params[8 + 2 * c->n_links] > 0.0f)) return fail(MTP_ERR_INVALID_ARG, "v_slip must be > 0");
-      const size_t rows = static_cast<size_t>(B);
+      const size_t rows = static_cast<size_t>(B) * static_cast<size_t>(c->n_replicas > 1 ? c->n_replicas : 1);
       for (size_t b = 0; b < rows; ++b)
         for (int k = 0; k < c->n_links; ++k)
           if (!(c->sample_params[b * (c->n_links + 1) + k] > 0.0f))
             return fail(MTP_ERR_INVALID_ARG, "sample masses must be > 0");
     }
+    if (c->dynamics == MTP_DYN_CHAIN && c->n_replicas > 1)
+      return fail(MTP_ERR_INVALID_ARG, "randomised replicas need the contact chain's per-sample table");
     if (!rollout_supported(c->dynamics, c->n_links))
       return fail(MTP_ERR_UNSUPPORTED, "chain length not instantiated in this build");
   }
@@ -123,7 +127,8 @@ Layout compute_layout(const mtp_config& c) {
   L.basis = take(T * kBasisStride * 4);
   L.span = take(T * 4);
   L.task = take(static_cast<size_t>(c.n_task_params) * 4);
-  L.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? take(B * (n + 1) * 4) : 0;
+  const size_t R = c.n_replicas > 1 ? static_cast<size_t>(c.n_replicas) : 1;
+  L.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? take(R * B * (n + 1) * 4) : 0;
   L.resident = off;
   off = 0;
   L.Z = take(static_cast<size_t>(c.n_layers) * c.n_width * n * 4);
@@ -262,6 +267,7 @@ PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uin
   P.T = c.horizon; P.L = c.n_layers; P.W = c.n_width; P.P = c.n_tensor; P.G = c.n_gauss;
   P.B = c.n_tensor + c.n_gauss; P.E = c.n_elites; P.K = c.n_iters; P.p = c.bspline_degree;
   P.n_dbg = c.n_debug_states; P.n_task = c.n_task_params; P.ldU = static_cast<int32_t>(L.ldU);
+  P.R = c.n_replicas > 1 ? c.n_replicas : 1;
   P.lam = c.temperature; P.alpha = c.smoothing; P.sigma_min = c.sigma_min; P.sigma_init = c.sigma_init;
   P.u_min = c.u_min; P.u_max = c.u_max; P.dt = c.dt;
   P.key0 = static_cast<uint32_t>(c.seed & 0xFFFFFFFFull);
@@ -298,7 +304,8 @@ mtp_status mtp::upload_plan_tables(const mtp_config& c, const PlanDesc& P, const
   cp(const_cast<float*>(P.basis), basis.data(), basis.size() * 4);
   cp(const_cast<int32_t*>(P.span), span.data(), span.size() * 4);
   cp(const_cast<float*>(P.task), task, static_cast<size_t>(c.n_task_params) * 4);
-  if (P.sparams) cp(const_cast<float*>(P.sparams), sparams, B * (c.ctrl_dim + 1) * 4);
+  const size_t R = c.n_replicas > 1 ? static_cast<size_t>(c.n_replicas) : 1;
+  if (P.sparams) cp(const_cast<float*>(P.sparams), sparams, R * B * (c.ctrl_dim + 1) * 4);
   cp(P.mu, mu.data(), Tn * 4);
   cp(P.sigma, sg.data(), Tn * 4);
   cp(P.ctrl, ctrl, sizeof(ctrl));
@@ -399,8 +406,9 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
   p->cfg = *cfg;
   p->task.assign(cfg->task_params, cfg->task_params + cfg->n_task_params);
   const size_t B = static_cast<size_t>(cfg->n_tensor) + cfg->n_gauss;
+  const size_t R = cfg->n_replicas > 1 ? static_cast<size_t>(cfg->n_replicas) : 1;
   if (cfg->dynamics == MTP_DYN_CHAIN_CONTACT)
-    p->sparams.assign(cfg->sample_params, cfg->sample_params + B * (cfg->ctrl_dim + 1));
+    p->sparams.assign(cfg->sample_params, cfg->sample_params + R * B * (cfg->ctrl_dim + 1));
   p->cfg.task_params = p->task.data();
   p->cfg.sample_params = p->sparams.empty() ? nullptr : p->sparams.data();
   p->lay = lay;

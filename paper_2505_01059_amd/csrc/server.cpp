@@ -316,7 +316,7 @@ static void copy_configs(mtp_server* s, const mtp_config* robots, int32_t n) {
     c.task_params = s->task[i].data();
     if (c.dynamics == MTP_DYN_CHAIN_CONTACT) {
       const size_t B = static_cast<size_t>(c.n_tensor) + c.n_gauss;
-      s->sparams[i].assign(c.sample_params, c.sample_params + B * (c.ctrl_dim + 1));
+      s->sparams[i].assign(c.sample_params, c.sample_params + B * (c.ctrl_dim + 1) * static_cast<size_t>(c.n_replicas > 1 ? c.n_replicas : 1));
       c.sample_params = s->sparams[i].data();
     } else {
       c.sample_params = nullptr;

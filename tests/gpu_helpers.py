@@ -53,6 +53,14 @@ def akima_ill_conditioned(cfg, I, Z):
 def switching_flags(cfg, x0, U, margin=1e-5):
     """Candidates whose oracle rollout passes within `margin` of a discontinuity."""
     B = U.shape[0]
+    R = int(getattr(cfg, "n_replicas", 1))
+    if R > 1:                    # any of the randomised models may sit on the surface
+        sp = np.asarray(cfg.sample_params).reshape(R, -1, cfg.sample_params.shape[1])
+        out = np.zeros(B, bool)
+        for r in range(R):
+            out |= switching_flags(cfg.replace(n_replicas=1, sample_params=np.ascontiguousarray(sp[r])),
+                                   x0, U, margin)
+        return out
     if cfg.dynamics == 0:
         s, X = OP.rollout(cfg, x0, U, keep_states=True)
         m = OD.point_mass_obstacle_margin(cfg.task, X)                    # (B, T)

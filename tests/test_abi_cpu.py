@@ -173,3 +173,26 @@ def test_linear_table_matches_oracle(L, T):
     for j in range(T):
         v = basis[j, 0] * C[:, span[j]] + basis[j, 1] * C[:, span[j] + 1]
         np.testing.assert_allclose(v, U[:, j], atol=1e-6)
+
+
+def test_replica_count_validation_and_workspace():
+    """R randomised models: contact chain only, 1..64, table of R*B rows."""
+    base = W.chain_contact_config(n_links=7, n_tensor=100, n_gauss=28, horizon=32, n_layers=6,
+                                  n_width=16, n_elites=8, n_iters=1)
+    r3 = W.chain_contact_config(n_links=7, n_tensor=100, n_gauss=28, horizon=32, n_layers=6,
+                                n_width=16, n_elites=8, n_iters=1, n_replicas=3)
+    assert N.validate(r3)[0] == 0
+    B, n = base.n_samples, base.n_links
+    grow = N.workspace_bytes(r3) - N.workspace_bytes(base)
+    assert 2 * B * (n + 1) * 4 <= grow <= 2 * B * (n + 1) * 4 + 512
+    st, why = N.validate(r3.replace(n_replicas=65))
+    assert st == 1 and "n_replicas" in why
+    st, why = N.validate(W.c0().replace(n_replicas=2))
+    assert st == 1 and "replicas" in why
+    st, why = N.validate(W.c1().replace(n_replicas=2))
+    assert st == 1 and "replicas" in why
+    # a table with a non-positive mass in the last replica is rejected
+    bad = r3.sample_params.copy()
+    bad[-1, 0] = 0.0
+    st, why = N.validate(r3.replace(sample_params=bad))
+    assert st == 1 and "masses" in why

@@ -41,6 +41,12 @@ def configs():
                                   n_gauss=70, horizon=24, n_layers=12, n_width=64, n_elites=16, n_iters=2),
         "contact24": W.chain_contact_config(name="contact24", n_tensor=200, n_gauss=56, horizon=48,
                                             n_elites=16, n_iters=2),
+        # online domain randomisation: cost averaged over R randomised models
+        "contact7_r3": W.chain_contact_config(name="contact7_r3", n_links=7, n_tensor=150, n_gauss=42,
+                                              horizon=40, n_layers=6, n_width=16, n_elites=16, n_iters=2,
+                                              n_replicas=3),
+        "contact24_r2": W.chain_contact_config(name="contact24_r2", n_tensor=100, n_gauss=28, horizon=32,
+                                               n_elites=12, n_iters=2, n_replicas=2),
         # corners of the (beta, E) plane named in the design ablation: PS, MPPI, TS-PS, TS-MPPI
         "corner_ps": W.point_mass_config(name="corner_ps", n_tensor=0, n_gauss=200, n_elites=1, n_iters=2),
         "corner_mppi": W.point_mass_config(name="corner_mppi", n_tensor=0, n_gauss=200, n_elites=200,

@@ -230,3 +230,40 @@ def test_linear_path_coverage_improves_with_graph_size():
     e1 = best_error(3, 3)
     e2 = best_error(5, 6)
     assert e2 < e1
+
+
+# ------------------------------------------------------------------ randomised replicas
+
+def _contact_small(R):
+    return W.chain_contact_config(name="contact_r", n_links=4, n_tensor=10, n_gauss=6, horizon=12,
+                                  n_layers=4, n_width=4, n_elites=4, n_iters=1, n_replicas=R)
+
+
+def test_identical_replicas_reduce_to_single_model():
+    """Online domain randomisation (Section 4): R copies of one model give that model's cost."""
+    one = _contact_small(1)
+    B = one.n_samples
+    three = _contact_small(3).replace(sample_params=np.tile(one.sample_params, (3, 1)))
+    U = np.random.default_rng(4).uniform(-2, 2, (B, one.horizon, one.ctrl_dim))
+    x0 = W.initial_state(one)
+    s1 = P.rollout(one, x0, U)
+    s3 = P.rollout(three, x0, U)
+    assert np.allclose(s3, s1, rtol=1e-13, atol=0)
+
+
+def test_replica_mean_is_permutation_invariant_and_bracketed():
+    """The averaged cost does not depend on the order of the R models, and lies
+    between the smallest and largest single-model cost of each candidate."""
+    cfg = _contact_small(3)
+    B = cfg.n_samples
+    U = np.random.default_rng(5).uniform(-2, 2, (B, cfg.horizon, cfg.ctrl_dim))
+    x0 = W.initial_state(cfg)
+    s = P.rollout(cfg, x0, U)
+    blocks = cfg.sample_params.reshape(3, B, -1)
+    perm = cfg.replace(sample_params=np.ascontiguousarray(blocks[[2, 0, 1]].reshape(3 * B, -1)))
+    assert np.allclose(P.rollout(perm, x0, U), s, rtol=1e-13, atol=0)
+    singles = np.stack([P.rollout(cfg.replace(n_replicas=1, sample_params=np.ascontiguousarray(blocks[r])), x0, U)
+                        for r in range(3)])
+    assert np.all(s >= singles.min(0) * (1 - 1e-12)) and np.all(s <= singles.max(0) * (1 + 1e-12))
+    # the models differ, so the mean is not any one of them
+    assert np.any(np.abs(singles[0] - s) > 1e-6 * np.abs(s))
