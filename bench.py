@@ -89,6 +89,23 @@ def cpu_baseline(cfg, x0):
     }
 
 
+def copy_probe(mib, reps):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings per dispatch
+    give the factor that turns the counters into bytes."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)                  # runtime copy (a blit kernel or a DMA engine)
+        torch.neg(src, out=dst)         # elementwise kernel with a copy's traffic
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,7 +117,12 @@ def main():
                     help="serving: Poisson request rates (req/s) to run, one after another")
     ap.add_argument("--duration", type=float, default=20.0, help="serving: measured seconds per rate")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serving: device-memory budget of the pool")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run device-to-device copies of this many MiB (the reference kernel that "
+                         "scales the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe_mib > 0:
+        return copy_probe(args.copy_probe_mib, max(args.steps, 1))
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(instances shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)

@@ -17,30 +17,42 @@ __global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) 
   cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, sm);
 }
 
+// The dispatcher hands workgroup g to XCD g mod 8, and each XCD has its own L2.
+// Rollout workgroups of 16..64 candidates read 64..256 B of every U row, less
+// than or equal to an L2 line, so neighbouring workgroups share lines: give each
+// XCD one contiguous run of workgroup indices so that a line is fetched into one
+// L2 only.  A bijection of [0, G) for any G.
+__device__ __forceinline__ int xcd_contiguous_block(int g, int G) {
+  constexpr int kXcds = 8;
+  const int x = g % kXcds, i = g / kXcds;
+  const int per = G / kXcds, rem = G % kXcds;
+  return x * per + min(x, rem) + i;
+}
+
 __global__ __launch_bounds__(kRollThreads) void k_rollout_point_mass(PlanDesc P) {
   __shared__ PointMassSmem sm;
   stage_obstacles(P, sm);
   __syncthreads();
-  const int b = blockIdx.x * kRollThreads + threadIdx.x;
+  const int b = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
   if (b < P.B) rollout_point_mass(P, b, sm);
 }
 
 template <int N, bool CONTACT>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_chain(PlanDesc P) {
-  const int b = blockIdx.x * kRollThreads + threadIdx.x;
+  const int b = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
   if (b < P.B) rollout_chain<N, CONTACT>(P, b);
 }
 
 template <int N, bool CONTACT>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_chain_pair(PlanDesc P) {
-  const int g = blockIdx.x * kRollThreads + threadIdx.x;
+  const int g = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
   const int b = g >> 1;
   if (b < P.B) rollout_chain_pair<N, CONTACT>(P, b, (g & 1) != 0);
 }
 
 template <int N>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_chain_quad(PlanDesc P) {
-  const int g = blockIdx.x * kRollThreads + threadIdx.x;
+  const int g = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
   const int b = g >> 2;
   if (b < P.B) rollout_chain_quad<N>(P, b, g & 3);
 }

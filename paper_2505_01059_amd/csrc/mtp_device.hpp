@@ -602,7 +602,7 @@ constexpr int kQXor2 = qperm_ctrl(2, 3, 0, 1);
 
 template <int CTRL>
 __device__ __forceinline__ float qperm(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float quad_sum(float v) {
@@ -615,82 +615,82 @@ constexpr bool quad_chain_links() { return N >= 5 && N <= 8; }
 
 __host__ __device__ constexpr bool is_quad_chain(int dyn, int n) { return dyn == kChain && n >= 5 && n <= 8; }
 
+// Per-lane constants.  Rows past the chain end and couplings to links that do
+// not exist are handled by zero coefficients instead of branches: every inverse
+// mass that multiplies a missing coupling is stored as 0 here, and the diagonal
+// of a padded row is 1, so the padded rows solve to zero tension and zero
+// acceleration with the same instructions as real rows.
 struct QuadChain {
-  float l0, l1, invl0, invl1, im0, im1, imp;   // own links r0 = 2s, r1 = 2s+1; imp: link r0-1
-  bool v0, v1;                                  // rows inside the chain
-  bool nxt1;                                    // link r1+1 exists
-  int s;                                        // lane within the quad
-  float g;
+  float l0, l1, invl0, invl1;   // own links r0 = 2s, r1 = 2s+1 (padded: 1)
+  float De, Do;                 // diagonals of rows r0, r1 (padded: 1)
+  float imD0, imD1;             // im[r0] + im[r0-1], im[r1] + im[r0] (padded: 0)
+  float imU0;                   // im[r0]: coupling r0 - r1 (0 unless r1 exists)
+  float imU1;                   // im[r1]: coupling r1 - r1+1 (0 unless r1+1 exists)
+  float impV;                   // im[r0-1]: coupling r0-1 - r0 (0 on lane 0 or padded r0)
+  float g0;                     // gravity on lane 0, 0 elsewhere
+  float v0f, v1f, nxt1f;        // 1 where row r0 / r1 / link r1+1 exists
 };
+
+template <int CTRL>
+__device__ __forceinline__ float qmul(float a, float b) { return qperm<CTRL>(a) * b; }
 
 // Accelerations of the lane's two links from the stage angles' sin/cos, the
 // stage angular velocities and the per-step torque terms
 // q0, q1 (own links), qp (link r0-1), qn (link r1+1).
 __device__ __forceinline__ void quad_accel(float s0, float c0, float s1, float c1, float w0, float w1, float q0,
                                            float q1, float qp, float qn, const QuadChain& K, float& a0, float& a1) {
-  const int s = K.s;
   const float sN = qperm<kQNext1>(s0), cN = qperm<kQNext1>(c0);
-  const float Cn0 = K.v1 ? fmaf(c0, c1, s0 * s1) : 0.0f;
-  const float Sn0 = K.v1 ? fmaf(s0, c1, -c0 * s1) : 0.0f;
-  const float Cn1 = K.nxt1 ? fmaf(c1, cN, s1 * sN) : 0.0f;
-  const float Sn1 = K.nxt1 ? fmaf(s1, cN, -c1 * sN) : 0.0f;
-  const float Cp0 = qperm<kQPrev1>(Cn1), Sp0 = qperm<kQPrev1>(Sn1);
-  const float Cp = (s > 0) ? Cp0 : 0.0f, Sp = (s > 0) ? Sp0 : 0.0f;   // link r0-1 against r0
+  const float Cn0 = fmaf(c0, c1, s0 * s1);           // links r0, r1
+  const float Sn0 = fmaf(s0, c1, -c0 * s1);
+  const float Cn1 = fmaf(c1, cN, s1 * sN);           // links r1, r1+1
+  const float Sn1 = fmaf(s1, cN, -c1 * sN);
+  const float Cp = qperm<kQPrev1>(Cn1), Sp = qperm<kQPrev1>(Sn1);   // links r0-1, r0
   // tension rows r0 (even) and r1 (odd): Lo x_{r-1} + D x_r + Up x_{r+1} = R
-  float De = K.im0 + K.imp, Ue = -K.im0 * Cn0, Le = -K.imp * Cp;
-  float Re = fmaf(K.l0 * w0, w0, fmaf(-K.im0 * q1, Sn0, K.imp * qp * Sp));
-  if (s == 0) Re = fmaf(K.g, c0, Re);
-  float Do = K.im1 + K.im0, Uo = -K.im1 * Cn1, Lo = -K.im0 * Cn0;
-  float Ro = fmaf(K.l1 * w1, w1, fmaf(-K.im1 * qn, Sn1, K.im0 * q0 * Sn0));
-  if (!K.v0) { De = 1.0f; Ue = 0.0f; Le = 0.0f; Re = 0.0f; }
-  if (!K.v1) { Do = 1.0f; Uo = 0.0f; Lo = 0.0f; Ro = 0.0f; }
+  const float Ue = -K.imU0 * Cn0, Le = -K.impV * Cp;
+  const float Re = fmaf(K.l0 * w0, w0, fmaf(-K.imU0 * q1, Sn0, fmaf(K.impV * qp, Sp, K.g0 * c0)));
+  const float Uo = -K.imU1 * Cn1, Lo = Ue;
+  const float Ro = fmaf(K.l1 * w1, w1, fmaf(-K.imU1 * qn, Sn1, K.imU0 * q0 * Sn0));
   // eliminate the even unknowns from the odd rows
-  const float iDe = __builtin_amdgcn_rcpf(De);
-  const float Le2 = qperm<kQNext1>(Le), iDe2 = qperm<kQNext1>(iDe), Ue2 = qperm<kQNext1>(Ue),
-              Re2 = qperm<kQNext1>(Re);
+  const float iDe = __builtin_amdgcn_rcpf(K.De);
   const float al = Lo * iDe;
-  const float ga = (s < 3) ? Uo * iDe2 : 0.0f;
+  const float ga = qmul<kQNext1>(iDe, Uo);
   float A = -al * Le;
-  float Bv = fmaf(-ga, Le2, fmaf(-al, Ue, Do));
-  float C = (s < 3) ? -ga * Ue2 : 0.0f;
-  float R = fmaf(-ga, Re2, fmaf(-al, Re, Ro));
-  // parallel cyclic reduction of the four odd rows, distance 1
+  float Bv = fmaf(-ga, qperm<kQNext1>(Le), fmaf(-al, Ue, K.Do));
+  float C = -ga * qperm<kQNext1>(Ue);
+  float R = fmaf(-ga, qperm<kQNext1>(Re), fmaf(-al, Re, Ro));
+  // parallel cyclic reduction of the four odd rows, distance 1 (A = 0 on lane
+  // 0 and C = 0 on lane 3 already, so the wrapped neighbours contribute 0)
   {
     const float iB = __builtin_amdgcn_rcpf(Bv);
-    const float Ap = qperm<kQPrev1>(A), iBp = qperm<kQPrev1>(iB), Cp1 = qperm<kQPrev1>(C), Rp = qperm<kQPrev1>(R);
-    const float An = qperm<kQNext1>(A), iBn = qperm<kQNext1>(iB), Cn = qperm<kQNext1>(C), Rn = qperm<kQNext1>(R);
-    const float x1 = (s > 0) ? -A * iBp : 0.0f;
-    const float y1 = (s < 3) ? -C * iBn : 0.0f;
+    const float x1 = -A * qperm<kQPrev1>(iB);
+    const float y1 = -C * qperm<kQNext1>(iB);
+    const float Ap = qperm<kQPrev1>(A), Cp1 = qperm<kQPrev1>(C), Rp = qperm<kQPrev1>(R);
+    const float An = qperm<kQNext1>(A), Cn = qperm<kQNext1>(C), Rn = qperm<kQNext1>(R);
     Bv = fmaf(y1, An, fmaf(x1, Cp1, Bv));
     R = fmaf(y1, Rn, fmaf(x1, Rp, R));
-    A = (s > 0) ? x1 * Ap : 0.0f;
-    C = (s < 3) ? y1 * Cn : 0.0f;
+    A = x1 * Ap;
+    C = y1 * Cn;
   }
   // distance 2
   {
     const float iB = __builtin_amdgcn_rcpf(Bv);
-    const float iBp = qperm<kQPrev2>(iB), Cp2 = qperm<kQPrev2>(C), Rp = qperm<kQPrev2>(R);
-    const float iBn = qperm<kQNext2>(iB), An = qperm<kQNext2>(A), Rn = qperm<kQNext2>(R);
-    const float x2 = (s >= 2) ? -A * iBp : 0.0f;
-    const float y2 = (s <= 1) ? -C * iBn : 0.0f;
-    Bv = fmaf(y2, An, fmaf(x2, Cp2, Bv));
-    R = fmaf(y2, Rn, fmaf(x2, Rp, R));
+    const float x2 = -A * qperm<kQPrev2>(iB);
+    const float y2 = -C * qperm<kQNext2>(iB);
+    Bv = fmaf(y2, qperm<kQNext2>(A), fmaf(x2, qperm<kQPrev2>(C), Bv));
+    R = fmaf(y2, qperm<kQNext2>(R), fmaf(x2, qperm<kQPrev2>(R), R));
   }
   const float xo = R * __builtin_amdgcn_rcpf(Bv);              // tension of link r1
-  const float xop = qperm<kQPrev1>(xo);
-  const float xo_prev = (s > 0) ? xop : 0.0f;                   // tension of link r0-1
+  const float xo_prev = qperm<kQPrev1>(xo);                     // tension of link r0-1
   const float xe = fmaf(-Le, xo_prev, fmaf(-Ue, xo, Re)) * iDe; // tension of link r0
-  const float xen = qperm<kQNext1>(xe);
-  const float xe_next = (s < 3) ? xen : 0.0f;                   // tension of link r1+1
-  float A0 = (K.im0 + K.imp) * q0;
-  A0 = fmaf(-K.im0, fmaf(xo, Sn0, q1 * Cn0), A0);
-  A0 = fmaf(-K.imp, fmaf(-xo_prev, Sp, qp * Cp), A0);
-  if (s == 0) A0 = fmaf(-K.g, s0, A0);
-  float A1 = (K.im1 + K.im0) * q1;
-  A1 = fmaf(-K.im1, fmaf(xe_next, Sn1, qn * Cn1), A1);
-  A1 = fmaf(-K.im0, fmaf(-xe, Sn0, q0 * Cn0), A1);
-  a0 = K.v0 ? A0 * K.invl0 : 0.0f;
-  a1 = K.v1 ? A1 * K.invl1 : 0.0f;
+  const float xe_next = qperm<kQNext1>(xe);                     // tension of link r1+1
+  float A0 = fmaf(K.imD0, q0, -K.g0 * s0);
+  A0 = fmaf(-K.imU0, fmaf(xo, Sn0, q1 * Cn0), A0);
+  A0 = fmaf(-K.impV, fmaf(-xo_prev, Sp, qp * Cp), A0);
+  float A1 = K.imD1 * q1;
+  A1 = fmaf(-K.imU1, fmaf(xe_next, Sn1, qn * Cn1), A1);
+  A1 = fmaf(-K.imU0, fmaf(-xe, Sn0, q0 * Cn0), A1);
+  a0 = A0 * K.invl0;
+  a1 = A1 * K.invl1;
 }
 
 // One candidate b per quad; s is the lane within the quad.  All four lanes of a
@@ -700,40 +700,52 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
   static_assert(N >= 5 && N <= 8, "quad-lane chain covers 5..8 links");
   const float* tk = P.task;
   QuadChain K;
-  K.s = s;
   const int r0 = 2 * s, r1 = 2 * s + 1;
-  K.v0 = r0 < N;
-  K.v1 = r1 < N;
-  K.nxt1 = r1 + 1 < N;
-  K.g = tk[0];
+  const bool v0 = r0 < N, v1 = r1 < N, nxt1 = r1 + 1 < N;
+  const float g = tk[0];
   const float wg = tk[1], wu = tk[2], tx = tk[3], ty = tk[4];
-  K.l0 = K.v0 ? tk[5 + N + r0] : 1.0f;
-  K.l1 = K.v1 ? tk[5 + N + r1] : 1.0f;
+  const float im0 = v0 ? 1.0f / tk[5 + r0] : 0.0f;
+  const float im1 = v1 ? 1.0f / tk[5 + r1] : 0.0f;
+  const float imp = (r0 > 0 && r0 - 1 < N) ? 1.0f / tk[5 + r0 - 1] : 0.0f;
+  K.l0 = v0 ? tk[5 + N + r0] : 1.0f;
+  K.l1 = v1 ? tk[5 + N + r1] : 1.0f;
   K.invl0 = 1.0f / K.l0;
   K.invl1 = 1.0f / K.l1;
-  K.im0 = K.v0 ? 1.0f / tk[5 + r0] : 0.0f;
-  K.im1 = K.v1 ? 1.0f / tk[5 + r1] : 0.0f;
-  K.imp = (r0 > 0 && r0 - 1 < N) ? 1.0f / tk[5 + r0 - 1] : 0.0f;
+  K.De = v0 ? im0 + imp : 1.0f;
+  K.Do = v1 ? im1 + im0 : 1.0f;
+  K.imD0 = v0 ? im0 + imp : 0.0f;
+  K.imD1 = v1 ? im1 + im0 : 0.0f;
+  K.imU0 = v1 ? im0 : 0.0f;
+  K.imU1 = nxt1 ? im1 : 0.0f;
+  K.impV = v0 ? imp : 0.0f;
+  K.g0 = (s == 0) ? g : 0.0f;
+  K.v0f = v0 ? 1.0f : 0.0f;
+  K.v1f = v1 ? 1.0f : 0.0f;
+  K.nxt1f = nxt1 ? 1.0f : 0.0f;
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
-  float ph0 = K.v0 ? P.x0[r0] : 0.0f, ph1 = K.v1 ? P.x0[r1] : 0.0f;
-  float om0 = K.v0 ? P.x0[N + r0] : 0.0f, om1 = K.v1 ? P.x0[N + r1] : 0.0f;
+  float ph0 = v0 ? P.x0[r0] : 0.0f, ph1 = v1 ? P.x0[r1] : 0.0f;
+  float om0 = v0 ? P.x0[N + r0] : 0.0f, om1 = v1 ? P.x0[N + r1] : 0.0f;
   float s0, c0, s1, c1;
   hw_sincos(ph0, &s0, &c0);
   hw_sincos(ph1, &s1, &c1);
+  // controls of padded rows are read from the last real row and zeroed by v0f/v1f
   const size_t ld = static_cast<size_t>(P.ldU);
-  const float* ub = P.U + b;
-  float u0 = K.v0 ? ub[r0 * ld] : 0.0f, u1 = K.v1 ? ub[r1 * ld] : 0.0f;
+  const float* p0 = P.U + b + static_cast<size_t>(v0 ? r0 : N - 1) * ld;
+  const float* p1 = P.U + b + static_cast<size_t>(v1 ? r1 : N - 1) * ld;
+  const size_t row = static_cast<size_t>(N) * ld;
+  float u0 = K.v0f * *p0, u1 = K.v1f * *p1;
   float cost = 0.0f;
   for (int t = 0; t < P.T; ++t) {
-    const bool more = (t + 1 < P.T);
-    const float un0 = (more && K.v0) ? ub[((t + 1) * N + r0) * ld] : 0.0f;
-    const float un1 = (more && K.v1) ? ub[((t + 1) * N + r1) * ld] : 0.0f;
+    // next step's controls (the last step re-reads its own row)
+    const size_t adv = (t + 1 < P.T) ? row : 0;
+    p0 += adv;
+    p1 += adv;
+    const float un0 = K.v0f * *p0;
+    const float un1 = K.v1f * *p1;
     // torque terms of this step
-    const float u0n = qperm<kQNext1>(u0);
     const float q0 = (u0 - u1) * K.invl0;
-    const float q1 = (u1 - (K.nxt1 ? u0n : 0.0f)) * K.invl1;
-    const float qpv = qperm<kQPrev1>(q1), qnv = qperm<kQNext1>(q0);
-    const float qp = (s > 0) ? qpv : 0.0f, qn = (K.nxt1 && s < 3) ? qnv : 0.0f;
+    const float q1 = fmaf(-K.nxt1f, qperm<kQNext1>(u0), u1) * K.invl1;
+    const float qp = qperm<kQPrev1>(q1), qn = qperm<kQNext1>(q0);
 
     float k0, k1;
     quad_accel(s0, c0, s1, c1, om0, om1, q0, q1, qp, qn, K, k0, k1);
@@ -753,13 +765,16 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
       aom0 = fmaf(wgt, k0, aom0);
       aom1 = fmaf(wgt, k1, aom1);
     }
-    if (K.v0) { ph0 = fmaf(dt6, aph0, ph0); om0 = fmaf(dt6, aom0, om0); }
-    if (K.v1) { ph1 = fmaf(dt6, aph1, ph1); om1 = fmaf(dt6, aom1, om1); }
+    // padded rows have zero velocity and acceleration, so their angle stays 0
+    ph0 = fmaf(dt6, aph0, ph0);
+    om0 = fmaf(dt6, aom0, om0);
+    ph1 = fmaf(dt6, aph1, ph1);
+    om1 = fmaf(dt6, aom1, om1);
     hw_sincos(ph0, &s0, &c0);
     hw_sincos(ph1, &s1, &c1);
-    float ex = 0.0f, ey = 0.0f;
-    if (K.v0) { ex = K.l0 * s0; ey = -K.l0 * c0; }
-    if (K.v1) { ex = fmaf(K.l1, s1, ex); ey = fmaf(-K.l1, c1, ey); }
+    const float l0v = K.v0f * K.l0, l1v = K.v1f * K.l1;
+    float ex = fmaf(l0v, s0, l1v * s1);
+    float ey = -fmaf(l0v, c0, l1v * c1);
     const float uu = fmaf(u0, u0, u1 * u1);
     ex = quad_sum(ex);
     ey = quad_sum(ey);
@@ -769,8 +784,8 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     if (b < P.n_dbg) {
       float* X = P.X + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
-      if (K.v0) { X[(t * 2 * N + r0) * ldx] = ph0; X[(t * 2 * N + N + r0) * ldx] = om0; }
-      if (K.v1) { X[(t * 2 * N + r1) * ldx] = ph1; X[(t * 2 * N + N + r1) * ldx] = om1; }
+      if (v0) { X[(t * 2 * N + r0) * ldx] = ph0; X[(t * 2 * N + N + r0) * ldx] = om0; }
+      if (v1) { X[(t * 2 * N + r1) * ldx] = ph1; X[(t * 2 * N + N + r1) * ldx] = om1; }
     }
     u0 = un0;
     u1 = un1;
