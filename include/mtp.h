@@ -112,10 +112,13 @@ typedef struct {
   uint64_t seed;             /* Philox key */
   const float* task_params;  /* host */
   int32_t n_task_params;
-  const float* sample_params;  /* host, CHAIN_CONTACT only, B*(n+1) floats */
+  const float* sample_params;  /* host, CHAIN_CONTACT only, R*B*(n+1) floats */
   int32_t n_debug_states;    /* record x_{t+1} of candidates 0..n_debug_states-1 (0 = off) */
   int32_t n_replicas;        /* R >= 1 randomised models per candidate (R > 1: CHAIN_CONTACT only);
                                 0 is read as 1 */
+  int32_t sample_wor;        /* 0: tensor path indices drawn with replacement (Alg. 1);
+                                1: without replacement (Section 3.2), needs P <= W^L */
+  int32_t diagnostics;       /* bit 0: record the cost entropy of every CEM iteration (Section 5.1) */
 } mtp_config;
 
 /*
@@ -132,9 +135,12 @@ typedef struct {
  *   x0         float [d]              start state of the current replan
  *   action     float [n]
  *   X_dbg      float [T][d][n_debug_states] or NULL (model 0 when R > 1)
+ *   entropy    float [K]              cost entropy H = -sum_b P_b log P_b, P = softmax(cost) over the
+ *                                     finite costs, of every iteration of the last replan
+ *                                     (written only when cfg.diagnostics bit 0 is set)
  */
 typedef struct {
-  void *Z, *I, *U, *cost, *elite_idx, *elite_cost, *weights, *mu, *sigma, *x0, *action, *X_dbg;
+  void *Z, *I, *U, *cost, *elite_idx, *elite_cost, *weights, *mu, *sigma, *x0, *action, *X_dbg, *entropy;
   size_t ld_U;
 } mtp_buffers;
 

@@ -92,6 +92,8 @@ class Config:
     task: object
     sample_params: Optional[np.ndarray] = None   # (R*B, n+1) float32: link masses, friction
     n_replicas: int = 1                          # R randomised models per candidate (contact chain)
+    sample_wor: int = 0                          # 1: tensor paths drawn without replacement
+    diagnostics: int = 0                         # bit 0: record the cost entropy per iteration
 
     @property
     def n_samples(self) -> int:

@@ -17,6 +17,9 @@ no layout; this one is shared with the GPU path by specification only):
   tag 1 (graph waypoints Z): item = layer l; element w*n + j
   tag 2 (path indices I):    item = tensor path p; element l
   tag 3 (local noise eps):   item = local sample g; element j*ceil(T/4)*4 + t
+  tag 4 (path permutation):  block = round i, item = digit group g (g < ceil(L/4):
+                             key digits 4g..4g+3, one per word; g = ceil(L/4):
+                             words 0, 1 are the round's bit-function key)
   element e lives in word e % 4 of block e // 4.
 """
 import numpy as np
@@ -28,7 +31,7 @@ _W1 = 0xBB67AE85
 _MASK = np.uint64(0xFFFFFFFF)
 _S32 = np.uint64(32)
 
-TAG_Z, TAG_I, TAG_EPS = 1, 2, 3
+TAG_Z, TAG_I, TAG_EPS, TAG_PERM = 1, 2, 3, 4
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):

@@ -66,7 +66,10 @@ def gaussian_noise(cfg, r, k):
 def tensor_samples(cfg, r, k):
     Z = sampling.waypoints(cfg.seed, r, k, cfg.n_layers, cfg.n_width, cfg.ctrl_dim,
                            cfg.u_min, cfg.u_max)
-    I = sampling.path_indices(cfg.seed, r, k, cfg.n_tensor, cfg.n_layers, cfg.n_width)
+    if getattr(cfg, "sample_wor", 0):
+        I = sampling.path_indices_without_replacement(cfg.seed, r, k, cfg.n_tensor, cfg.n_layers, cfg.n_width)
+    else:
+        I = sampling.path_indices(cfg.seed, r, k, cfg.n_tensor, cfg.n_layers, cfg.n_width)
     C = sampling.gather(Z, I).astype(np.float64)
     if cfg.interp == 0:
         UG = interp.bspline_interp(C, cfg.bspline_degree, cfg.horizon)
@@ -147,6 +150,20 @@ def refit(U, s, iE, mu, sigma, cfg):
     return mu_new + a * (mu - mu_new), sd_new + a * (sigma - sd_new), w
 
 
+def cost_entropy(s):
+    """Exploration diagnostic of Section 5.1: H = -sum_j P_j log P_j with
+    P_j = exp(J_j) / sum_l exp(J_l) over the batch of rollout costs J (the sign
+    as printed).  Non-finite costs are left out; no finite cost gives 0."""
+    J = np.asarray(s, dtype=np.float64)
+    J = J[np.isfinite(J)]
+    if J.size == 0:
+        return 0.0
+    e = np.exp(J - J.max())
+    Pj = e / e.sum()
+    nz = Pj > 0
+    return float(-np.sum(Pj[nz] * np.log(Pj[nz])))
+
+
 def iterate(cfg, x0, mu, sigma, r, k, sample_index=None, keep_states=False):
     """One CEM iteration; returns every intermediate in a dict."""
     Z, I, U = candidates(cfg, mu, sigma, r, k)
@@ -157,7 +174,7 @@ def iterate(cfg, x0, mu, sigma, r, k, sample_index=None, keep_states=False):
     iE = top_elites(s, cfg.n_elites)
     mu2, sg2, w = refit(U, s, iE, mu, sigma, cfg)
     return dict(Z=Z, I=I, U=U, s=s, X=X, iE=iE, w=w, mu=mu2, sigma=sg2,
-                action=U[iE[0], 0, :].copy())
+                action=U[iE[0], 0, :].copy(), entropy=cost_entropy(s))
 
 
 def replan(cfg, x0, mu, sigma, r, shift=1):

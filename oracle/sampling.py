@@ -38,3 +38,80 @@ def gather(Z, I):
     """Alg. 1, second line: C[p, l, :] = Z[l, I[p, l], :]."""
     L = Z.shape[0]
     return Z[np.arange(L)[None, :], I, :]                   # (P, L, n)
+
+
+# ---------------------------------------------------------------- without replacement
+# Section 3.2 names sampling paths without replacement as the more diverse but
+# costlier variant.  Here path p (0 <= p < P <= W**L) is the image of p under a
+# keyed permutation of the W**L path numbers, so distinct p give distinct paths.
+# The permutation is the swap-or-not shuffle of Hoang, Morris and Rogaway
+# (CRYPTO 2012): each round i has a key K_i in [0, W**L) and a bit function F_i;
+# x is replaced by x' = (K_i - x) mod W**L when F_i(max(x, x')) = 1.  Path
+# number x names the layer indices by its base-W digits, layer l being digit l
+# (least significant first).  Keys and bit functions come from Philox stream 4.
+# Python integers carry the modular arithmetic exactly at any W**L.
+
+def perm_rounds(n_layers, n_width):
+    """2 L ceil(log2 W) rounds (at least 2 L)."""
+    bits = max(1, int(n_width - 1).bit_length())
+    return 2 * n_layers * bits
+
+
+def perm_round_keys(seed, r, k, n_layers, n_width):
+    """Per round: the key K_i (a Python int below W**L) and the two words of the
+    bit function's Philox key."""
+    R = perm_rounds(n_layers, n_width)
+    groups = (n_layers + 3) // 4
+    k0, k1 = philox.key_of(seed)
+    c3 = (philox.TAG_PERM << 16) | (int(k) & 0xFFFF)
+    keys, fkeys = [], []
+    for i in range(R):
+        K = 0
+        for l in range(n_layers):
+            w = philox.philox4x32_10(i, l // 4, int(r) & 0xFFFFFFFF, c3, k0, k1)[l % 4]
+            K += int(philox.index_of(w, n_width)) * n_width ** l
+        w = philox.philox4x32_10(i, groups, int(r) & 0xFFFFFFFF, c3, k0, k1)
+        keys.append(K)
+        fkeys.append((int(w[0]), int(w[1])))
+    return keys, fkeys
+
+
+def digits(x, n_layers, n_width):
+    """Base-W digits of the path numbers x (least significant first): (len(x), L) int64."""
+    out = np.zeros((len(x), n_layers), dtype=np.int64)
+    for i, v in enumerate(x):
+        v = int(v)
+        for l in range(n_layers):
+            v, out[i, l] = divmod(v, n_width)
+    return out
+
+
+def perm_bit(x, fkey, n_layers, n_width):
+    """F(x): bit 0 of Philox word 0 with key fkey and the digits of x packed as
+    bytes (digit l in byte l % 4 of counter word l // 4)."""
+    d = digits(x, n_layers, n_width)
+    words = np.zeros((len(x), 4), dtype=np.uint64)
+    for l in range(n_layers):
+        words[:, l // 4] |= d[:, l].astype(np.uint64) << np.uint64(8 * (l % 4))
+    w0 = philox.philox4x32_10(words[:, 0], words[:, 1], words[:, 2], words[:, 3], fkey[0], fkey[1])[0]
+    return (w0 & 1).astype(bool)
+
+
+def perm_round(x, K, fkey, n_layers, n_width):
+    """One swap-or-not round on a list of path numbers (an involution)."""
+    D = n_width ** n_layers
+    xp = [(K - v) % D for v in x]
+    hi = [max(a, b) for a, b in zip(x, xp)]
+    flip = perm_bit(hi, fkey, n_layers, n_width)
+    return [b if f else a for a, b, f in zip(x, xp, flip)]
+
+
+def path_indices_without_replacement(seed, r, k, n_paths, n_layers, n_width):
+    """I[p, l] = digit l of pi(p): P distinct paths of the W**L."""
+    if n_paths > n_width ** n_layers:
+        raise ValueError("more paths requested than the graph holds")
+    keys, fkeys = perm_round_keys(seed, r, k, n_layers, n_width)
+    x = list(range(n_paths))
+    for K, fk in zip(keys, fkeys):
+        x = perm_round(x, K, fk, n_layers, n_width)
+    return digits(x, n_layers, n_width)

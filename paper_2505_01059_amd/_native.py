@@ -41,14 +41,14 @@ class mtp_config(ctypes.Structure):
         ("seed", c_uint64),
         ("task_params", POINTER(c_float)), ("n_task_params", c_int32),
         ("sample_params", POINTER(c_float)), ("n_debug_states", c_int32),
-        ("n_replicas", c_int32),
+        ("n_replicas", c_int32), ("sample_wor", c_int32), ("diagnostics", c_int32),
     ]
 
 
 class mtp_buffers(ctypes.Structure):
     _fields_ = [(name, c_void_p) for name in
                 ("Z", "I", "U", "cost", "elite_idx", "elite_cost", "weights", "mu", "sigma", "x0",
-                 "action", "X_dbg")] + [("ld_U", c_size_t)]
+                 "action", "X_dbg", "entropy")] + [("ld_U", c_size_t)]
 
 
 _LIB = None
@@ -169,6 +169,8 @@ def config_struct(cfg, n_debug_states=0):
         c.sample_params = sp.ctypes.data_as(POINTER(c_float))
     c.n_debug_states = int(n_debug_states)
     c.n_replicas = int(getattr(cfg, "n_replicas", 1))
+    c.sample_wor = int(getattr(cfg, "sample_wor", 0))
+    c.diagnostics = int(getattr(cfg, "diagnostics", 0))
     return c, keep
 
 
@@ -348,6 +350,7 @@ def _buffer_views(b, cfg, workspace, n_debug):
         sigma=view(b.sigma, torch.float32, (T, n)),
         x0=view(b.x0, torch.float32, (d,)),
         action=view(b.action, torch.float32, (n,)),
+        entropy=view(b.entropy, torch.float32, (cfg.n_iters,)),
     )
     out["X"] = view(b.X_dbg, torch.float32, (T, d, n_debug)) if n_debug > 0 else None
     out["ld_U"] = ld

@@ -34,9 +34,11 @@ uint32_t items_for(const mtp_config& c, int k_begin, int k_end) {
   const int B = c.n_tensor + c.n_gauss;
   const bool quad = is_quad_chain(c.dynamics, c.n_links);
   const bool pair = is_pair_chain(c.dynamics, c.n_links);
-  const uint32_t per_iter = host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhCand, quad, pair) +
-                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhRoll, quad, pair) + 1u +
-                            host_phase_tiles(B, c.horizon, c.ctrl_dim, kPhUpd, quad, pair);
+  const int Pn = c.n_tensor;
+  const uint32_t per_iter = host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhPaths, quad, pair) +
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhCand, quad, pair) +
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhRoll, quad, pair) + 1u +
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhUpd, quad, pair);
   return 1u + per_iter * static_cast<uint32_t>(k_end - k_begin);
 }
 
@@ -492,7 +494,7 @@ mtp_status mtp_batch_get_buffers(const mtp_batch* b, int32_t i, mtp_buffers* out
   const PlanDesc& P = b->descs[i];
   out->Z = P.Z; out->I = P.I; out->U = P.U; out->cost = P.cost; out->elite_idx = P.eidx;
   out->elite_cost = P.ecost; out->weights = P.w; out->mu = P.mu; out->sigma = P.sigma; out->x0 = P.x0;
-  out->action = P.action; out->X_dbg = P.X; out->ld_U = static_cast<size_t>(P.ldU);
+  out->action = P.action; out->X_dbg = P.X; out->entropy = P.entropy; out->ld_U = static_cast<size_t>(P.ldU);
   return MTP_OK;
 }
 

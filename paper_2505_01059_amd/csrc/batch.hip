@@ -21,6 +21,7 @@ namespace mtp {
 __device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phase) {
   switch (phase) {
     case kPhShift: return 1u;
+    case kPhPaths: return P.P > 0 ? static_cast<uint32_t>((P.P + kCandThreads - 1) / kCandThreads) : 1u;
     case kPhCand: return static_cast<uint32_t>((P.B + kCandThreads - 1) / kCandThreads);
     case kPhRoll: {
       const int per = is_quad_chain(P.dyn, P.n_links)   ? kBatchThreads / 4
@@ -34,8 +35,10 @@ __device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phas
 }
 
 union BatchSmem {
+  PathSmem path;
   CandSmem cand;
   TopkSmem topk;
+  EntropySmem ent;
   PointMassSmem pm;
 };
 
@@ -149,10 +152,15 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
       case kPhShift:
         shift_block<kBatchThreads>(P, static_cast<int>(P.ctrl[1]));
         break;
+      case kPhPaths:
+        path_tile(P, P.ctrl[0], static_cast<int>(k), static_cast<int>(tile), static_cast<int>(phase_tiles(P, kPhPaths)),
+                  sm.path);
+        break;
       case kPhCand: {
         const uint32_t r = P.ctrl[0];
+        const CandView v = cand_view(sm.cand);
         for (int j = 0; j < P.n; ++j) {
-          cand_tile(P, r, static_cast<int>(k), j, static_cast<int>(tile) * kCandThreads, sm.cand);
+          cand_tile(P, r, static_cast<int>(k), j, static_cast<int>(tile) * kCandThreads, 0, P.T, v);
           __syncthreads();
         }
         break;
@@ -162,6 +170,10 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         break;
       case kPhTopk:
         topk_block<kBatchThreads>(P, sm.topk);
+        if (P.diag & 1) {
+          __syncthreads();
+          entropy_block<kBatchThreads>(P, static_cast<int>(k), sm.ent);
+        }
         break;
       default: {
         const int wave = tid >> 6;
@@ -185,9 +197,9 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         atomicExch(&ictl[inst].done, 0u);
         uint32_t nph, nk;
         if (phase == kPhShift) {
-          nph = kPhCand; nk = ictl[inst].k_begin;
+          nph = kPhPaths; nk = ictl[inst].k_begin;
         } else if (phase == kPhUpd) {
-          nph = kPhCand; nk = k + 1u;
+          nph = kPhPaths; nk = k + 1u;
         } else {
           nph = phase + 1u; nk = k;
         }

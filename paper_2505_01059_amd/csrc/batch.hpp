@@ -11,7 +11,7 @@ namespace mtp {
 constexpr int kBatchThreads = 256;       // workgroup of the persistent kernel
 constexpr int kUpdOutputsPerTile = 64;   // refit outputs per queue item
 
-enum : uint32_t { kPhShift = 0, kPhCand = 1, kPhRoll = 2, kPhTopk = 3, kPhUpd = 4 };
+enum : uint32_t { kPhShift = 0, kPhPaths = 1, kPhCand = 2, kPhRoll = 3, kPhTopk = 4, kPhUpd = 5 };
 
 struct BatchItem {
   uint32_t inst, phase, k, tile;
@@ -78,9 +78,10 @@ const char* batch_error(const mtp_batch* b);
 hipStream_t batch_stream(const mtp_batch* b);
 
 // host mirror of the per-phase tile counts
-inline uint32_t host_phase_tiles(int B, int T, int n, uint32_t phase, bool quad, bool pair) {
+inline uint32_t host_phase_tiles(int B, int P, int T, int n, uint32_t phase, bool quad, bool pair) {
   switch (phase) {
     case kPhShift: return 1u;
+    case kPhPaths: return P > 0 ? static_cast<uint32_t>((P + kCandThreads - 1) / kCandThreads) : 1u;
     case kPhCand: return static_cast<uint32_t>((B + kCandThreads - 1) / kCandThreads);
     case kPhRoll: {
       const int per = quad ? kBatchThreads / 4 : (pair ? kBatchThreads / 2 : kBatchThreads);

@@ -12,16 +12,35 @@ __global__ __launch_bounds__(256) void k_shift(PlanDesc P) {
   shift_block<256>(P, static_cast<int>(P.ctrl[1]));
 }
 
-__global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) {
-  __shared__ CandSmem sm;
-  cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, sm);
+__global__ __launch_bounds__(kCandThreads) void k_paths(PlanDesc P, int k) {
+  __shared__ PathSmem sm;
+  path_tile(P, P.ctrl[0], k, blockIdx.x, gridDim.x, sm);
 }
 
+static int cand_chunk(const PlanDesc& P) { return P.tc < kTChunk ? P.tc : kTChunk; }
+
+// grid (candidate tiles, joints, horizon chunks of P.tc steps); LDS sized for
+// the plan so that several workgroups fit on a compute unit
+__global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) {
+  extern __shared__ float cand_lds[];
+  const CandView v = cand_view_dyn(cand_lds, P.L, P.W, P.tc < kTChunk ? P.tc : kTChunk);
+  const int t_begin = blockIdx.z * P.tc;
+  cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, t_begin, min(P.T, t_begin + P.tc), v);
+}
+
+__global__ __launch_bounds__(kTopkThreads) void k_entropy(PlanDesc P, int k) {
+  __shared__ EntropySmem sm;
+  entropy_block<kTopkThreads>(P, k, sm);
+}
+
+// Rollout workgroups are four waves: the waves of one workgroup go to the four
+// SIMDs of a compute unit, while single-wave workgroups sharing a unit were seen
+// to stack two waves on one SIMD now and then, doubling the time of a launch
+// with fewer waves than SIMDs.
 // The dispatcher hands workgroup g to XCD g mod 8, and each XCD has its own L2.
-// Rollout workgroups of 16..64 candidates read 64..256 B of every U row, less
-// than or equal to an L2 line, so neighbouring workgroups share lines: give each
-// XCD one contiguous run of workgroup indices so that a line is fetched into one
-// L2 only.  A bijection of [0, G) for any G.
+// Giving each XCD one contiguous run of workgroup indices keeps the U rows of
+// neighbouring candidates, and the lines they share, in one L2.  A bijection of
+// [0, G) for any G.
 __device__ __forceinline__ int xcd_contiguous_block(int g, int G) {
   constexpr int kXcds = 8;
   const int x = g % kXcds, i = g / kXcds;
@@ -161,14 +180,25 @@ hipError_t launch_shift(const PlanDesc& P, hipStream_t st) {
 hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
   switch (stage) {
     case 0: {
-      const dim3 grid((P.B + kCandThreads - 1) / kCandThreads, P.n);
-      k_candidates<<<grid, kCandThreads, 0, st>>>(P, k);
+      if (P.P > 0) {
+        k_paths<<<(P.P + kCandThreads - 1) / kCandThreads, kCandThreads, 0, st>>>(P, k);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+      const dim3 grid((P.B + kCandThreads - 1) / kCandThreads, P.n, (P.T + P.tc - 1) / P.tc);
+      const size_t lds = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, cand_chunk(P)));
+      k_candidates<<<grid, kCandThreads, lds, st>>>(P, k);
       return hipGetLastError();
     }
     case 1:
       return launch_rollout(P, st);
     case 2:
       k_topk<<<1, kTopkThreads, 0, st>>>(P);
+      if (P.diag & 1) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_entropy<<<1, kTopkThreads, 0, st>>>(P, k);
+      }
       return hipGetLastError();
     case 3: {
       const int outs = P.T * P.n;

@@ -14,7 +14,7 @@ constexpr int kMaxWidth = 256;
 constexpr int kMaxElites = 4096;
 constexpr int kBasisStride = 8;     // spline table row: up to degree 5 (6 weights) or 4 Hermite weights
 constexpr int kCandThreads = 256;   // candidate tile: 256 samples of one joint
-constexpr int kRollThreads = 64;    // rollout tile: one wave, one sample per lane
+constexpr int kRollThreads = 256;   // rollout workgroup: four waves, one per SIMD of a compute unit
 constexpr int kTopkThreads = 1024;  // top-E: one workgroup per plan
 constexpr int kUpdThreads = 256;    // refit tile: 4 waves, one (t, j) output per wave
 
@@ -32,6 +32,10 @@ struct PlanDesc {
   int32_t dyn, interp, n_links, d, n, T, L, W, P, G, B, E, K, p, n_dbg, n_task;
   int32_t ldU;
   int32_t R;             // randomised models per candidate (contact chain), cost averaged
+  int32_t wor;           // tensor paths drawn without replacement (keyed permutation of the W^L paths)
+  int32_t sw_rounds;     // rounds of that permutation
+  int32_t diag;          // bit 0: cost entropy of every CEM iteration into entropy[k]
+  int32_t tc;            // time steps per candidate workgroup (a multiple of 4)
   float lam, alpha, sigma_min, sigma_init, u_min, u_max, dt;
   uint32_t key0, key1;
   uint32_t* ctrl;        // [0] replan index r, [1] shift, [2] flags (bit 0: all elites +inf, bit 1: selection fault)
@@ -53,6 +57,7 @@ struct PlanDesc {
   float* ecost;          // [E]
   float* w;              // [E]
   float* X;              // [T][d][n_dbg] or null
+  float* entropy;        // [K] cost entropy of each iteration of the last replan
 };
 
 // ------------------------------------------------------------------ Philox
@@ -74,7 +79,7 @@ __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
   return r;
 }
 
-constexpr uint32_t kTagZ = 1, kTagI = 2, kTagEps = 3;
+constexpr uint32_t kTagZ = 1, kTagI = 2, kTagEps = 3, kTagPerm = 4;
 
 __device__ __forceinline__ uint32_t stream_c3(uint32_t tag, int k) {
   return (tag << 16) | (static_cast<uint32_t>(k) & 0xFFFFu);
@@ -124,42 +129,203 @@ struct CandSmem {
   float tmu[kTChunk], tsg[kTChunk];              // mean and std of joint j at those steps
 };
 
-__device__ __forceinline__ void akima_slopes_thread(int L, int tid, CandSmem& sm) {
+// The candidate tile's LDS arrays, either the fixed-size struct above or a
+// block sized for one plan (L*W graph column, L control points and slopes per
+// thread, `chunk` staged steps).
+struct CandView {
+  float* z;        // [L*W]
+  float* ctrl;     // [L][kCandThreads]
+  float* slope;    // [L][kCandThreads]
+  float* tb;       // [chunk][kBasisStride]
+  int32_t* ts;     // [chunk]
+  float* tmu;      // [chunk]
+  float* tsg;      // [chunk]
+  int chunk;
+};
+
+__device__ __forceinline__ CandView cand_view(CandSmem& sm) {
+  CandView v;
+  v.z = sm.z; v.ctrl = &sm.ctrl[0][0]; v.slope = &sm.slope[0][0]; v.tb = sm.tb; v.ts = sm.ts;
+  v.tmu = sm.tmu; v.tsg = sm.tsg; v.chunk = kTChunk;
+  return v;
+}
+
+__host__ __device__ constexpr int cand_dyn_floats(int L, int W, int chunk) {
+  return L * W + 2 * L * kCandThreads + chunk * (kBasisStride + 3);
+}
+
+__device__ __forceinline__ CandView cand_view_dyn(float* base, int L, int W, int chunk) {
+  CandView v;
+  v.z = base;
+  v.ctrl = v.z + L * W;
+  v.slope = v.ctrl + L * kCandThreads;
+  v.tb = v.slope + L * kCandThreads;
+  v.ts = reinterpret_cast<int32_t*>(v.tb + chunk * kBasisStride);
+  v.tmu = reinterpret_cast<float*>(v.ts + chunk);
+  v.tsg = v.tmu + chunk;
+  v.chunk = chunk;
+  return v;
+}
+
+__device__ __forceinline__ void akima_slopes_thread(int L, int tid, const CandView& sm) {
   // unit-spacing secants m_i = z_{i+1} - z_i; slope rules of the Akima spline
   // with the paper's end conditions; both weights zero -> mean of the secants.
   for (int i = 0; i < L; ++i) {
     float s;
     if (i == 0) {
-      s = sm.ctrl[1][tid] - sm.ctrl[0][tid];
+      s = sm.ctrl[1 * kCandThreads + tid] - sm.ctrl[0 * kCandThreads + tid];
     } else if (i == L - 1) {
-      s = sm.ctrl[L - 1][tid] - sm.ctrl[L - 2][tid];
+      s = sm.ctrl[(L - 1) * kCandThreads + tid] - sm.ctrl[(L - 2) * kCandThreads + tid];
     } else if (i == 1) {
-      s = 0.5f * (sm.ctrl[2][tid] - sm.ctrl[0][tid]);
+      s = 0.5f * (sm.ctrl[2 * kCandThreads + tid] - sm.ctrl[0 * kCandThreads + tid]);
     } else if (i == L - 2) {
-      s = 0.5f * (sm.ctrl[L - 1][tid] - sm.ctrl[L - 3][tid]);
+      s = 0.5f * (sm.ctrl[(L - 1) * kCandThreads + tid] - sm.ctrl[(L - 3) * kCandThreads + tid]);
     } else {
-      const float m2 = sm.ctrl[i - 1][tid] - sm.ctrl[i - 2][tid];
-      const float m1 = sm.ctrl[i][tid] - sm.ctrl[i - 1][tid];
-      const float m0 = sm.ctrl[i + 1][tid] - sm.ctrl[i][tid];
-      const float mp = sm.ctrl[i + 2][tid] - sm.ctrl[i + 1][tid];
+      const float m2 = sm.ctrl[(i - 1) * kCandThreads + tid] - sm.ctrl[(i - 2) * kCandThreads + tid];
+      const float m1 = sm.ctrl[i * kCandThreads + tid] - sm.ctrl[(i - 1) * kCandThreads + tid];
+      const float m0 = sm.ctrl[(i + 1) * kCandThreads + tid] - sm.ctrl[i * kCandThreads + tid];
+      const float mp = sm.ctrl[(i + 2) * kCandThreads + tid] - sm.ctrl[(i + 1) * kCandThreads + tid];
       const float wa = fabsf(mp - m0);
       const float wb = fabsf(m1 - m2);
       const float den = wa + wb;
       s = (den == 0.0f) ? 0.5f * (m1 + m0) : (wa * m1 + wb * m0) / den;
     }
-    sm.slope[i][tid] = s;
+    sm.slope[i * kCandThreads + tid] = s;
   }
 }
 
+// ------------------------------------------------------------------ path indices
+// Tensor path p takes layer indices I[l][p].  With replacement (Alg. 1) every
+// index is an independent uniform draw from Philox stream tag 2.  Without
+// replacement, path p is the image of p under a keyed permutation of the W^L
+// paths (swap-or-not shuffle, Hoang, Morris and Rogaway, CRYPTO 2012): path
+// numbers are L base-W digits (layer l is digit l, least significant first);
+// round i maps x to K_i - x mod W^L when a pseudo-random bit of max(x, K_i - x)
+// is set.  Each round pairs x with K_i - x, so every round and their
+// composition are bijections: distinct p give distinct paths.  Round keys K_i
+// (digits) and the bit function's Philox key come from stream tag 4.
+
+constexpr int kMaxPermRounds = 2 * kMaxLayers * 8;   // 2 L ceil(log2 W) with W <= 256
+
+struct PathSmem {
+  uint8_t kd[kMaxPermRounds][kMaxLayers];   // round key digits
+  uint32_t fk[kMaxPermRounds][2];           // bit-function key per round
+};
+
+__device__ __forceinline__ void perm_round_keys(const PlanDesc& P, uint32_t r, int k, PathSmem& sm) {
+  const int groups = (P.L + 3) >> 2;
+  for (int e = threadIdx.x; e < P.sw_rounds * (groups + 1); e += blockDim.x) {
+    const int i = e / (groups + 1), g = e - i * (groups + 1);
+    const Words4 q = philox(static_cast<uint32_t>(i), static_cast<uint32_t>(g), r, stream_c3(kTagPerm, k), P.key0,
+                            P.key1);
+    if (g < groups) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int l = 4 * g + c;
+        if (l < P.L) sm.kd[i][l] = static_cast<uint8_t>(__umulhi(q.w[c], static_cast<uint32_t>(P.W)));
+      }
+    } else {
+      sm.fk[i][0] = q.w[0];
+      sm.fk[i][1] = q.w[1];
+    }
+  }
+}
+
+// Graph waypoints (Def. 1): Z[l][w][j] = lo + (hi - lo) u with u from stream
+// tag 1, item l, element w*n + j.  Tile `tile` of `n_tiles` takes every
+// n_tiles-th Philox block.
+__device__ __forceinline__ void graph_tile(const PlanDesc& P, uint32_t r, int k, int tile, int n_tiles) {
+  const int Wn = P.W * P.n;
+  const int nb = (Wn + 3) >> 2;
+  const float lo = P.u_min, span = P.u_max - P.u_min;
+  for (int c = tile * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x); c < P.L * nb;
+       c += n_tiles * static_cast<int>(blockDim.x)) {
+    const int l = c / nb, blk = c - l * nb;
+    const Words4 q = philox(static_cast<uint32_t>(blk), static_cast<uint32_t>(l), r, stream_c3(kTagZ, k), P.key0,
+                            P.key1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = 4 * blk + e;
+      if (idx < Wn) P.Z[static_cast<size_t>(l) * Wn + idx] = fmaf(span, u01(q.w[e]), lo);
+    }
+  }
+}
+
+// Draws the graph (its share) and writes I[.][p] for the tensor paths p in
+// [p0, p0 + blockDim.x).  Every thread of the workgroup must call this (it
+// synchronises the workgroup).
+__device__ __forceinline__ void path_tile(const PlanDesc& P, uint32_t r, int k, int tile, int n_tiles,
+                                          PathSmem& sm) {
+  if (P.P > 0) graph_tile(P, r, k, tile, n_tiles);
+  const int pp = tile * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+  if (!P.wor) {
+    if (pp >= P.P) return;
+    for (int l4 = 0; l4 < P.L; l4 += 4) {
+      const Words4 q = philox(static_cast<uint32_t>(l4 >> 2), static_cast<uint32_t>(pp), r, stream_c3(kTagI, k),
+                              P.key0, P.key1);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int l = l4 + c;
+        if (l < P.L)
+          P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(__umulhi(q.w[c], static_cast<uint32_t>(P.W)));
+      }
+    }
+    return;
+  }
+  perm_round_keys(P, r, k, sm);
+  __syncthreads();
+  if (pp >= P.P) return;
+  const uint32_t W = static_cast<uint32_t>(P.W);
+  const int L = P.L;
+  uint32_t x[kMaxLayers];
+  {
+    uint32_t v = static_cast<uint32_t>(pp);
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+      x[l] = (l < L) ? v % W : 0u;
+      v = (l < L) ? v / W : v;
+    }
+  }
+  for (int i = 0; i < P.sw_rounds; ++i) {
+    // x' = K_i - x mod W^L, digit by digit with a borrow
+    uint32_t xs[kMaxLayers];
+    uint32_t borrow = 0u;
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+      const int32_t dgt = static_cast<int32_t>(sm.kd[i][l < L ? l : 0]) - static_cast<int32_t>(x[l]) -
+                          static_cast<int32_t>(borrow);
+      xs[l] = (l < L) ? static_cast<uint32_t>(dgt < 0 ? dgt + static_cast<int32_t>(W) : dgt) : 0u;
+      borrow = (l < L && dgt < 0) ? 1u : 0u;
+    }
+    // the larger of x and x' (most significant digit first) names the pair
+    int cmp = 0;
+#pragma unroll
+    for (int l = kMaxLayers - 1; l >= 0; --l)
+      if (cmp == 0 && l < L) cmp = (xs[l] > x[l]) ? 1 : ((xs[l] < x[l]) ? -1 : 0);
+    uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) wd[l >> 2] |= (cmp > 0 ? xs[l] : x[l]) << (8 * (l & 3));
+    const Words4 f = philox(wd[0], wd[1], wd[2], wd[3], sm.fk[i][0], sm.fk[i][1]);
+    if (f.w[0] & 1u) {
+#pragma unroll
+      for (int l = 0; l < kMaxLayers; ++l) x[l] = xs[l];
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < kMaxLayers; ++l)
+    if (l < L) P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(x[l]);
+}
+
+// Candidates [b0, b0 + kCandThreads) of joint j over steps [t_begin, t_end)
+// (t_begin a multiple of 4).  Tensor paths read their layer indices from I.
 // Every thread of the tile must call this (it synchronises the workgroup).
-__device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, int j, int b0,
-                                          CandSmem& sm) {
+__device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, int j, int b0, int t_begin,
+                                          int t_end, const CandView& sm) {
   const int tid = threadIdx.x;
   const int b = b0 + tid;
   const int G1 = P.G - 1;                       // local samples [0, G1)
   const int tens_lo = G1, tens_hi = G1 + P.P;   // tensor paths [G1, G1+P)
   const bool tile_has_tensor = (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
-  const bool z_writer = tile_has_tensor && (b0 <= tens_lo);
   const float lo = P.u_min, hi = P.u_max;
   const size_t ld = static_cast<size_t>(P.ldU);
   const bool live = b < P.B;
@@ -167,38 +333,18 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
   const bool is_tensor = live && b >= tens_lo && b < tens_hi;
 
   if (tile_has_tensor) {
-    const float span = hi - lo;
-    const int LW = P.L * P.W;
-    for (int e = tid; e < LW; e += kCandThreads) {
-      const int l = e / P.W, w = e - l * P.W;
-      const uint32_t idx = static_cast<uint32_t>(w * P.n + j);
-      const Words4 q = philox(idx >> 2, static_cast<uint32_t>(l), r, stream_c3(kTagZ, k), P.key0, P.key1);
-      const float z = fmaf(span, u01(q.w[idx & 3u]), lo);
-      sm.z[e] = z;
-      if (z_writer) P.Z[static_cast<size_t>(e) * P.n + j] = z;
-    }
+    // graph column of joint j (drawn by the path tiles)
+    for (int e = tid; e < P.L * P.W; e += kCandThreads) sm.z[e] = P.Z[static_cast<size_t>(e) * P.n + j];
   }
   __syncthreads();
   if (is_tensor) {
     const int pp = b - G1;
-    for (int l4 = 0; l4 < P.L; l4 += 4) {
-      const Words4 q = philox(static_cast<uint32_t>(l4 >> 2), static_cast<uint32_t>(pp), r,
-                              stream_c3(kTagI, k), P.key0, P.key1);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int l = l4 + c;
-        if (l < P.L) {
-          const uint32_t wi = __umulhi(q.w[c], static_cast<uint32_t>(P.W));
-          sm.ctrl[l][tid] = sm.z[l * P.W + wi];
-          if (j == 0) P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(wi);
-        }
-      }
-    }
+    for (int l = 0; l < P.L; ++l) sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + P.I[static_cast<size_t>(l) * P.P + pp]];
     if (P.interp == kAkima) akima_slopes_thread(P.L, tid, sm);
   }
   const int Tq = (P.T + 3) >> 2;
-  for (int t0 = 0; t0 < P.T; t0 += kTChunk) {
-    const int tn = min(kTChunk, P.T - t0);
+  for (int t0 = t_begin; t0 < t_end; t0 += sm.chunk) {
+    const int tn = min(sm.chunk, t_end - t0);
     for (int i = tid; i < tn; i += kCandThreads) {
       const int o = (t0 + i) * P.n + j;
       sm.ts[i] = P.span[t0 + i];
@@ -231,10 +377,10 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
         for (int i = 0; i < tn; ++i) {
           const int s0 = sm.ts[i];
           const float* bw = sm.tb + i * kBasisStride;
-          float v = bw[0] * sm.ctrl[s0][tid];
-          v = fmaf(bw[1], sm.ctrl[s0 + 1][tid], v);
-          v = fmaf(bw[2], sm.ctrl[s0 + 2][tid], v);
-          v = fmaf(bw[3], sm.ctrl[s0 + 3][tid], v);
+          float v = bw[0] * sm.ctrl[s0 * kCandThreads + tid];
+          v = fmaf(bw[1], sm.ctrl[(s0 + 1) * kCandThreads + tid], v);
+          v = fmaf(bw[2], sm.ctrl[(s0 + 2) * kCandThreads + tid], v);
+          v = fmaf(bw[3], sm.ctrl[(s0 + 3) * kCandThreads + tid], v);
           P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
         }
       } else if (P.interp != kAkima) {
@@ -244,7 +390,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           const int s0 = sm.ts[i];
           const float* bw = sm.tb + i * kBasisStride;
           float v = 0.0f;
-          for (int q = 0; q < np1; ++q) v = fmaf(bw[q], sm.ctrl[s0 + q][tid], v);
+          for (int q = 0; q < np1; ++q) v = fmaf(bw[q], sm.ctrl[(s0 + q) * kCandThreads + tid], v);
           P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
         }
       } else {
@@ -252,10 +398,10 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
         for (int i = 0; i < tn; ++i) {
           const int iv = sm.ts[i];
           const float* h = sm.tb + i * kBasisStride;
-          float v = h[0] * sm.ctrl[iv][tid];
-          v = fmaf(h[1], sm.slope[iv][tid], v);
-          v = fmaf(h[2], sm.ctrl[iv + 1][tid], v);
-          v = fmaf(h[3], sm.slope[iv + 1][tid], v);
+          float v = h[0] * sm.ctrl[iv * kCandThreads + tid];
+          v = fmaf(h[1], sm.slope[iv * kCandThreads + tid], v);
+          v = fmaf(h[2], sm.ctrl[(iv + 1) * kCandThreads + tid], v);
+          v = fmaf(h[3], sm.slope[(iv + 1) * kCandThreads + tid], v);
           P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
         }
       }
@@ -1257,6 +1403,53 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const float inv = 1.0f / sm.red[0];
   for (int e = tid; e < E; e += BS) P.w[e] *= inv;
   if (tid == 0 && !(s0 < INFINITY)) atomicOr(&P.ctrl[2], 1u);
+}
+
+// ------------------------------------------------------------------ cost entropy
+// H = -sum_j P_j log P_j with P_j = exp(J_j) / sum_l exp(J_l) over the finite
+// rollout costs J of one iteration (the exploration diagnostic of Section 5.1),
+// as H = log S0 - S1 / S0 with S0 = sum e^{J - m}, S1 = sum e^{J - m} (J - m),
+// m = max J.  1024 virtual lanes each fold the costs b = v, v + 1024, ... in
+// turn with a running maximum, then a fixed binary tree combines the lanes,
+// so the value depends neither on the block size nor on scheduling.
+
+constexpr int kEntLanes = 1024;
+
+struct EntropySmem {
+  float m[kEntLanes], s0[kEntLanes], s1[kEntLanes];
+};
+
+__device__ __forceinline__ void ent_fold(float& m, float& s0, float& s1, float m2, float a0, float a1) {
+  if (!(a0 > 0.0f)) return;
+  if (!(s0 > 0.0f)) { m = m2; s0 = a0; s1 = a1; return; }
+  const float mm = fmaxf(m, m2);
+  const float fa = __expf(m - mm), fb = __expf(m2 - mm);
+  s1 = fa * fmaf(m - mm, s0, s1) + fb * fmaf(m2 - mm, a0, a1);
+  s0 = fa * s0 + fb * a0;
+  m = mm;
+}
+
+template <int BS>
+__device__ __forceinline__ void entropy_block(const PlanDesc& P, int k, EntropySmem& sm) {
+  for (int v = threadIdx.x; v < kEntLanes; v += BS) {
+    float m = 0.0f, s0 = 0.0f, s1 = 0.0f;
+    for (int b = v; b < P.B; b += kEntLanes) {
+      const float J = P.cost[b];
+      if (!(fabsf(J) <= 3.402823466e38f)) continue;
+      ent_fold(m, s0, s1, J, 1.0f, 0.0f);
+    }
+    sm.m[v] = m; sm.s0[v] = s0; sm.s1[v] = s1;
+  }
+  __syncthreads();
+  for (int h = kEntLanes / 2; h > 0; h >>= 1) {
+    for (int v = threadIdx.x; v < h; v += BS) {
+      float m = sm.m[v], s0 = sm.s0[v], s1 = sm.s1[v];
+      ent_fold(m, s0, s1, sm.m[v + h], sm.s0[v + h], sm.s1[v + h]);
+      sm.m[v] = m; sm.s0[v] = s0; sm.s1[v] = s1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) P.entropy[k] = (sm.s0[0] > 0.0f) ? __logf(sm.s0[0]) - sm.s1[0] / sm.s0[0] : 0.0f;
 }
 
 // ------------------------------------------------------------------ refit

@@ -73,6 +73,15 @@ bool validate_config(const mtp_config* c, std::string* why, mtp_status* code) {
   if (!(c->dt > 0.0f) || !std::isfinite(c->dt)) return fail(MTP_ERR_INVALID_ARG, "dt must be finite and > 0");
   if (c->n_debug_states < 0 || c->n_debug_states > B) return fail(MTP_ERR_INVALID_ARG, "n_debug_states must be in 0..B");
   if (c->n_replicas < 0 || c->n_replicas > 64) return fail(MTP_ERR_INVALID_ARG, "n_replicas must be in 0..64");
+  if (c->sample_wor != 0 && c->sample_wor != 1) return fail(MTP_ERR_INVALID_ARG, "sample_wor must be 0 or 1");
+  if (c->diagnostics < 0 || c->diagnostics > 1) return fail(MTP_ERR_INVALID_ARG, "diagnostics must be 0 or 1");
+  if (c->sample_wor == 1) {
+    // P distinct paths need P <= W^L
+    long double paths = 1.0L;
+    for (int l = 0; l < c->n_layers && paths < static_cast<long double>(c->n_tensor); ++l) paths *= c->n_width;
+    if (paths < static_cast<long double>(c->n_tensor))
+      return fail(MTP_ERR_INVALID_ARG, "sampling without replacement needs n_tensor <= n_width^n_layers");
+  }
   if (c->n_task_params < 0 || (c->n_task_params > 0 && c->task_params == nullptr))
     return fail(MTP_ERR_INVALID_ARG, "task_params missing");
   if (c->dynamics == MTP_DYN_POINT_MASS) {
@@ -129,6 +138,7 @@ Layout compute_layout(const mtp_config& c) {
   L.task = take(static_cast<size_t>(c.n_task_params) * 4);
   const size_t R = c.n_replicas > 1 ? static_cast<size_t>(c.n_replicas) : 1;
   L.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? take(R * B * (n + 1) * 4) : 0;
+  L.entropy = take(static_cast<size_t>(c.n_iters) * 4);
   L.resident = off;
   off = 0;
   L.Z = take(static_cast<size_t>(c.n_layers) * c.n_width * n * 4);
@@ -261,6 +271,24 @@ void mtp::set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8
   P->X = c.n_debug_states > 0 ? reinterpret_cast<float*>(tb + L.X) : nullptr;
 }
 
+int mtp::perm_rounds(int L, int W) {
+  int bits = 0;
+  while ((1 << bits) < W) ++bits;
+  return 2 * L * (bits > 0 ? bits : 1);
+}
+
+// Enough workgroups to give every SIMD of the chip a few waves: short horizons
+// and small batches split the horizon into chunks of a multiple of 4 steps.
+int mtp::cand_time_chunk(int B, int T, int n) {
+  constexpr long long kTargetWaves = 4096;
+  const long long waves = static_cast<long long>((B + kCandThreads - 1) / kCandThreads) * n * (kCandThreads / 64);
+  long long chunks = waves >= kTargetWaves ? 1 : (kTargetWaves + waves - 1) / waves;
+  chunks = std::min<long long>(chunks, std::max(1, T / 16));
+  int tc = static_cast<int>((T + chunks - 1) / chunks);
+  tc = (tc + 3) & ~3;
+  return std::max(tc, 4);
+}
+
 PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uint8_t* tb) {
   PlanDesc P{};
   P.dyn = c.dynamics; P.interp = c.interp; P.n_links = c.n_links; P.d = c.state_dim; P.n = c.ctrl_dim;
@@ -268,6 +296,10 @@ PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uin
   P.B = c.n_tensor + c.n_gauss; P.E = c.n_elites; P.K = c.n_iters; P.p = c.bspline_degree;
   P.n_dbg = c.n_debug_states; P.n_task = c.n_task_params; P.ldU = static_cast<int32_t>(L.ldU);
   P.R = c.n_replicas > 1 ? c.n_replicas : 1;
+  P.wor = c.sample_wor;
+  P.sw_rounds = c.sample_wor ? perm_rounds(c.n_layers, c.n_width) : 0;
+  P.diag = c.diagnostics;
+  P.tc = cand_time_chunk(P.B, P.T, P.n);
   P.lam = c.temperature; P.alpha = c.smoothing; P.sigma_min = c.sigma_min; P.sigma_init = c.sigma_init;
   P.u_min = c.u_min; P.u_max = c.u_max; P.dt = c.dt;
   P.key0 = static_cast<uint32_t>(c.seed & 0xFFFFFFFFull);
@@ -283,6 +315,7 @@ PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uin
   P.span = reinterpret_cast<const int32_t*>(base + L.span);
   P.task = reinterpret_cast<const float*>(base + L.task);
   P.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? reinterpret_cast<const float*>(base + L.sparams) : nullptr;
+  P.entropy = reinterpret_cast<float*>(base + L.entropy);
   if (tb != nullptr) set_transient(&P, c, L, tb);
   return P;
 }
@@ -544,7 +577,7 @@ mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out) {
   const PlanDesc& P = p->P;
   out->Z = P.Z; out->I = P.I; out->U = P.U; out->cost = P.cost; out->elite_idx = P.eidx;
   out->elite_cost = P.ecost; out->weights = P.w; out->mu = P.mu; out->sigma = P.sigma; out->x0 = P.x0;
-  out->action = P.action; out->X_dbg = P.X; out->ld_U = static_cast<size_t>(P.ldU);
+  out->action = P.action; out->X_dbg = P.X; out->entropy = P.entropy; out->ld_U = static_cast<size_t>(P.ldU);
   return MTP_OK;
 }
 

@@ -19,7 +19,7 @@ namespace mtp {
 // base; a single plan places the transient part right after the resident one.
 struct Layout {
   size_t ldU;
-  size_t ctrl, x0, mu, sigma, tmp, action, basis, span, task, sparams;   // resident
+  size_t ctrl, x0, mu, sigma, tmp, action, basis, span, task, sparams, entropy;   // resident
   size_t Z, I, U, cost, eidx, ecost, w, X;                               // transient
   size_t resident, transient;
   size_t total;   // resident + transient
@@ -34,5 +34,9 @@ hipError_t enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStre
 PlanDesc make_desc(const mtp_config& c, const Layout& L, uint8_t* resident, uint8_t* transient);
 // Point a descriptor's transient buffers at a new base.
 void set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* transient);
+// Rounds of the without-replacement path permutation: 2 L ceil(log2 W).
+int perm_rounds(int L, int W);
+// Time steps per candidate workgroup of the single-plan candidate kernel.
+int cand_time_chunk(int B, int T, int n);
 
 }  // namespace mtp

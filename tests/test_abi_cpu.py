@@ -196,3 +196,16 @@ def test_replica_count_validation_and_workspace():
     bad[-1, 0] = 0.0
     st, why = N.validate(r3.replace(sample_params=bad))
     assert st == 1 and "masses" in why
+
+
+def test_without_replacement_and_diagnostics_validation():
+    ok = W.point_mass_config(n_tensor=256, n_gauss=8, n_layers=4, n_width=4).replace(sample_wor=1, diagnostics=1)
+    assert N.validate(ok)[0] == 0
+    st, why = N.validate(ok.replace(n_tensor=257))          # more paths than 4^4
+    assert st == 1 and "without replacement" in why
+    st, why = N.validate(ok.replace(sample_wor=2))
+    assert st == 1 and "sample_wor" in why
+    st, why = N.validate(ok.replace(diagnostics=2))
+    assert st == 1 and "diagnostics" in why
+    # the entropy record lives with the plan: K floats more than without
+    assert N.workspace_bytes(ok) >= N.workspace_bytes(ok.replace(diagnostics=0))

@@ -32,6 +32,11 @@ def small_mix():
                        n_layers=12, n_width=64, n_elites=16, n_iters=2, seed=6),
         W.chain_contact_config(name="b_k24", n_tensor=200, n_gauss=56, horizon=48, n_elites=16, n_iters=2,
                                seed=7),
+        # paths without replacement and the cost-entropy diagnostic
+        W.chain_config(name="b_wor", n_tensor=500, n_gauss=60, horizon=40, n_elites=20, n_iters=3,
+                       seed=8).replace(sample_wor=1, diagnostics=1),
+        W.point_mass_config(name="b_pmwor", n_tensor=200, n_gauss=40, horizon=30, n_layers=4, n_width=4,
+                            n_elites=16, n_iters=2, seed=9).replace(sample_wor=1, diagnostics=1),
     ]
 
 
@@ -43,7 +48,8 @@ def standalone(cfg, x0, replans, shift=1):
         p.replan(x0, shift=shift, replan_idx=r)
     torch.cuda.synchronize()
     b = p.buffers()
-    out = (b["mu"].cpu().numpy().copy(), b["sigma"].cpu().numpy().copy(), p.action())
+    out = (b["mu"].cpu().numpy().copy(), b["sigma"].cpu().numpy().copy(), p.action(),
+           b["entropy"].cpu().numpy().copy())
     p.close()
     return out
 
@@ -61,11 +67,13 @@ def test_batch_equals_standalone(use_graph):
         bt.replan(xp, shift=1)
     acts = bt.actions()
     for i, c in enumerate(cfgs):
-        mu, sg, a = standalone(c, x0s[i], 2)
+        mu, sg, a, ent = standalone(c, x0s[i], 2)
         b = bt.buffers(i)
         assert np.array_equal(b["mu"].cpu().numpy(), mu), c.name
         assert np.array_equal(b["sigma"].cpu().numpy(), sg), c.name
         assert np.array_equal(acts[i], a), c.name
+        if c.diagnostics:
+            assert np.array_equal(b["entropy"].cpu().numpy(), ent), c.name
     bt.close()
 
 
@@ -85,7 +93,7 @@ def test_batch_step_split_iterations_and_subsets():
     acts = bt.actions()
     torch.cuda.synchronize()
     for i, c in enumerate(cfgs):
-        mu, sg, a = standalone(c, x0s[i], 1)
+        mu, sg, a, _ = standalone(c, x0s[i], 1)
         b = bt.buffers(i)
         assert np.array_equal(b["mu"].cpu().numpy(), mu), c.name
         assert np.array_equal(b["sigma"].cpu().numpy(), sg), c.name
@@ -106,7 +114,7 @@ def test_batch_autotune_and_reset():
     bt.replan(xp, shift=1)                       # replan index 0 after the reset
     acts = bt.actions()
     for i, c in enumerate(cfgs):
-        mu, sg, a = standalone(c, x0s[i], 1)
+        mu, sg, a, _ = standalone(c, x0s[i], 1)
         assert np.array_equal(acts[i], a)
     bt.close()
 
@@ -123,7 +131,7 @@ def test_mix_of_256_sampled_against_standalone():
     bt.replan(xp, shift=1)
     acts = bt.actions()
     for i in (0, 1, 5, 77, 128, 255):
-        mu, sg, a = standalone(cfgs[i], x0s[i], 1)
+        mu, sg, a, _ = standalone(cfgs[i], x0s[i], 1)
         b = bt.buffers(i)
         assert np.array_equal(b["mu"].cpu().numpy(), mu), cfgs[i].name
         assert np.array_equal(acts[i], a), cfgs[i].name

@@ -47,6 +47,11 @@ def configs():
                                               n_replicas=3),
         "contact24_r2": W.chain_contact_config(name="contact24_r2", n_tensor=100, n_gauss=28, horizon=32,
                                                n_elites=12, n_iters=2, n_replicas=2),
+        # tensor paths without replacement: near saturation (200 of 4^4) and a wide graph
+        "wor_pm": W.point_mass_config(name="wor_pm", n_tensor=200, n_gauss=40, horizon=30, n_layers=4,
+                                      n_width=4, n_elites=16, n_iters=2).replace(sample_wor=1),
+        "wor_chain7": W.chain_config(name="wor_chain7", n_tensor=700, n_gauss=101, horizon=66,
+                                     n_elites=40, n_iters=2).replace(sample_wor=1),
         # corners of the (beta, E) plane named in the design ablation: PS, MPPI, TS-PS, TS-MPPI
         "corner_ps": W.point_mass_config(name="corner_ps", n_tensor=0, n_gauss=200, n_elites=1, n_iters=2),
         "corner_mppi": W.point_mass_config(name="corner_mppi", n_tensor=0, n_gauss=200, n_elites=200,
@@ -67,6 +72,12 @@ def configs():
 
 CONFIGS = configs()
 NAMES = list(CONFIGS)
+
+
+def ref_indices(cfg, r, k):
+    if cfg.sample_wor:
+        return OS.path_indices_without_replacement(cfg.seed, r, k, cfg.n_tensor, cfg.n_layers, cfg.n_width)
+    return OS.path_indices(cfg.seed, r, k, cfg.n_tensor, cfg.n_layers, cfg.n_width)
 
 
 def random_state(cfg, seed=0):
@@ -102,7 +113,7 @@ def test_candidates_stage(name, torch_mod):
     torch_mod.cuda.synchronize()
     b = plan.buffers()
     Z_ref = OS.waypoints(cfg.seed, r, k, cfg.n_layers, cfg.n_width, cfg.ctrl_dim, cfg.u_min, cfg.u_max)
-    I_ref = OS.path_indices(cfg.seed, r, k, cfg.n_tensor, cfg.n_layers, cfg.n_width)
+    I_ref = ref_indices(cfg, r, k)
     if cfg.n_tensor > 0:                 # without tensor paths the graph is never drawn
         assert np.array_equal(b["Z"].cpu().numpy(), Z_ref), "graph waypoints not bit-exact"
     assert np.array_equal(b["I"].cpu().numpy().T.astype(np.int64), I_ref), "path indices not bit-exact"
@@ -270,4 +281,45 @@ def test_teacher_forced_replan(name, torch_mod):
         mu = b["mu"].cpu().numpy().copy()
         sg = b["sigma"].cpu().numpy().copy()
     _log(f"  margin events {margin_events}")
+    plan.close()
+
+
+@pytest.mark.parametrize("B_tensor", [700, 9215])
+def test_cost_entropy_on_given_costs(B_tensor, torch_mod):
+    """Cost entropy (Section 5.1) of the costs in the cost buffer, written by the
+    top-E stage: compared with the oracle on the same float32 costs, including
+    non-finite ones (left out) and a spread that tilts the distribution."""
+    cfg = W.chain_config(name="ent", n_tensor=B_tensor, n_gauss=1, horizon=16, n_elites=8,
+                         n_iters=3).replace(diagnostics=1)
+    _log(f"[entropy] B={cfg.n_samples}")
+    plan = make_plan(cfg)
+    b = plan.buffers()
+    rng = np.random.default_rng(B_tensor)
+    for k, scale in enumerate([0.5, 3.0, 40.0]):
+        s = rng.normal(10.0, scale, cfg.n_samples).astype(np.float32)
+        s[rng.choice(cfg.n_samples, 5, replace=False)] = np.inf
+        s[3] = np.nan
+        b["cost"].copy_(torch_mod.from_numpy(s).to(b["cost"].device))
+        plan.run_stage(2, 0, k)
+        torch_mod.cuda.synchronize()
+        H = float(b["entropy"].cpu().numpy()[k])
+        H_ref = OP.cost_entropy(s.astype(np.float64))
+        _log(f"  scale {scale}: H {H:.6f} oracle {H_ref:.6f}")
+        assert abs(H - H_ref) <= 1e-4 * max(1.0, H_ref)
+    plan.close()
+
+
+def test_cost_entropy_in_whole_replan(torch_mod):
+    """With diagnostics on, every iteration of a replan records the entropy of
+    its costs; the last one matches the oracle on the GPU's final costs."""
+    cfg = CONFIGS["pm_bspline"].replace(diagnostics=1, n_iters=3)
+    plan = make_plan(cfg)
+    x0 = W.initial_state(cfg)
+    plan.replan(x0, shift=1, replan_idx=0)
+    torch_mod.cuda.synchronize()
+    b = plan.buffers()
+    ent = b["entropy"].cpu().numpy()
+    s = b["cost"].cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(ent)) and np.all(ent >= 0)
+    assert abs(ent[-1] - OP.cost_entropy(s)) <= 1e-4 * max(1.0, ent[-1])
     plan.close()

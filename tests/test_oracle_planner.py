@@ -267,3 +267,25 @@ def test_replica_mean_is_permutation_invariant_and_bracketed():
     assert np.all(s >= singles.min(0) * (1 - 1e-12)) and np.all(s <= singles.max(0) * (1 + 1e-12))
     # the models differ, so the mean is not any one of them
     assert np.any(np.abs(singles[0] - s) > 1e-6 * np.abs(s))
+
+
+# ------------------------------------------------------------------ cost entropy (Section 5.1)
+
+def test_cost_entropy_closed_forms():
+    from scipy import special, stats
+    B = 37
+    assert P.cost_entropy(np.full(B, 3.25)) == pytest.approx(math.log(B), rel=1e-14)
+    # n1 costs at a, n2 at b: P = e^a / Z on n1 entries, e^b / Z on n2 entries
+    n1, n2, a, b = 5, 11, 0.7, -1.3
+    Z = n1 * math.exp(a) + n2 * math.exp(b)
+    pa, pb = math.exp(a) / Z, math.exp(b) / Z
+    H = -(n1 * pa * math.log(pa) + n2 * pb * math.log(pb))
+    J = np.array([a] * n1 + [b] * n2)
+    assert P.cost_entropy(J) == pytest.approx(H, rel=1e-13)
+    J = np.random.default_rng(3).normal(0, 2, 500)
+    assert P.cost_entropy(J) == pytest.approx(stats.entropy(special.softmax(J)), rel=1e-12)
+    # shift invariance, non-finite costs left out, one dominant cost
+    assert P.cost_entropy(J + 1e3) == pytest.approx(P.cost_entropy(J), rel=1e-10)
+    assert P.cost_entropy(np.concatenate([J, [np.inf, np.nan]])) == pytest.approx(P.cost_entropy(J), rel=1e-14)
+    assert P.cost_entropy(np.array([0.0, 800.0])) < 1e-300 + 1e-12
+    assert P.cost_entropy(np.array([np.inf])) == 0.0

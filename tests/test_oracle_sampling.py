@@ -3,6 +3,7 @@ import itertools
 import math
 
 import numpy as np
+import pytest
 from scipy import stats
 
 from oracle import sampling, philox
@@ -58,3 +59,65 @@ def test_gather_picks_layer_waypoints():
     for p in range(50):
         for l in range(4):
             assert np.array_equal(C[p, l], Z[l, I[p, l]])
+
+
+# ------------------------------------------------------------------ without replacement
+
+@pytest.mark.parametrize("W_, L_", [(2, 1), (2, 4), (3, 3), (5, 2), (4, 4), (7, 2)])
+def test_permutation_is_a_bijection_of_all_paths(W_, L_):
+    """P = W^L paths without replacement enumerate every path exactly once."""
+    D = W_ ** L_
+    I = sampling.path_indices_without_replacement(11, 3, 1, D, L_, W_)
+    assert I.shape == (D, L_) and I.min() >= 0 and I.max() < W_
+    num = (I * (W_ ** np.arange(L_))).sum(axis=1)
+    assert sorted(num.tolist()) == list(range(D))
+
+
+def test_permutation_rounds_are_involutions():
+    keys, fkeys = sampling.perm_round_keys(5, 2, 0, 6, 9)
+    D = 9 ** 6
+    x = [int(v) for v in np.random.default_rng(0).integers(0, D, 500)]
+    for K, fk in list(zip(keys, fkeys))[:6]:
+        assert sampling.perm_round(sampling.perm_round(x, K, fk, 6, 9), K, fk, 6, 9) == x
+    assert len(keys) == sampling.perm_rounds(6, 9) == 2 * 6 * 4
+
+
+def test_digits_recompose():
+    x = [0, 1, 63, 64, 2 ** 40 - 1, 12345678901]
+    d = sampling.digits(x, 8, 32)
+    assert [int(sum(int(v) * 32 ** l for l, v in enumerate(row))) for row in d] == x
+
+
+def test_without_replacement_beyond_64_bits():
+    """W^L = 64^12 = 2^72 paths: the exact integer arithmetic still yields distinct paths."""
+    I = sampling.path_indices_without_replacement(0, 0, 0, 300, 12, 64)
+    assert len({tuple(r) for r in I}) == 300 and I.max() < 64
+
+
+def test_with_replacement_collides_where_without_does_not():
+    """At 200 of 4^4 = 256 paths draws with replacement repeat paths (birthday
+    bound), draws without replacement never do."""
+    Iw = sampling.path_indices(0, 0, 0, 200, 4, 4)
+    Io = sampling.path_indices_without_replacement(0, 0, 0, 200, 4, 4)
+    assert len({tuple(r) for r in Iw}) < 200
+    assert len({tuple(r) for r in Io}) == 200
+
+
+def test_permutation_is_close_to_uniform():
+    """Over many replan indices the first path is uniform over the 8 paths of a
+    2^3 graph and the first two form a uniform ordered pair of distinct paths
+    (chi-square at the 0.1% level)."""
+    from scipy import stats
+    n = 1500
+    first, pair = [], []
+    for r in range(n):
+        I = sampling.path_indices_without_replacement(7, r, 0, 2, 3, 2)
+        a, b = (int((row * (2 ** np.arange(3))).sum()) for row in I)
+        first.append(a)
+        pair.append(a * 8 + b)
+    c1 = np.bincount(first, minlength=8)
+    assert stats.chisquare(c1).pvalue > 1e-3
+    c2 = np.bincount(pair, minlength=64).reshape(8, 8)
+    assert np.all(np.diag(c2) == 0)
+    off = c2[~np.eye(8, dtype=bool)]
+    assert stats.chisquare(off).pvalue > 1e-3
