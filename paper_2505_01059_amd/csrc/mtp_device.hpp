@@ -1253,32 +1253,36 @@ __device__ __forceinline__ uint32_t cost_order(float c) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-constexpr int kTopkBins = 2048;   // 11-bit digits over the 32-bit cost image
+constexpr int kTopkBins = 2048;      // radix digits of up to 11 bits
+constexpr int kTopkCache = 16384;    // batches up to this size keep their cost images in LDS
+constexpr int kTopkRankSort = 1024;  // elite sets up to this size are ordered by counting ranks
 
 struct TopkSmem {
-  unsigned long long keys[kMaxElites];
+  uint32_t cache[kTopkCache];                 // cost images of the batch (when it fits)
+  unsigned long long keys[kMaxElites];        // selected keys, unordered
+  unsigned long long sorted[kTopkRankSort];   // selected keys by rank
   uint32_t hist[kTopkBins];
   unsigned long long prefix;
   uint32_t rank;
   uint32_t count;
   uint32_t sel_count;
+  uint32_t lo, hi;
   float red[kTopkThreads / 64];
+  uint32_t wlo[kTopkThreads / 64], whi[kTopkThreads / 64];
 };
 
-__device__ __forceinline__ unsigned long long topk_key(const PlanDesc& P, int b) {
-  return (static_cast<unsigned long long>(cost_order(P.cost[b])) << 32) | static_cast<uint32_t>(b);
-}
-
 // Wave 0 finds the digit whose bin holds the rank-th key (1-based) of the
-// histogram hist[0..nbins); writes the digit, the rank left inside that bin and
-// the bin's size to shared memory.
+// histogram hist[0..nbins); writes the digit (into the prefix at `shift`), the
+// rank left inside that bin and the bin's size to shared memory.
 __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t rank, unsigned long long prefix,
                                               int shift) {
   const int lane = threadIdx.x;
   if (lane >= 64) return;
-  const int per = nbins / 64;
+  const int per = nbins >= 64 ? nbins / 64 : 1;
+  const int first = lane * per;
   uint32_t tot = 0;
-  for (int i = 0; i < per; ++i) tot += sm.hist[lane * per + i];
+  for (int i = 0; i < per; ++i)
+    if (first + i < nbins) tot += sm.hist[first + i];
   uint32_t inc = tot;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -1288,10 +1292,10 @@ __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t 
   const uint32_t exc = inc - tot;
   if (exc < rank && rank <= inc) {
     uint32_t rr = rank - exc;
-    int d = lane * per;
+    int d = first;
     for (int i = 0; i < per; ++i) {
-      const uint32_t h = sm.hist[lane * per + i];
-      if (rr <= h) { d = lane * per + i; sm.sel_count = h; break; }
+      const uint32_t h = sm.hist[first + i];
+      if (rr <= h) { d = first + i; sm.sel_count = h; break; }
       rr -= h;
     }
     sm.prefix = prefix | (static_cast<unsigned long long>(d) << shift);
@@ -1299,46 +1303,81 @@ __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t 
   }
 }
 
+// Top-E by a radix select over the order-preserving 32-bit cost image, taken
+// relative to the batch minimum so that the first digit spreads the keys over
+// the bins instead of piling them on the few that share an exponent.  If no tie
+// straddles the elite boundary the elites are the keys with image <= c*;
+// otherwise a second radix over the index bits orders the ties by index.  The
+// E keys (image << 32 | index) are then ordered by counting ranks (all keys are
+// distinct), or by a bitonic network for very large E.
 template <int BS>
 __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const int tid = threadIdx.x;
   const int B = P.B, E = P.E;
-  // Radix select over the 32-bit cost image with 11/11/10-bit digits: finds the
-  // image c* of the E-th smallest cost and how many of the keys equal to c* are
-  // needed.  If all of them are (no tie straddles the elite boundary), the elites
-  // are exactly the keys with image <= c*.  Otherwise continue the radix select
-  // over the full 64-bit key (image, index), which orders ties by index.
+  const bool cached = B <= kTopkCache;
+  auto image = [&](int b) -> uint32_t { return cached ? sm.cache[b] : cost_order(P.cost[b]); };
+
+  // images, their minimum and maximum
+  uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+  for (int b = tid; b < B; b += BS) {
+    const uint32_t o = cost_order(P.cost[b]);
+    if (cached) sm.cache[b] = o;
+    lo = min(lo, o);
+    hi = max(hi, o);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, static_cast<uint32_t>(__shfl_xor(static_cast<int>(lo), o, 64)));
+    hi = max(hi, static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), o, 64)));
+  }
+  if ((tid & 63) == 0) { sm.wlo[tid >> 6] = lo; sm.whi[tid >> 6] = hi; }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t l = sm.wlo[0], h = sm.whi[0];
+    for (int w = 1; w < BS / 64; ++w) { l = min(l, sm.wlo[w]); h = max(h, sm.whi[w]); }
+    sm.lo = l; sm.hi = h;
+  }
+  __syncthreads();
+  lo = sm.lo;
+  const uint32_t range = sm.hi - lo;
+  const int bits = range == 0u ? 0 : 32 - __clz(static_cast<int>(range));
+
+  // radix select over v = image - lo, digits of up to 11 bits from the top
   unsigned long long prefix = 0ull, mask = 0ull;
-  uint32_t rank = static_cast<uint32_t>(E);
-  for (int pass = 0; pass < 3; ++pass) {
-    const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0), nb = pass == 2 ? 1024 : 2048;
+  uint32_t rank = static_cast<uint32_t>(E), sel = static_cast<uint32_t>(B);
+  for (int shift = bits; shift > 0;) {
+    const int width = shift < 11 ? shift : 11;
+    shift -= width;
+    const int nb = 1 << width;
     for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
     __syncthreads();
     for (int b = tid; b < B; b += BS) {
-      const uint32_t o = cost_order(P.cost[b]);
-      if ((static_cast<unsigned long long>(o) & mask) == prefix) atomicAdd(&sm.hist[(o >> sh) & (nb - 1)], 1u);
+      const uint32_t v = image(b) - lo;
+      if ((static_cast<unsigned long long>(v) & mask) == prefix) atomicAdd(&sm.hist[(v >> shift) & (nb - 1)], 1u);
     }
     __syncthreads();
-    topk_find_bin(sm, nb, rank, prefix, sh);
+    topk_find_bin(sm, nb, rank, prefix, shift);
     __syncthreads();
     prefix = sm.prefix;
     rank = sm.rank;
-    mask |= static_cast<unsigned long long>(nb - 1) << sh;
+    sel = sm.sel_count;
+    mask |= static_cast<unsigned long long>(nb - 1) << shift;
     __syncthreads();
   }
+  const uint32_t cstar = lo + static_cast<uint32_t>(prefix);   // image of the E-th smallest cost
   unsigned long long limit;   // elites are the keys <= limit
-  if (rank == sm.sel_count) {
-    limit = (prefix << 32) | 0xFFFFFFFFull;
+  if (rank == sel) {
+    limit = (static_cast<unsigned long long>(cstar) << 32) | 0xFFFFFFFFull;
   } else {
     // ties at the boundary: radix over the index bits of the keys with image c*
-    unsigned long long kp = prefix << 32, km = 0xFFFFFFFF00000000ull;
+    unsigned long long kp = 0ull, km = 0ull;
     for (int pass = 0; pass < 3; ++pass) {
       const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0), nb = pass == 2 ? 1024 : 2048;
       for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
       __syncthreads();
       for (int b = tid; b < B; b += BS) {
-        const unsigned long long key = topk_key(P, b);
-        if ((key & km) == kp) atomicAdd(&sm.hist[(key >> sh) & static_cast<unsigned long long>(nb - 1)], 1u);
+        const unsigned long long ib = static_cast<uint32_t>(b);
+        if (image(b) == cstar && (ib & km) == kp) atomicAdd(&sm.hist[(ib >> sh) & static_cast<unsigned long long>(nb - 1)], 1u);
       }
       __syncthreads();
       topk_find_bin(sm, nb, rank, kp, sh);
@@ -1348,41 +1387,68 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
       km |= static_cast<unsigned long long>(nb - 1) << sh;
       __syncthreads();
     }
-    limit = kp;
+    limit = (static_cast<unsigned long long>(cstar) << 32) | kp;
   }
-  int M = 1;
-  while (M < E) M <<= 1;
+  // gather the E keys <= limit, one counter bump per wave
   if (tid == 0) sm.count = 0u;
-  for (int i = tid; i < M; i += BS) sm.keys[i] = ~0ull;
   __syncthreads();
-  for (int b = tid; b < B; b += BS) {
-    const unsigned long long key = topk_key(P, b);
-    if (key <= limit) {
-      const uint32_t slot = atomicAdd(&sm.count, 1u);
-      if (slot < static_cast<uint32_t>(M)) sm.keys[slot] = key;
+  for (int base = 0; base < B; base += BS) {
+    const int b = base + tid;
+    unsigned long long key = 0ull;
+    bool take = false;
+    if (b < B) {
+      key = (static_cast<unsigned long long>(image(b)) << 32) | static_cast<uint32_t>(b);
+      take = key <= limit;
+    }
+    const unsigned long long m = __ballot(take);
+    if (m != 0ull) {
+      const int lane = tid & 63;
+      const int leader = __ffsll(static_cast<long long>(m)) - 1;
+      uint32_t slot0 = 0u;
+      if (lane == leader) slot0 = atomicAdd(&sm.count, static_cast<uint32_t>(__popcll(m)));
+      slot0 = static_cast<uint32_t>(__shfl(static_cast<int>(slot0), leader, 64));
+      const uint32_t slot = slot0 + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+      if (take && slot < static_cast<uint32_t>(kMaxElites)) sm.keys[slot] = key;
     }
   }
   __syncthreads();
-  // bitonic sort ascending of M keys
-  for (int size = 2; size <= M; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < M; i += BS) {
-        const int jx = i ^ stride;
-        if (jx > i) {
-          const bool up = ((i & size) == 0);
-          const unsigned long long a = sm.keys[i], c = sm.keys[jx];
-          if ((a > c) == up) { sm.keys[i] = c; sm.keys[jx] = a; }
+  const unsigned long long* ord;
+  if (E <= kTopkRankSort) {
+    // rank of each key among the E (keys are distinct)
+    for (int e = tid; e < E; e += BS) {
+      const unsigned long long k = sm.keys[e];
+      int r = 0;
+      for (int q = 0; q < E; ++q) r += sm.keys[q] < k ? 1 : 0;
+      sm.sorted[r] = k;
+    }
+    ord = sm.sorted;
+  } else {
+    int M = 1;
+    while (M < E) M <<= 1;
+    for (int i = E + tid; i < M; i += BS) sm.keys[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= M; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = tid; i < M; i += BS) {
+          const int jx = i ^ stride;
+          if (jx > i) {
+            const bool up = ((i & size) == 0);
+            const unsigned long long a = sm.keys[i], c = sm.keys[jx];
+            if ((a > c) == up) { sm.keys[i] = c; sm.keys[jx] = a; }
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
+    ord = sm.keys;
   }
+  __syncthreads();
   // elites, costs and softmax weights w_e = exp(-(s_e - s_0)/lambda) / sum
-  const uint32_t i0 = static_cast<uint32_t>(sm.keys[0]);
+  const uint32_t i0 = static_cast<uint32_t>(ord[0]);
   const float s0 = P.cost[i0 < static_cast<uint32_t>(B) ? i0 : 0u];
   const bool uniform = !(P.lam < INFINITY) || !(s0 < INFINITY);
   for (int e = tid; e < E; e += BS) {
-    uint32_t uidx = static_cast<uint32_t>(sm.keys[e]);
+    uint32_t uidx = static_cast<uint32_t>(ord[e]);
     if (uidx >= static_cast<uint32_t>(B)) { uidx = 0u; atomicOr(&P.ctrl[2], 2u); }   // never expected
     const int idx = static_cast<int>(uidx);
     const float ce = P.cost[idx];

@@ -199,6 +199,32 @@ def test_topk_sizes(E, torch_mod):
     plan.close()
 
 
+@pytest.mark.parametrize("B, E, kind", [(70000, 512, "ties"), (20011, 1500, "uniform"), (3000, 100, "equal"),
+                                        (17000, 4096, "ties"), (16384, 1, "uniform")])
+def test_topk_batches_beyond_the_lds_cache_and_degenerate(B, E, kind, torch_mod):
+    """Top-E for batches larger than the cost cache (read from HBM every pass),
+    with rounded costs (many ties across the elite boundary), all-equal costs
+    (only the index order decides) and the largest elite sets."""
+    import torch
+    cfg = W.point_mass_config(n_tensor=B - 40, n_gauss=40, n_elites=E)
+    _log(f"[topk] B={B} E={E} {kind}")
+    plan = make_plan(cfg)
+    b = plan.buffers()
+    rng = np.random.default_rng(B + E)
+    if kind == "ties":
+        s = np.round(rng.normal(50.0, 3.0, size=B), 1).astype(np.float32)
+        s[rng.choice(B, 30, replace=False)] = np.inf
+    elif kind == "equal":
+        s = np.full(B, 1.5, np.float32)
+    else:
+        s = rng.uniform(0, 10, size=B).astype(np.float32)
+    b["cost"].copy_(torch.from_numpy(s).cuda())
+    plan.run_stage(2, 0, 0)
+    torch_mod.cuda.synchronize()
+    assert np.array_equal(b["elite_idx"].cpu().numpy(), OP.top_elites(s.astype(np.float64), E))
+    plan.close()
+
+
 def test_all_inf_costs_flag_uniform_weights(torch_mod):
     import torch
     cfg = W.point_mass_config(n_tensor=100, n_gauss=28, n_elites=8)
