@@ -66,25 +66,36 @@ def traffic_from_profiles(workload):
         return None
 
 
-def cpu_baseline(cfg, x0):
-    """Oracle (FP64 NumPy, as written) on one CEM iteration of the same workload, one thread."""
+def cpu_baseline(cfg, x0, min_seconds=10.0, max_iters=100000):
+    """Oracle (FP64 NumPy, as written) on CEM iterations of the same workload, one
+    thread: whole iterations until at least min_seconds have passed."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import planner as OP
     mu, sg = OP.initial_distribution(cfg)
     sub = cfg
     if cfg.n_samples > 20000:
-        # bounded sample: the first 1024 candidates of the batch, same horizon and model
-        sub = cfg.replace(n_tensor=1024 - min(cfg.n_gauss, 128), n_gauss=min(cfg.n_gauss, 128),
-                          n_elites=min(cfg.n_elites, 64))
+        # bounded sample: the first 256 candidates of the batch, same horizon and model
+        G = min(cfg.n_gauss, 32)
+        sub = cfg.replace(n_tensor=256 - G, n_gauss=G, n_elites=min(cfg.n_elites, 16))
+        if cfg.sample_params is not None:
+            B, R = cfg.n_samples, max(1, int(cfg.n_replicas))
+            rows = [cfg.sample_params[r * B:r * B + sub.n_samples] for r in range(R)]
+            sub = sub.replace(sample_params=np.concatenate(rows, axis=0))
+    iters = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        OP.iterate(sub, x0, mu, sg, 0, 0)
-        dt = time.perf_counter() - t0
-    steps = sub.n_samples * sub.horizon
+        while True:
+            out = OP.iterate(sub, x0, mu, sg, 0, iters)
+            mu, sg = out["mu"], out["sigma"]
+            iters += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_seconds or iters >= max_iters:
+                break
+    steps = sub.n_samples * sub.horizon * iters
     return {
         "value": steps / dt, "unit": "rollout steps/s", "cores": 1, "kind": "oracle",
-        "sample": f"one CEM iteration, {sub.n_samples} candidates x {sub.horizon} steps "
+        "sample": f"{iters} CEM iteration(s), {sub.n_samples} candidates x {sub.horizon} steps each "
                   f"(FP64 NumPy oracle, 1 thread, {dt:.1f} s; host {cpu_model()}, nproc {os.cpu_count()})",
     }
 
