@@ -37,6 +37,8 @@ def workloads():
         "chain7_akima": W.c1,
         "point_mass_bspline": W.c0,
         "chain24_contact_bspline": W.c4,
+        "chain24_contact_share8": lambda: W.c4_share(8),
+        "point_mass_paper": W.p0,
         "mix256": lambda: W.mix(256),
         "serve512": lambda: ("serve", W.robot_fleet(512)),
     }

@@ -241,6 +241,22 @@ def c4() -> Config:
     return chain_contact_config()
 
 
+def c4_share(n_gpus: int = 8) -> Config:
+    """One GPU's share of the 24-link contact chain split over n_gpus: B/n_gpus
+    candidates (tensor and Gaussian counts both divided) at the same T, n, L, W."""
+    full = chain_contact_config()
+    return chain_contact_config(name=f"chain24_contact_share{n_gpus}", n_tensor=full.n_tensor // n_gpus,
+                                n_gauss=full.n_gauss // n_gpus, n_elites=full.n_elites)
+
+
+def p0() -> Config:
+    """Point mass at the sizes of the paper's Navigation runs (Section 5.1, Tab. 3):
+    B = 256 all from the tensor (beta = 1, the nominal kept as the one Gaussian
+    slot), L = 5, W = 30, T = 20, dt = 0.05."""
+    return point_mass_config(name="point_mass_paper", n_tensor=255, n_gauss=1, n_layers=5, n_width=30,
+                             horizon=20, dt=0.05, n_elites=16, n_iters=10)
+
+
 def mix_instance(seed: int) -> Config:
     """One instance of the uneven batching mix (256 of these form the batch).
 
