@@ -958,107 +958,125 @@ constexpr bool pair_chain_links() { return N >= 10 && (N % 2) == 0; }
 
 __device__ __forceinline__ float pswap(float v) { return qperm<kQXor1>(v); }
 
+// Both lanes work in their own local order: local link i of lane B is global
+// link N-1-i, so walking i upwards moves from the lane's outer end towards the
+// middle.  Lane B also takes its link directions reversed (sin and cos of
+// phi + pi), i.e. pointing from local node i to local node i+1 as in lane A.  In
+// that frame the tension system, the contact terms and the accelerations have
+// the same form in both lanes: with node i between local links i-1 and i,
+//   row i:  -imP_i P_{i-1} T_{i-1} + (imP_i + imN_i) T_i - imN_i P_i T_{i+1} = rhs_i
+// (imP, imN: inverse masses of the nodes before and after the link), and the
+// relative acceleration of a link's two nodes is F[i+1] - F[i].  Lane A's node 0
+// is the pinned base (inverse mass 0, relative acceleration +g against free fall);
+// lane B's node 0 is the free tip.  Only the torque difference q, the start of
+// the node positions (the tip, for lane B) and the sign of the end-effector sum
+// depend on the lane, once per step.
+
 template <int N>
 struct PairConsts {
   static constexpr int M = N / 2;
-  float l[M], invl[M], im[M];      // own links in local order
-  float im_mid_other;              // inverse mass of the other lane's local link M-1
-  float g;
+  float l[M], invl[M];   // own links in local order
+  float im[M + 1];       // inverse masses of local nodes 0..M (node M is the middle one)
+  float half;            // revolution offset of the local frame: 0 (lane A) or 1/2 (lane B)
+  float bf;              // 1 for lane B, 0 for lane A
+  float g0;              // base node's relative acceleration against free fall: g (lane A), 0 (lane B)
+  float sgn;             // +1 (lane A), -1 (lane B)
   float yg, kc, dc, inv_vs, muf;   // contact only
-  bool B;                          // lane owns the tip half (reverse order)
+  bool B;                // lane owns the tip half
 };
 
 template <int N>
 __device__ __forceinline__ int pair_link(bool B, int i) { return B ? N - 1 - i : i; }
 
+// mass index (0-based link whose distal end carries it) of local node i
+template <int N>
+__device__ __forceinline__ int pair_node_mass(bool B, int i) { return B ? (i < N / 2 ? N - 1 - i : N / 2 - 1) : i - 1; }
+
+template <int N>
+__device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N>& K) {
+  constexpr int M = N / 2;
+#pragma unroll
+  for (int i = 0; i <= M; ++i) K.im[i] = (i == 0 && !K.B) ? 0.0f : 1.0f / m[pair_node_mass<N>(K.B, i)];
+}
+
+// sin and cos of phi + half revolution
+__device__ __forceinline__ void hw_sincos_off(float x, float half, float* s, float* c) {
+  const float rev = __builtin_amdgcn_fractf(fmaf(x, 0.15915494309189535f, half));
+  *s = __builtin_amdgcn_sinf(rev);
+  *c = __builtin_amdgcn_cosf(rev);
+}
+
+// Local-frame accelerations of the lane's M links from the local sin/cos, the
+// angular velocities and the per-step torque terms q (q_o: the other lane's
+// link next to the middle).
 template <int N, bool CONTACT>
 __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
-                                           const float (&q)[N / 2], float q_other, const PairConsts<N>& K,
+                                           const float (&q)[N / 2], float q_o, const PairConsts<N>& K,
                                            float (&acc)[N / 2]) {
   constexpr int M = N / 2;
-  const bool B = K.B;
-  // trig of neighbouring local links; entry M-1 pairs with the other lane's link
-  float P[M], Q[M];
-#pragma unroll
-  for (int i = 0; i + 1 < M; ++i) {
-    P[i] = fmaf(c[i], c[i + 1], s[i] * s[i + 1]);
-    Q[i] = fmaf(s[i], c[i + 1], -c[i] * s[i + 1]);
-  }
-  {
-    const float so = pswap(s[M - 1]), co = pswap(c[M - 1]);
-    P[M - 1] = fmaf(c[M - 1], co, s[M - 1] * so);
-    Q[M - 1] = fmaf(s[M - 1], co, -c[M - 1] * so);
-  }
-  // non-constraint accelerations (contact forces / mass); gravity enters at the base
-  float fx[CONTACT ? M : 1], fy[CONTACT ? M : 1];
-  float fxo = 0.0f, fyo = 0.0f;
+  // the other lane's middle link in this lane's frame (its frame is reversed)
+  const float so = -pswap(s[M - 1]), co = -pswap(c[M - 1]);
+  // node relative accelerations F[0..M]
+  float Fx[M + 1], Fy[M + 1];
   if constexpr (CONTACT) {
-    float tx = 0.0f, ty = 0.0f, tvx = 0.0f, tvy = 0.0f;
+    // node heights and velocities: y_{i+1} = y_i - l_i c_i, v_{i+1} = v_i + l_i w_i (c_i, s_i)
+    float py[M + 1], vx[M + 1], vy[M + 1];
+    py[0] = 0.0f; vx[0] = 0.0f; vy[0] = 0.0f;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       const float lw = K.l[i] * w[i];
-      tx = fmaf(K.l[i], s[i], tx);
-      ty = fmaf(-K.l[i], c[i], ty);
-      tvx = fmaf(lw, c[i], tvx);
-      tvy = fmaf(lw, s[i], tvy);
+      py[i + 1] = fmaf(-K.l[i], c[i], py[i]);
+      vx[i + 1] = fmaf(lw, c[i], vx[i]);
+      vy[i + 1] = fmaf(lw, s[i], vy[i]);
     }
-    const float Tx = tx + pswap(tx), Ty = ty + pswap(ty), Tvx = tvx + pswap(tvx), Tvy = tvy + pswap(tvy);
-    float ex = 0.0f, ey = 0.0f, evx = 0.0f, evy = 0.0f;   // sums over local links before i
+    // lane B starts at the tip: the sum of lane A's links minus its own (reversed) ones
+    const float y0 = K.bf * (pswap(py[M]) - py[M]);
+    const float u0 = K.bf * (pswap(vx[M]) - vx[M]), v0 = K.bf * (pswap(vy[M]) - vy[M]);
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const float lw = K.l[i] * w[i];
-      const float ox = K.l[i] * s[i], oy = -K.l[i] * c[i], ovx = lw * c[i], ovy = lw * s[i];
-      const float py = B ? Ty - ey : ey + oy;
-      const float vx = B ? Tvx - evx : evx + ovx;
-      const float vy = B ? Tvy - evy : evy + ovy;
-      ex += ox; ey += oy; evx += ovx; evy += ovy;
-      const float pen = K.yg - py;
-      float ffx = 0.0f, ffy = 0.0f;
+    for (int i = 0; i <= M; ++i) {
+      const float yy = py[i] + y0, vyy = vy[i] + v0, vxx = vx[i] + u0;
+      const float pen = K.yg - yy;
+      float fx = 0.0f, fy = 0.0f;
       if (pen > 0.0f) {
-        const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vy), 0.0f);
-        const float ft = -K.muf * fn * fast_tanh(vx * K.inv_vs);
-        ffx = ft * K.im[i];
-        ffy = fn * K.im[i];
+        const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vyy), 0.0f);
+        fx = -K.muf * fn * fast_tanh(vxx * K.inv_vs) * K.im[i];
+        fy = fn * K.im[i];
       }
-      fx[i] = ffx;
-      fy[i] = ffy;
+      Fx[i] = fx;
+      Fy[i] = fy;
     }
-    (void)Tx;
-    fxo = pswap(fx[M - 1]);
-    fyo = pswap(fy[M - 1]);
+  } else {
+#pragma unroll
+    for (int i = 0; i <= M; ++i) { Fx[i] = 0.0f; Fy[i] = 0.0f; }
   }
+  Fy[0] += K.g0;
+  // forward elimination from the lane's outer end towards the middle
   float cp[M], dp[M];
   float cp_prev = 0.0f, dp_prev = 0.0f;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    const float tipP = B ? (i > 0 ? P[i - 1] : 0.0f) : P[i];
-    const float tipQ = B ? (i > 0 ? -Q[i - 1] : 0.0f) : Q[i];
-    const float baseP = B ? P[i] : (i > 0 ? P[i - 1] : 0.0f);
-    const float baseQ = B ? -Q[i] : (i > 0 ? Q[i - 1] : 0.0f);
-    const float q_tip = B ? (i > 0 ? q[i - 1] : 0.0f) : (i + 1 < M ? q[i + 1] : q_other);
-    const float q_base = B ? (i + 1 < M ? q[i + 1] : q_other) : (i > 0 ? q[i - 1] : 0.0f);
-    const float im_base = B ? (i + 1 < M ? K.im[i + 1] : K.im_mid_other) : (i > 0 ? K.im[i - 1] : 0.0f);
-    float dfx = 0.0f, dfy = 0.0f;
-    if constexpr (CONTACT) {
-      const float fbx = B ? (i + 1 < M ? fx[i + 1] : fxo) : (i > 0 ? fx[i - 1] : 0.0f);
-      const float fby = B ? (i + 1 < M ? fy[i + 1] : fyo) : (i > 0 ? fy[i - 1] : 0.0f);
-      dfx = fx[i] - fbx;
-      dfy = fy[i] - fby;
-    }
-    if (i == 0 && !B) dfy -= K.g;
-    const float D = K.im[i] + im_base;
-    const float tip_coef = -K.im[i] * tipP;
-    const float base_coef = -im_base * baseP;
+    const float sn = (i + 1 < M) ? s[i + 1] : so, cn = (i + 1 < M) ? c[i + 1] : co;
+    const float Pn = fmaf(c[i], cn, s[i] * sn);            // cos(phi_i - phi_{i+1})
+    const float Qn = fmaf(s[i], cn, -c[i] * sn);           // sin(phi_i - phi_{i+1})
     float rhs = K.l[i] * w[i] * w[i];
-    rhs = fmaf(s[i], dfx, rhs);
-    rhs = fmaf(-c[i], dfy, rhs);
-    rhs = fmaf(-K.im[i] * q_tip, tipQ, rhs);
-    rhs = fmaf(im_base * q_base, baseQ, rhs);
-    const float Lp = B ? tip_coef : base_coef;
-    const float Un = B ? base_coef : tip_coef;
-    const float inv = __builtin_amdgcn_rcpf(fmaf(-Lp, cp_prev, D));
-    cp_prev = Un * inv;
-    dp_prev = fmaf(-Lp, dp_prev, rhs) * inv;
+    rhs = fmaf(s[i], Fx[i + 1] - Fx[i], rhs);
+    rhs = fmaf(-c[i], Fy[i + 1] - Fy[i], rhs);
+    const float qn = (i + 1 < M) ? q[i + 1] : q_o;
+    rhs = fmaf(-K.im[i + 1] * qn, Qn, rhs);
+    float Dg = K.im[i] + K.im[i + 1];
+    if (i > 0) {
+      const float Pp = fmaf(c[i - 1], c[i], s[i - 1] * s[i]);
+      const float Qp = fmaf(s[i - 1], c[i], -c[i - 1] * s[i]);
+      rhs = fmaf(K.im[i] * q[i - 1], Qp, rhs);
+      const float Lp = -K.im[i] * Pp;
+      const float inv = __builtin_amdgcn_rcpf(fmaf(-Lp, cp_prev, Dg));
+      cp_prev = -K.im[i + 1] * Pn * inv;
+      dp_prev = fmaf(-Lp, dp_prev, rhs) * inv;
+    } else {
+      const float inv = __builtin_amdgcn_rcpf(Dg);
+      cp_prev = -K.im[i + 1] * Pn * inv;
+      dp_prev = rhs * inv;
+    }
     cp[i] = cp_prev;
     dp[i] = dp_prev;
   }
@@ -1070,40 +1088,21 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
 #pragma unroll
   for (int i = M - 2; i >= 0; --i) dp[i] = fmaf(-cp[i], dp[i + 1], dp[i]);
   const float xo = pswap(dp[M - 1]);
-  // neighbour trig again (cheaper than keeping it live across the solve)
-  {
-    const float so = pswap(s[M - 1]), co = pswap(c[M - 1]);
-#pragma unroll
-    for (int i = 0; i + 1 < M; ++i) {
-      P[i] = fmaf(c[i], c[i + 1], s[i] * s[i + 1]);
-      Q[i] = fmaf(s[i], c[i + 1], -c[i] * s[i + 1]);
-    }
-    P[M - 1] = fmaf(c[M - 1], co, s[M - 1] * so);
-    Q[M - 1] = fmaf(s[M - 1], co, -c[M - 1] * so);
-  }
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    const float tipP = B ? (i > 0 ? P[i - 1] : 0.0f) : P[i];
-    const float tipQ = B ? (i > 0 ? -Q[i - 1] : 0.0f) : Q[i];
-    const float baseP = B ? P[i] : (i > 0 ? P[i - 1] : 0.0f);
-    const float baseQ = B ? -Q[i] : (i > 0 ? Q[i - 1] : 0.0f);
-    const float q_tip = B ? (i > 0 ? q[i - 1] : 0.0f) : (i + 1 < M ? q[i + 1] : q_other);
-    const float q_base = B ? (i + 1 < M ? q[i + 1] : q_other) : (i > 0 ? q[i - 1] : 0.0f);
-    const float im_base = B ? (i + 1 < M ? K.im[i + 1] : K.im_mid_other) : (i > 0 ? K.im[i - 1] : 0.0f);
-    const float T_tip = B ? (i > 0 ? dp[i - 1] : 0.0f) : (i + 1 < M ? dp[i + 1] : xo);
-    const float T_base = B ? (i + 1 < M ? dp[i + 1] : xo) : (i > 0 ? dp[i - 1] : 0.0f);
-    float a = (K.im[i] + im_base) * q[i];
-    a = fmaf(-K.im[i], fmaf(T_tip, tipQ, q_tip * tipP), a);
-    a = fmaf(-im_base, fmaf(-T_base, baseQ, q_base * baseP), a);
-    float dfx = 0.0f, dfy = 0.0f;
-    if constexpr (CONTACT) {
-      const float fbx = B ? (i + 1 < M ? fx[i + 1] : fxo) : (i > 0 ? fx[i - 1] : 0.0f);
-      const float fby = B ? (i + 1 < M ? fy[i + 1] : fyo) : (i > 0 ? fy[i - 1] : 0.0f);
-      dfx = fx[i] - fbx;
-      dfy = fy[i] - fby;
+    const float sn = (i + 1 < M) ? s[i + 1] : so, cn = (i + 1 < M) ? c[i + 1] : co;
+    const float Pn = fmaf(c[i], cn, s[i] * sn);
+    const float Qn = fmaf(s[i], cn, -c[i] * sn);
+    const float qn = (i + 1 < M) ? q[i + 1] : q_o;
+    const float Tn = (i + 1 < M) ? dp[i + 1] : xo;
+    float a = (K.im[i] + K.im[i + 1]) * q[i];
+    a = fmaf(-K.im[i + 1], fmaf(Tn, Qn, qn * Pn), a);
+    if (i > 0) {
+      const float Pp = fmaf(c[i - 1], c[i], s[i - 1] * s[i]);
+      const float Qp = fmaf(s[i - 1], c[i], -c[i - 1] * s[i]);
+      a = fmaf(-K.im[i], fmaf(-dp[i - 1], Qp, q[i - 1] * Pp), a);
     }
-    if (i == 0 && !B) dfy -= K.g;
-    a = fmaf(c[i], dfx, fmaf(s[i], dfy, a));
+    a = fmaf(c[i], Fx[i + 1] - Fx[i], fmaf(s[i], Fy[i + 1] - Fy[i], a));
     acc[i] = a * K.invl[i];
   }
 }
@@ -1117,21 +1116,21 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
   const float* tk = P.task;
   PairConsts<N> K;
   K.B = B;
-  K.g = tk[0];
+  K.half = B ? 0.5f : 0.0f;
+  K.bf = B ? 1.0f : 0.0f;
+  K.g0 = B ? 0.0f : tk[0];
+  K.sgn = B ? -1.0f : 1.0f;
   const float wg = tk[1], wu = tk[2], tgx = tk[3], tgy = tk[4];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    const int k = pair_link<N>(B, i);
-    K.l[i] = tk[5 + N + k];
+    K.l[i] = tk[5 + N + pair_link<N>(B, i)];
     K.invl[i] = 1.0f / K.l[i];
   }
   if constexpr (CONTACT) {
     K.yg = tk[5 + 2 * N]; K.kc = tk[6 + 2 * N]; K.dc = tk[7 + 2 * N]; K.inv_vs = 1.0f / tk[8 + 2 * N];
   } else {
-#pragma unroll
-    for (int i = 0; i < M; ++i) K.im[i] = 1.0f / tk[5 + pair_link<N>(B, i)];
+    pair_load_masses<N>(tk + 5, K);
     K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
-    K.im_mid_other = pswap(K.im[M - 1]);
   }
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
   // randomised models: the candidate's cost is the mean over R rollouts
@@ -1141,10 +1140,8 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
   for (int rep = 0; rep < R; ++rep) {
   if constexpr (CONTACT) {
     const float* sp = P.sparams + (static_cast<size_t>(rep) * P.B + b) * (N + 1);
-#pragma unroll
-    for (int i = 0; i < M; ++i) K.im[i] = 1.0f / sp[pair_link<N>(B, i)];
+    pair_load_masses<N>(sp, K);
     K.muf = sp[N];
-    K.im_mid_other = pswap(K.im[M - 1]);
   }
   float ph[M], om[M], s[M], c[M];
 #pragma unroll
@@ -1152,7 +1149,7 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     const int k = pair_link<N>(B, i);
     ph[i] = P.x0[k];
     om[i] = P.x0[N + k];
-    hw_sincos(ph[i], &s[i], &c[i]);
+    hw_sincos_off(ph[i], K.half, &s[i], &c[i]);
   }
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* ub = P.U + b;
@@ -1165,7 +1162,8 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     const bool more = (t + 1 < P.T);
 #pragma unroll
     for (int i = 0; i < M; ++i) un[i] = more ? ub[((t + 1) * N + pair_link<N>(B, i)) * ld] : 0.0f;
-    // torque terms (u_k - u_{k+1}) / l_k; the tip neighbour of lane A's last link is lane B's
+    // torque terms (u_k - u_{k+1}) / l_k: the distal neighbour is local i+1 in lane A
+    // (the other lane's link at the middle) and local i-1 in lane B (none at the tip)
     float q[M];
     const float u_other = pswap(u[M - 1]);
 #pragma unroll
@@ -1173,10 +1171,10 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
       const float u_tip = B ? (i > 0 ? u[i - 1] : 0.0f) : (i + 1 < M ? u[i + 1] : u_other);
       q[i] = (u[i] - u_tip) * K.invl[i];
     }
-    const float q_other = pswap(q[M - 1]);
+    const float q_o = pswap(q[M - 1]);
 
     float kk[M], oms[M], aph[M], aom[M];
-    pair_accel<N, CONTACT>(s, c, om, q, q_other, K, kk);
+    pair_accel<N, CONTACT>(s, c, om, q, q_o, K, kk);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       aph[i] = om[i];
@@ -1189,10 +1187,10 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
       float s2[M], c2[M];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        hw_sincos(fmaf(h, oms[i], ph[i]), &s2[i], &c2[i]);
+        hw_sincos_off(fmaf(h, oms[i], ph[i]), K.half, &s2[i], &c2[i]);
         oms[i] = fmaf(h, kk[i], om[i]);
       }
-      pair_accel<N, CONTACT>(s2, c2, oms, q, q_other, K, kk);
+      pair_accel<N, CONTACT>(s2, c2, oms, q, q_o, K, kk);
       const float wgt = (stage == 3) ? 1.0f : 2.0f;
 #pragma unroll
       for (int i = 0; i < M; ++i) {
@@ -1205,11 +1203,14 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     for (int i = 0; i < M; ++i) {
       ph[i] = fmaf(dt6, aph[i], ph[i]);
       om[i] = fmaf(dt6, aom[i], om[i]);
-      hw_sincos(ph[i], &s[i], &c[i]);
+      hw_sincos_off(ph[i], K.half, &s[i], &c[i]);
       ex = fmaf(K.l[i], s[i], ex);
       ey = fmaf(-K.l[i], c[i], ey);
       uu = fmaf(u[i], u[i], uu);
     }
+    // end effector: the lanes' link sums, lane B's taken back to the physical frame
+    ex *= K.sgn;
+    ey *= K.sgn;
     ex += pswap(ex);
     ey += pswap(ey);
     uu += pswap(uu);
