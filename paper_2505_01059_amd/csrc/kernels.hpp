@@ -12,5 +12,10 @@ hipError_t launch_set_ctrl(const PlanDesc& P, uint32_t r, int shift, const float
 hipError_t launch_shift(const PlanDesc& P, hipStream_t st);
 // stage: 0 candidates, 1 rollout, 2 top-E, 3 refit (the replan index is read from P.ctrl[0])
 hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st);
+// Grid and segment count of the time-sliced pair-lane rollout for the current
+// device (no-op for plans that do not use it).
+hipError_t seg_configure(PlanDesc* P);
+// defined in plan.cpp
+int segment_count(int groups, int resident_waves);
 
 }  // namespace mtp

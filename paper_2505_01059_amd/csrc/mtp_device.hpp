@@ -58,6 +58,11 @@ struct PlanDesc {
   float* w;              // [E]
   float* X;              // [T][d][n_dbg] or null
   float* entropy;        // [K] cost entropy of each iteration of the last replan
+  // time-sliced pair-lane rollout (long chains, launches of more waves than SIMDs); null when unused
+  struct SegCtl* seg_ctl;
+  uint32_t* seg_done;    // [groups] segments completed, tagged with the launch epoch
+  float* seg_state;      // [(n + 1)][groups][64] angles, rates and cost between segments
+  int32_t seg_S, seg_len, seg_grid;
 };
 
 // ------------------------------------------------------------------ Philox
@@ -1107,20 +1112,15 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
   }
 }
 
-// One candidate b per lane pair; B is the tip-half lane.  Both lanes of a pair
-// must run this together.
 template <int N, bool CONTACT>
-__device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, bool B) {
-  static_assert(N >= 10 && N % 2 == 0, "pair-lane chain needs an even link count >= 10");
+__device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts<N>& K) {
   constexpr int M = N / 2;
   const float* tk = P.task;
-  PairConsts<N> K;
   K.B = B;
   K.half = B ? 0.5f : 0.0f;
   K.bf = B ? 1.0f : 0.0f;
   K.g0 = B ? 0.0f : tk[0];
   K.sgn = B ? -1.0f : 1.0f;
-  const float wg = tk[1], wu = tk[2], tgx = tk[3], tgy = tk[4];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     K.l[i] = tk[5 + N + pair_link<N>(B, i)];
@@ -1132,34 +1132,29 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     pair_load_masses<N>(tk + 5, K);
     K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
   }
+}
+
+// Steps [t0, t1) of candidate b from the physical angles ph and rates om of the
+// lane's links (updated in place), adding each step's cost to `cost`.
+template <int N, bool CONTACT>
+__device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N>& K, int b, float (&ph)[N / 2],
+                                           float (&om)[N / 2], float& cost, int t0, int t1, bool record) {
+  constexpr int M = N / 2;
+  const bool B = K.B;
+  const float* tk = P.task;
+  const float wg = tk[1], wu = tk[2], tgx = tk[3], tgy = tk[4];
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
-  // randomised models: the candidate's cost is the mean over R rollouts
-  const int R = CONTACT ? P.R : 1;
-  float total = 0.0f;
-#pragma unroll 1
-  for (int rep = 0; rep < R; ++rep) {
-  if constexpr (CONTACT) {
-    const float* sp = P.sparams + (static_cast<size_t>(rep) * P.B + b) * (N + 1);
-    pair_load_masses<N>(sp, K);
-    K.muf = sp[N];
-  }
-  float ph[M], om[M], s[M], c[M];
+  float s[M], c[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) {
-    const int k = pair_link<N>(B, i);
-    ph[i] = P.x0[k];
-    om[i] = P.x0[N + k];
-    hw_sincos_off(ph[i], K.half, &s[i], &c[i]);
-  }
+  for (int i = 0; i < M; ++i) hw_sincos_off(ph[i], K.half, &s[i], &c[i]);
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* ub = P.U + b;
   float u[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) u[i] = ub[pair_link<N>(B, i) * ld];
-  float cost = 0.0f;
-  for (int t = 0; t < P.T; ++t) {
+  for (int i = 0; i < M; ++i) u[i] = ub[(t0 * N + pair_link<N>(B, i)) * ld];
+  for (int t = t0; t < t1; ++t) {
     float un[M];
-    const bool more = (t + 1 < P.T);
+    const bool more = (t + 1 < t1);
 #pragma unroll
     for (int i = 0; i < M; ++i) un[i] = more ? ub[((t + 1) * N + pair_link<N>(B, i)) * ld] : 0.0f;
     // torque terms (u_k - u_{k+1}) / l_k: the distal neighbour is local i+1 in lane A
@@ -1216,7 +1211,7 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     uu += pswap(uu);
     const float dx = ex - tgx, dy = ey - tgy;
     cost += fmaf(wg, fmaf(dx, dx, dy * dy), wu * uu);
-    if (rep == 0 && b < P.n_dbg) {
+    if (record && b < P.n_dbg) {
       float* X = P.X + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
 #pragma unroll
@@ -1229,9 +1224,140 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
 #pragma unroll
     for (int i = 0; i < M; ++i) u[i] = un[i];
   }
-  total += cost;
+}
+
+template <int N>
+__device__ __forceinline__ void pair_start(const PlanDesc& P, bool B, float (&ph)[N / 2], float (&om)[N / 2]) {
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const int k = pair_link<N>(B, i);
+    ph[i] = P.x0[k];
+    om[i] = P.x0[N + k];
+  }
+}
+
+// One candidate b per lane pair; B is the tip-half lane.  Both lanes of a pair
+// must run this together.
+template <int N, bool CONTACT>
+__device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, bool B) {
+  static_assert(N >= 10 && N % 2 == 0, "pair-lane chain needs an even link count >= 10");
+  constexpr int M = N / 2;
+  PairConsts<N> K;
+  pair_setup<N, CONTACT>(P, B, K);
+  // randomised models: the candidate's cost is the mean over R rollouts
+  const int R = CONTACT ? P.R : 1;
+  float total = 0.0f;
+#pragma unroll 1
+  for (int rep = 0; rep < R; ++rep) {
+    if constexpr (CONTACT) {
+      const float* sp = P.sparams + (static_cast<size_t>(rep) * P.B + b) * (N + 1);
+      pair_load_masses<N>(sp, K);
+      K.muf = sp[N];
+    }
+    float ph[M], om[M];
+    pair_start<N>(P, B, ph, om);
+    float cost = 0.0f;
+    pair_steps<N, CONTACT>(P, K, b, ph, om, cost, 0, P.T, rep == 0);
+    total += cost;
   }
   if (!B) P.cost[b] = finite_or_inf(R == 1 ? total : total / static_cast<float>(R));
+}
+
+// ------------------------------------------------------------------ time-sliced pair rollout
+// A launch of G pair-lane waves on fewer SIMDs runs in ceil(G / SIMDs) rounds
+// of whole horizons; when G is slightly above a multiple, the last round leaves
+// most SIMDs idle (24 links, 69632 candidates: 2176 waves, 3 rounds for 2.125
+// rounds of work).  Here the horizon is cut into S segments and resident waves
+// take (wave group, segment) units from a counter in segment-major order, saving
+// the group's state (angles, rates, cost so far) between segments; a unit waits
+// for its group's previous segment, taken at least one full round earlier.  The
+// arithmetic per candidate is exactly that of the plain rollout.
+
+struct SegCtl {
+  uint32_t head;     // next unit
+  uint32_t epoch;    // launch counter: done flags hold epoch * 256 + segments completed
+  uint32_t error;    // bit 0: a wait timed out
+  uint32_t pad;
+};
+
+__device__ __forceinline__ uint32_t seg_tag(uint32_t epoch, int done) { return (epoch << 8) | static_cast<uint32_t>(done); }
+
+// One wave: lanes 2c, 2c+1 hold candidate g*32 + c.  `state` holds (2M + 1)
+// floats per lane per group, laid out [k][group][lane].
+template <int N, bool CONTACT>
+__device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl* ctl, uint32_t* done, float* state,
+                                                       int S, int seg_len, uint64_t wait_ticks) {
+  constexpr int M = N / 2;
+  const int lane = threadIdx.x & 63;
+  const bool B = (lane & 1) != 0;
+  const int groups = (P.B + 31) / 32;
+  const uint32_t total = static_cast<uint32_t>(groups) * static_cast<uint32_t>(S);
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  PairConsts<N> K;
+  pair_setup<N, CONTACT>(P, B, K);
+  for (;;) {
+    uint32_t u = 0u;
+    if (lane == 0) u = atomicAdd(&ctl->head, 1u);
+    u = __builtin_amdgcn_readfirstlane(u);
+    if (u >= total) break;
+    const int seg = static_cast<int>(u / static_cast<uint32_t>(groups));
+    const int g = static_cast<int>(u - static_cast<uint32_t>(seg) * static_cast<uint32_t>(groups));
+    if (seg > 0) {
+      int ok = 1;
+      if (lane == 0) {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(&done[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != seg_tag(epoch, seg)) {
+          if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+              wall_clock64() - t0 > wait_ticks) {
+            atomicOr(&ctl->error, 1u);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      ok = __builtin_amdgcn_readfirstlane(ok);
+      if (!ok) break;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    const int bb = g * 32 + (lane >> 1);
+    const bool live = bb < P.B;
+    const int b = live ? bb : P.B - 1;   // idle pairs shadow the last candidate and store nothing
+    if constexpr (CONTACT) {
+      const float* sp = P.sparams + static_cast<size_t>(b) * (N + 1);
+      pair_load_masses<N>(sp, K);
+      K.muf = sp[N];
+    }
+    float ph[M], om[M], cost;
+    const size_t gl = static_cast<size_t>(g) * 64 + static_cast<size_t>(lane);
+    const size_t kstride = static_cast<size_t>(groups) * 64;
+    if (seg == 0) {
+      pair_start<N>(P, B, ph, om);
+      cost = 0.0f;
+    } else {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        ph[i] = state[i * kstride + gl];
+        om[i] = state[(M + i) * kstride + gl];
+      }
+      cost = state[2 * M * kstride + gl];
+    }
+    const int t0 = seg * seg_len;
+    const int t1 = min(P.T, t0 + seg_len);
+    pair_steps<N, CONTACT>(P, K, b, ph, om, cost, t0, t1, live);
+    if (seg + 1 < S) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        state[i * kstride + gl] = ph[i];
+        state[(M + i) * kstride + gl] = om[i];
+      }
+      state[2 * M * kstride + gl] = cost;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0) __hip_atomic_store(&done[g], seg_tag(epoch, seg + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (live && !B) {
+      P.cost[b] = finite_or_inf(cost);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ reductions

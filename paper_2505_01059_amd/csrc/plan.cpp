@@ -139,6 +139,10 @@ Layout compute_layout(const mtp_config& c) {
   const size_t R = c.n_replicas > 1 ? static_cast<size_t>(c.n_replicas) : 1;
   L.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? take(R * B * (n + 1) * 4) : 0;
   L.entropy = take(static_cast<size_t>(c.n_iters) * 4);
+  L.segmented = uses_segmented_rollout(c);
+  const size_t groups = (B + 31) / 32;
+  L.seg_ctl = L.segmented ? take(64) : 0;
+  L.seg_done = L.segmented ? take(groups * 4) : 0;
   L.resident = off;
   off = 0;
   L.Z = take(static_cast<size_t>(c.n_layers) * c.n_width * n * 4);
@@ -149,6 +153,7 @@ Layout compute_layout(const mtp_config& c) {
   L.ecost = take(static_cast<size_t>(c.n_elites) * 4);
   L.w = take(static_cast<size_t>(c.n_elites) * 4);
   L.X = c.n_debug_states > 0 ? take(T * d * static_cast<size_t>(c.n_debug_states) * 4) : 0;
+  L.seg_state = L.segmented ? take((n + 1) * groups * 64 * 4) : 0;
   L.transient = off;
   L.total = L.resident + L.transient;
   return L;
@@ -269,6 +274,30 @@ void mtp::set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8
   P->ecost = reinterpret_cast<float*>(tb + L.ecost);
   P->w = reinterpret_cast<float*>(tb + L.w);
   P->X = c.n_debug_states > 0 ? reinterpret_cast<float*>(tb + L.X) : nullptr;
+  P->seg_state = L.segmented ? reinterpret_cast<float*>(tb + L.seg_state) : nullptr;
+}
+
+bool mtp::uses_segmented_rollout(const mtp_config& c) {
+  constexpr long long kSimds = 1024;   // 256 compute units x 4 SIMDs
+  const long long B = static_cast<long long>(c.n_tensor) + c.n_gauss;
+  const bool pair = (c.dynamics == MTP_DYN_CHAIN || c.dynamics == MTP_DYN_CHAIN_CONTACT) && c.n_links >= 10 &&
+                    (c.n_links % 2) == 0;
+  const int R = c.n_replicas > 1 ? c.n_replicas : 1;
+  return pair && R == 1 && (B + 31) / 32 > kSimds && c.horizon >= 16;
+}
+
+// The S in 4..16 whose unit count groups*S is closest above to a whole number
+// of rounds of the resident waves (ties to the smaller S).
+int mtp::segment_count(int groups, int resident_waves) {
+  int best = 4;
+  double best_eff = 0.0;
+  for (int S = 4; S <= 16; ++S) {
+    const long long units = static_cast<long long>(groups) * S;
+    const long long rounds = (units + resident_waves - 1) / resident_waves;
+    const double eff = static_cast<double>(units) / static_cast<double>(rounds * resident_waves);
+    if (eff > best_eff + 1e-9) { best_eff = eff; best = S; }
+  }
+  return best;
 }
 
 int mtp::perm_rounds(int L, int W) {
@@ -316,6 +345,9 @@ PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uin
   P.task = reinterpret_cast<const float*>(base + L.task);
   P.sparams = c.dynamics == MTP_DYN_CHAIN_CONTACT ? reinterpret_cast<const float*>(base + L.sparams) : nullptr;
   P.entropy = reinterpret_cast<float*>(base + L.entropy);
+  P.seg_ctl = L.segmented ? reinterpret_cast<SegCtl*>(base + L.seg_ctl) : nullptr;
+  P.seg_done = L.segmented ? reinterpret_cast<uint32_t*>(base + L.seg_done) : nullptr;
+  P.seg_S = 0; P.seg_len = 0; P.seg_grid = 0;   // set by the launcher's device query (seg_configure)
   if (tb != nullptr) set_transient(&P, c, L, tb);
   return P;
 }
@@ -342,6 +374,11 @@ mtp_status mtp::upload_plan_tables(const mtp_config& c, const PlanDesc& P, const
   cp(P.mu, mu.data(), Tn * 4);
   cp(P.sigma, sg.data(), Tn * 4);
   cp(P.ctrl, ctrl, sizeof(ctrl));
+  const std::vector<uint32_t> seg_zero(P.seg_ctl != nullptr ? 4 + (B + 31) / 32 : 0, 0u);   // lives past the sync
+  if (P.seg_ctl != nullptr) {
+    cp(P.seg_ctl, seg_zero.data(), 16);
+    cp(P.seg_done, seg_zero.data() + 4, ((B + 31) / 32) * 4);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     if (err) *err = std::string("upload: ") + hipGetErrorString(e);
@@ -452,6 +489,10 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
   if (s != MTP_OK) {
     delete p;
     return s;
+  }
+  if (seg_configure(&p->P) != hipSuccess) {
+    delete p;
+    return MTP_ERR_DEVICE;
   }
   *out = p;
   return MTP_OK;

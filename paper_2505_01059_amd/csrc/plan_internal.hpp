@@ -19,8 +19,9 @@ namespace mtp {
 // base; a single plan places the transient part right after the resident one.
 struct Layout {
   size_t ldU;
-  size_t ctrl, x0, mu, sigma, tmp, action, basis, span, task, sparams, entropy;   // resident
-  size_t Z, I, U, cost, eidx, ecost, w, X;                               // transient
+  size_t ctrl, x0, mu, sigma, tmp, action, basis, span, task, sparams, entropy, seg_ctl, seg_done;   // resident
+  size_t Z, I, U, cost, eidx, ecost, w, X, seg_state;                                       // transient
+  bool segmented;   // the rollout is time-sliced (see uses_segmented_rollout)
   size_t resident, transient;
   size_t total;   // resident + transient
 };
@@ -34,6 +35,12 @@ hipError_t enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStre
 PlanDesc make_desc(const mtp_config& c, const Layout& L, uint8_t* resident, uint8_t* transient);
 // Point a descriptor's transient buffers at a new base.
 void set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* transient);
+// Whether a plan's rollout runs time-sliced: even chains of >= 10 links (two lanes
+// per candidate) without randomised replicas whose launch has more waves than
+// the chip has SIMDs.
+bool uses_segmented_rollout(const mtp_config& c);
+// Segments of the time-sliced rollout for a given number of resident waves.
+int segment_count(int groups, int resident_waves);
 // Rounds of the without-replacement path permutation: 2 L ceil(log2 W).
 int perm_rounds(int L, int W);
 // Time steps per candidate workgroup of the single-plan candidate kernel.

@@ -119,3 +119,38 @@ def test_point_mass_full():
 
 def test_chain24_contact_full():
     check_fullsize(W.c4(), "chain24 contact full")
+
+
+@pytest.mark.parametrize("contact", [False, True])
+def test_time_sliced_rollout_equals_plain(contact):
+    """Launches of more pair-lane waves than SIMDs run time-sliced (segments of
+    the horizon taken from a counter, state saved between them); the batched
+    kernel runs the same instance with plain whole-horizon tiles.  One replan of
+    each must agree bit for bit, and no wait may time out."""
+    import torch
+    import paper_2505_01059_amd as mtp
+    if contact:
+        cfg = W.chain_contact_config(name="ts_contact", n_tensor=68000, n_gauss=2000, horizon=40,
+                                     n_elites=64, n_iters=2, seed=3)
+    else:
+        cfg = W.chain_config(name="ts_chain24", n_links=24, interp=W.BSPLINE, n_tensor=68000, n_gauss=2000,
+                             horizon=40, n_layers=12, n_width=64, n_elites=64, n_iters=2, seed=4)
+    x0 = W.initial_state(cfg, seed=1)
+    _log(f"[time-sliced] contact={contact} B={cfg.n_samples}")
+    plan = mtp.Plan(cfg, device="cuda:0")
+    plan.replan(x0, shift=1, replan_idx=0)
+    torch.cuda.synchronize()
+    assert plan.flags() & 4 == 0, "a segment wait timed out"
+    b = plan.buffers()
+    mu, sg, act = b["mu"].cpu().numpy().copy(), b["sigma"].cpu().numpy().copy(), plan.action()
+    cost = b["cost"].cpu().numpy().copy()
+    plan.close()
+    bt = mtp.Batch([cfg], device="cuda:0")
+    bt.replan(bt.pack_x0([x0]), shift=1)
+    acts = bt.actions()
+    bb = bt.buffers(0)
+    assert np.array_equal(bb["cost"].cpu().numpy(), cost)
+    assert np.array_equal(bb["mu"].cpu().numpy(), mu)
+    assert np.array_equal(bb["sigma"].cpu().numpy(), sg)
+    assert np.array_equal(acts[0], act)
+    bt.close()
