@@ -153,6 +153,11 @@ size_t mtp_workspace_bytes(const mtp_config* cfg);
  * (NUL-terminated, at most why_len bytes; may be NULL). */
 mtp_status mtp_validate_config(const mtp_config* cfg, char* why, size_t why_len);
 
+/* Bytes of the per-replan (transient) buffers of one instance: graph, paths,
+ * candidates, costs, elites.  A server lends this much from its pool to every
+ * replan in flight; 0 if cfg is invalid. */
+size_t mtp_transient_bytes(const mtp_config* cfg);
+
 /* Validate cfg, lay the plan out in the caller's workspace, upload its tables
  * (spline basis, task and sample parameters) on `hip_stream` (NULL = default
  * stream) and initialise mu = (u_min+u_max)/2, sigma = sigma_init, replan index 0. */

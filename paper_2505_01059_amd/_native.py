@@ -66,6 +66,7 @@ def load():
     P = c_void_p
     sig = {
         "mtp_workspace_bytes": (c_size_t, [P]),
+        "mtp_transient_bytes": (c_size_t, [P]),
         "mtp_validate_config": (c_int32, [P, c_char_p, c_size_t]),
         "mtp_plan_create": (c_int32, [P, P, c_size_t, P, POINTER(P)]),
         "mtp_replan": (c_int32, [P, P, c_int32]),
@@ -205,6 +206,12 @@ def workspace_bytes(cfg, n_debug_states=0):
     lib = load()
     c, keep = config_struct(cfg, n_debug_states)
     return int(lib.mtp_workspace_bytes(byref(c)))
+
+
+def transient_bytes(cfg) -> int:
+    """Bytes one replan of cfg borrows from a server's pool (0 if invalid)."""
+    c, keep = config_struct(cfg)
+    return int(load().mtp_transient_bytes(byref(c)))
 
 
 def _torch():

@@ -209,3 +209,13 @@ def test_without_replacement_and_diagnostics_validation():
     assert st == 1 and "diagnostics" in why
     # the entropy record lives with the plan: K floats more than without
     assert N.workspace_bytes(ok) >= N.workspace_bytes(ok.replace(diagnostics=0))
+
+
+def test_transient_bytes_smaller_than_plan_workspace():
+    """A plan's workspace holds its resident tables and the transient buffers; a
+    server lends only the transient part, which holds at least the candidates U."""
+    for cfg in (W.c0(), W.c1(), W.c4()):
+        t, w = N.transient_bytes(cfg), N.workspace_bytes(cfg)
+        U = cfg.horizon * cfg.ctrl_dim * (((cfg.n_samples * 4 + 255) // 256) * 256)
+        assert U <= t < w
+    assert N.transient_bytes(W.c0().replace(n_iters=0)) == 0

@@ -28,7 +28,7 @@ def test_served_equals_alone():
     robots = fleet()
     rounds = 3
     x0 = {(i, k): W.initial_state(c, seed=100 * k + i) for i, c in enumerate(robots) for k in range(rounds)}
-    slabs = [N.workspace_bytes(c) for c in robots]
+    slabs = [N.transient_bytes(c) for c in robots]
     srv = mtp.Server(robots, pool_bytes=int(1.05 * max(slabs)), iters_per_launch=1, max_inflight=2, device="cuda:0")
     got = []
     order = [(i, k) for k in range(rounds) for i in (3, 0, 4, 1, 2)]
