@@ -35,10 +35,10 @@ uint32_t items_for(const mtp_config& c, int k_begin, int k_end) {
   const bool quad = is_quad_chain(c.dynamics, c.n_links);
   const bool pair = is_pair_chain(c.dynamics, c.n_links);
   const int Pn = c.n_tensor;
-  const uint32_t per_iter = host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhPaths, quad, pair) +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhCand, quad, pair) +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhRoll, quad, pair) + 1u +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhUpd, quad, pair);
+  const uint32_t per_iter = host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhPaths, quad, pair, c.sample_wor != 0) +
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhCand, quad, pair, false) +
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhRoll, quad, pair, false) + 1u +
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhUpd, quad, pair, false);
   return 1u + per_iter * static_cast<uint32_t>(k_end - k_begin);
 }
 

@@ -21,7 +21,7 @@ namespace mtp {
 __device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phase) {
   switch (phase) {
     case kPhShift: return 1u;
-    case kPhPaths: return P.P > 0 ? static_cast<uint32_t>((P.P + kCandThreads - 1) / kCandThreads) : 1u;
+    case kPhPaths: return (P.P > 0 && P.wor) ? static_cast<uint32_t>((P.P + kCandThreads - 1) / kCandThreads) : 1u;
     case kPhCand: return static_cast<uint32_t>((P.B + kCandThreads - 1) / kCandThreads);
     case kPhRoll: {
       const int per = is_quad_chain(P.dyn, P.n_links)   ? kBatchThreads / 4

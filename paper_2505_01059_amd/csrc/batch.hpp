@@ -78,10 +78,10 @@ const char* batch_error(const mtp_batch* b);
 hipStream_t batch_stream(const mtp_batch* b);
 
 // host mirror of the per-phase tile counts
-inline uint32_t host_phase_tiles(int B, int P, int T, int n, uint32_t phase, bool quad, bool pair) {
+inline uint32_t host_phase_tiles(int B, int P, int T, int n, uint32_t phase, bool quad, bool pair, bool wor) {
   switch (phase) {
     case kPhShift: return 1u;
-    case kPhPaths: return P > 0 ? static_cast<uint32_t>((P + kCandThreads - 1) / kCandThreads) : 1u;
+    case kPhPaths: return (P > 0 && wor) ? static_cast<uint32_t>((P + kCandThreads - 1) / kCandThreads) : 1u;
     case kPhCand: return static_cast<uint32_t>((B + kCandThreads - 1) / kCandThreads);
     case kPhRoll: {
       const int per = quad ? kBatchThreads / 4 : (pair ? kBatchThreads / 2 : kBatchThreads);

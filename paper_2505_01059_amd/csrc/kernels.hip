@@ -220,7 +220,7 @@ hipError_t launch_shift(const PlanDesc& P, hipStream_t st) {
 hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
   switch (stage) {
     case 0: {
-      if (P.P > 0) {
+      if (P.P > 0 && P.wor) {
         k_paths<<<(P.P + kCandThreads - 1) / kCandThreads, kCandThreads, 0, st>>>(P, k);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -256,11 +256,12 @@ __device__ __forceinline__ void graph_tile(const PlanDesc& P, uint32_t r, int k,
   }
 }
 
-// Draws the graph (its share) and writes I[.][p] for the tensor paths p in
-// [p0, p0 + blockDim.x).  Every thread of the workgroup must call this (it
+// Without replacement: draws the graph (its share) and writes I[.][p] for the
+// tensor paths p of the tile.  Every thread of the workgroup must call this (it
 // synchronises the workgroup).
 __device__ __forceinline__ void path_tile(const PlanDesc& P, uint32_t r, int k, int tile, int n_tiles,
                                           PathSmem& sm) {
+  if (!P.wor) return;   // with replacement the candidate tiles draw the graph and the indices
   if (P.P > 0) graph_tile(P, r, k, tile, n_tiles);
   const int pp = tile * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
   if (!P.wor) {
@@ -338,13 +339,46 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
   const bool is_tensor = live && b >= tens_lo && b < tens_hi;
 
   if (tile_has_tensor) {
-    // graph column of joint j (drawn by the path tiles)
-    for (int e = tid; e < P.L * P.W; e += kCandThreads) sm.z[e] = P.Z[static_cast<size_t>(e) * P.n + j];
+    if (P.wor) {
+      // graph column of joint j, drawn by the path tiles
+      for (int e = tid; e < P.L * P.W; e += kCandThreads) sm.z[e] = P.Z[static_cast<size_t>(e) * P.n + j];
+    } else {
+      // draw the graph column of joint j here; the tile holding the first tensor
+      // path stores it to Z
+      const bool z_writer = (b0 <= tens_lo) && t_begin == 0;
+      const float span = hi - lo;
+      for (int e = tid; e < P.L * P.W; e += kCandThreads) {
+        const int l = e / P.W, w = e - l * P.W;
+        const uint32_t idx = static_cast<uint32_t>(w * P.n + j);
+        const Words4 q = philox(idx >> 2, static_cast<uint32_t>(l), r, stream_c3(kTagZ, k), P.key0, P.key1);
+        const float z = fmaf(span, u01(q.w[idx & 3u]), lo);
+        sm.z[e] = z;
+        if (z_writer) P.Z[static_cast<size_t>(e) * P.n + j] = z;
+      }
+    }
   }
   __syncthreads();
   if (is_tensor) {
     const int pp = b - G1;
-    for (int l = 0; l < P.L; ++l) sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + P.I[static_cast<size_t>(l) * P.P + pp]];
+    if (P.wor) {
+      for (int l = 0; l < P.L; ++l) sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + P.I[static_cast<size_t>(l) * P.P + pp]];
+    } else {
+      // Alg. 1 indices drawn here; the tiles of joint 0 and the first horizon chunk store I
+      const bool i_writer = j == 0 && t_begin == 0;
+      for (int l4 = 0; l4 < P.L; l4 += 4) {
+        const Words4 q = philox(static_cast<uint32_t>(l4 >> 2), static_cast<uint32_t>(pp), r, stream_c3(kTagI, k),
+                                P.key0, P.key1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int l = l4 + c;
+          if (l < P.L) {
+            const uint32_t wi = __umulhi(q.w[c], static_cast<uint32_t>(P.W));
+            sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + wi];
+            if (i_writer) P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(wi);
+          }
+        }
+      }
+    }
     if (P.interp == kAkima) akima_slopes_thread(P.L, tid, sm);
   }
   const int Tq = (P.T + 3) >> 2;
@@ -372,7 +406,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           const int t = 4 * tq + c;
           if (t < t0 + tn) {
             const int i = t - t0;
-            P.U[(t * P.n + j) * ld + b] = clampf(fmaf(sm.tsg[i], z[c], sm.tmu[i]), lo, hi);
+            __builtin_nontemporal_store(clampf(fmaf(sm.tsg[i], z[c], sm.tmu[i]), lo, hi), &P.U[(t * P.n + j) * ld + b]);
           }
         }
       }
@@ -386,7 +420,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           v = fmaf(bw[1], sm.ctrl[(s0 + 1) * kCandThreads + tid], v);
           v = fmaf(bw[2], sm.ctrl[(s0 + 2) * kCandThreads + tid], v);
           v = fmaf(bw[3], sm.ctrl[(s0 + 3) * kCandThreads + tid], v);
-          P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
+          __builtin_nontemporal_store(clampf(v, lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
         }
       } else if (P.interp != kAkima) {
         const int np1 = P.interp == kLinear ? 2 : P.p + 1;
@@ -396,7 +430,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           const float* bw = sm.tb + i * kBasisStride;
           float v = 0.0f;
           for (int q = 0; q < np1; ++q) v = fmaf(bw[q], sm.ctrl[(s0 + q) * kCandThreads + tid], v);
-          P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
+          __builtin_nontemporal_store(clampf(v, lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
         }
       } else {
 #pragma unroll 4
@@ -407,13 +441,13 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           v = fmaf(h[1], sm.slope[iv * kCandThreads + tid], v);
           v = fmaf(h[2], sm.ctrl[(iv + 1) * kCandThreads + tid], v);
           v = fmaf(h[3], sm.slope[(iv + 1) * kCandThreads + tid], v);
-          P.U[((t0 + i) * P.n + j) * ld + b] = clampf(v, lo, hi);
+          __builtin_nontemporal_store(clampf(v, lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
         }
       }
     } else if (live) {
       // nominal mean
 #pragma unroll 4
-      for (int i = 0; i < tn; ++i) P.U[((t0 + i) * P.n + j) * ld + b] = clampf(sm.tmu[i], lo, hi);
+      for (int i = 0; i < tn; ++i) __builtin_nontemporal_store(clampf(sm.tmu[i], lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
     }
     __syncthreads();
   }
