@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_point_mass(PlanDesc P)
   stage_obstacles(P, sm);
   __syncthreads();
   const int b = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
-  if (b < P.B) rollout_point_mass(P, b, sm);
+  if (b < P.B) rollout_point_mass_any(P, b, sm);
 }
 
 template <int N, bool CONTACT>

@@ -476,31 +476,75 @@ __device__ __forceinline__ void stage_obstacles(const PlanDesc& P, PointMassSmem
   }
 }
 
+// Obstacle tests: the uniform obstacle table either lives in registers (up to
+// NOBS obstacles, padded with radius^2 = -1 so the padding never hits) or, for
+// longer tables, is read from LDS.  Register tables avoid one LDS round trip per
+// obstacle and step, which dominates a rollout of a few hundred candidates.
+template <int NOBS>
 __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, const PointMassSmem& sm) {
   // task: goal_x, goal_y, goal_w, obstacle_penalty, ctrl_w, n_obs, (cx, cy, r)*
   const float* tk = P.task;
   const float gx = tk[0], gy = tk[1], wg = tk[2], pen = tk[3], wu = tk[4];
   const int n_obs = static_cast<int>(tk[5]);
+  float ocx[NOBS > 0 ? NOBS : 1], ocy[NOBS > 0 ? NOBS : 1], orr[NOBS > 0 ? NOBS : 1];
+  if constexpr (NOBS > 0) {
+    // read from the LDS copy so that the table lands in vector registers (as
+    // uniform scalars it would not fit the scalar register file)
+#pragma unroll
+    for (int o = 0; o < NOBS; ++o) {
+      const bool on = o < n_obs;
+      ocx[o] = on ? sm.obs[3 * o] : 0.0f;
+      ocy[o] = on ? sm.obs[3 * o + 1] : 0.0f;
+      orr[o] = on ? sm.obs[3 * o + 2] : -1.0f;
+    }
+  }
   const float* obs = sm.obs;
   const float dt = P.dt;
   float px = P.x0[0], py = P.x0[1], vx = P.x0[2], vy = P.x0[3];
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* u0 = P.U + b;
   float cost = 0.0f;
-  float ux = u0[0], uy = u0[ld];
-  for (int t = 0; t < P.T; ++t) {
-    // prefetch next step's controls
-    float nx = 0.0f, ny = 0.0f;
-    if (t + 1 < P.T) { nx = u0[(2 * (t + 1)) * ld]; ny = u0[(2 * (t + 1) + 1) * ld]; }
+  // controls arrive in blocks of kPmBlock steps, the next block loading while
+  // the current one is integrated: one step is too short to hide a load
+  constexpr int kPmBlock = 8;
+  float cux[kPmBlock], cuy[kPmBlock];
+#pragma unroll
+  for (int i = 0; i < kPmBlock; ++i) {
+    const bool in = i < P.T;
+    cux[i] = in ? u0[(2 * i) * ld] : 0.0f;
+    cuy[i] = in ? u0[(2 * i + 1) * ld] : 0.0f;
+  }
+  for (int t0 = 0; t0 < P.T; t0 += kPmBlock) {
+    float nux[kPmBlock], nuy[kPmBlock];
+#pragma unroll
+    for (int i = 0; i < kPmBlock; ++i) {
+      const int tn = t0 + kPmBlock + i;
+      const bool in = tn < P.T;
+      nux[i] = in ? u0[(2 * tn) * ld] : 0.0f;
+      nuy[i] = in ? u0[(2 * tn + 1) * ld] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < kPmBlock; ++i) {
+    const int t = t0 + i;
+    if (t >= P.T) break;
+    const float ux = cux[i], uy = cuy[i];
     vx = fmaf(dt, ux, vx);
     vy = fmaf(dt, uy, vy);
     px = fmaf(dt, vx, px);
     py = fmaf(dt, vy, py);
     const float dx = px - gx, dy = py - gy;
     float c = wg * fmaf(dx, dx, dy * dy);
-    for (int o = 0; o < n_obs; ++o) {
-      const float ox = px - obs[3 * o], oy = py - obs[3 * o + 1];
-      c += (fmaf(ox, ox, oy * oy) < obs[3 * o + 2]) ? pen : 0.0f;
+    if constexpr (NOBS > 0) {
+#pragma unroll
+      for (int o = 0; o < NOBS; ++o) {
+        const float ox = px - ocx[o], oy = py - ocy[o];
+        c += (fmaf(ox, ox, oy * oy) < orr[o]) ? pen : 0.0f;
+      }
+    } else {
+      for (int o = 0; o < n_obs; ++o) {
+        const float ox = px - obs[3 * o], oy = py - obs[3 * o + 1];
+        c += (fmaf(ox, ox, oy * oy) < obs[3 * o + 2]) ? pen : 0.0f;
+      }
     }
     c = fmaf(wu, fmaf(ux, ux, uy * uy), c);
     cost += c;
@@ -510,9 +554,25 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
       X[(t * 4 + 0) * ldx] = px; X[(t * 4 + 1) * ldx] = py;
       X[(t * 4 + 2) * ldx] = vx; X[(t * 4 + 3) * ldx] = vy;
     }
-    ux = nx; uy = ny;
+    }
+#pragma unroll
+    for (int i = 0; i < kPmBlock; ++i) { cux[i] = nux[i]; cuy[i] = nuy[i]; }
   }
   P.cost[b] = finite_or_inf(cost);
+}
+
+// Obstacle-table size class of a point-mass plan: 8, 16, 32 in registers, 0 in LDS.
+__device__ __host__ __forceinline__ int point_mass_obs_class(int n_obs) {
+  return n_obs <= 8 ? 8 : (n_obs <= 16 ? 16 : (n_obs <= 32 ? 32 : 0));
+}
+
+__device__ __forceinline__ void rollout_point_mass_any(const PlanDesc& P, int b, const PointMassSmem& sm) {
+  switch (point_mass_obs_class(static_cast<int>(P.task[5]))) {
+    case 8: rollout_point_mass<8>(P, b, sm); return;
+    case 16: rollout_point_mass<16>(P, b, sm); return;
+    case 32: rollout_point_mass<32>(P, b, sm); return;
+    default: rollout_point_mass<0>(P, b, sm); return;
+  }
 }
 
 // Planar chain of point masses on massless links, absolute angles from the
