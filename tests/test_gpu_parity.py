@@ -47,6 +47,27 @@ def configs():
                                               n_replicas=3),
         "contact24_r2": W.chain_contact_config(name="contact24_r2", n_tensor=100, n_gauss=28, horizon=32,
                                                n_elites=12, n_iters=2, n_replicas=2),
+        # degenerate and extreme shapes: one step, ragged horizons, one waypoint per
+        # layer, a straight Akima line, only the nominal, E = B, the largest graph,
+        # a candidate tile plus one, one-lane chains with linear paths and with contact
+        "deg_T1": W.point_mass_config(name="deg_T1", horizon=1, n_tensor=100, n_gauss=10, n_elites=5, n_iters=2),
+        "deg_T3": W.chain_config(name="deg_T3", horizon=3, n_tensor=300, n_gauss=20, n_elites=8, n_iters=2),
+        "deg_W1": W.point_mass_config(name="deg_W1", interp=W.AKIMA, n_layers=5, n_width=1, n_tensor=64,
+                                      n_gauss=16, horizon=25, n_elites=8, n_iters=2),
+        "deg_L2": W.point_mass_config(name="deg_L2", interp=W.AKIMA, n_layers=2, n_width=6, n_tensor=90,
+                                      n_gauss=10, horizon=30, n_elites=8, n_iters=2),
+        "deg_nominal": W.point_mass_config(name="deg_nominal", n_tensor=0, n_gauss=1, n_elites=1, n_iters=2),
+        "deg_E_eq_B": W.chain_config(name="deg_E_eq_B", n_links=2, n_tensor=50, n_gauss=15, n_elites=65,
+                                     horizon=20, n_layers=4, n_width=5, n_iters=2, temperature=1.0),
+        "deg_maxgraph": W.point_mass_config(name="deg_maxgraph", interp=W.AKIMA, n_layers=16, n_width=256,
+                                            n_tensor=600, n_gauss=40, horizon=64, n_elites=16, n_iters=2),
+        "deg_ragged12": W.chain_config(name="deg_ragged12", n_links=12, interp=W.BSPLINE, n_tensor=240,
+                                       n_gauss=17, horizon=17, n_layers=9, n_width=16, n_elites=12, n_iters=2),
+        "deg_chain3_linear": W.chain_config(name="deg_chain3_linear", n_links=3, interp=W.LINEAR, n_tensor=200,
+                                            n_gauss=40, horizon=33, n_layers=6, n_width=10, n_elites=10,
+                                            n_iters=2),
+        "deg_contact4": W.chain_contact_config(name="deg_contact4", n_links=4, n_tensor=150, n_gauss=30,
+                                               horizon=40, n_layers=6, n_width=12, n_elites=12, n_iters=2),
         # tensor paths without replacement: near saturation (200 of 4^4) and a wide graph
         "wor_pm": W.point_mass_config(name="wor_pm", n_tensor=200, n_gauss=40, horizon=30, n_layers=4,
                                       n_width=4, n_elites=16, n_iters=2).replace(sample_wor=1),
