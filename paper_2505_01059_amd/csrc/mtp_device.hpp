@@ -1743,17 +1743,47 @@ __device__ __forceinline__ void entropy_block(const PlanDesc& P, int k, EntropyS
 // One wave per output (t, j): lanes stride over the elites, fixed-order
 // butterfly reduction, then the sigma floor and exponential smoothing.
 
+// The elite values of a row are gathered once: up to kUpdKeep per lane stay in
+// registers for the variance pass (each gather touches its own cache line, so
+// the second pass would double the line traffic); larger elite sets re-read.
+constexpr int kUpdKeep = 16;
+
 __device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
   const int lane = threadIdx.x & 63;
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* row = P.U + static_cast<size_t>(o) * ld;
+  float keep[kUpdKeep];
   float m = 0.0f;
-  for (int e = lane; e < P.E; e += 64) m = fmaf(P.w[e], row[P.eidx[e]], m);
+  if (P.E <= 64 * kUpdKeep) {
+#pragma unroll
+    for (int q = 0; q < kUpdKeep; ++q) {
+      const int e = lane + 64 * q;
+      keep[q] = e < P.E ? row[P.eidx[e]] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kUpdKeep; ++q) {
+      const int e = lane + 64 * q;
+      if (e < P.E) m = fmaf(P.w[e], keep[q], m);
+    }
+  } else {
+    for (int e = lane; e < P.E; e += 64) m = fmaf(P.w[e], row[P.eidx[e]], m);
+  }
   m = wave_sum64(m);
   float v = 0.0f;
-  for (int e = lane; e < P.E; e += 64) {
-    const float dv = row[P.eidx[e]] - m;
-    v = fmaf(P.w[e], dv * dv, v);
+  if (P.E <= 64 * kUpdKeep) {
+#pragma unroll
+    for (int q = 0; q < kUpdKeep; ++q) {
+      const int e = lane + 64 * q;
+      if (e < P.E) {
+        const float dv = keep[q] - m;
+        v = fmaf(P.w[e], dv * dv, v);
+      }
+    }
+  } else {
+    for (int e = lane; e < P.E; e += 64) {
+      const float dv = row[P.eidx[e]] - m;
+      v = fmaf(P.w[e], dv * dv, v);
+    }
   }
   v = wave_sum64(v);
   if (lane == 0) {
