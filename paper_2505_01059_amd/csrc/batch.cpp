@@ -186,7 +186,7 @@ static mtp_status ensure_graph(mtp_batch* b) {
   if (e == hipSuccess) e = launch_batch_pack(L, b->d_out, b->n, b->lay.act_total, b->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
-  if (e != hipSuccess) { if (g) hipGraphDestroy(g); return bdev(b, e, "capture"); }
+  if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return bdev(b, e, "capture"); }
   if (e2 != hipSuccess) return bdev(b, e2, "end capture");
   b->graph = g;
   BCHK(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");

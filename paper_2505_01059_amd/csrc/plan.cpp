@@ -511,7 +511,7 @@ static mtp_status ensure_graph(mtp_plan* p) {
   if (e == hipSuccess) e = enqueue_iterations(p->P, 0, p->cfg.n_iters, p->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
-  if (e != hipSuccess) { if (g) hipGraphDestroy(g); return device_err(p, e, "capture launch"); }
+  if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return device_err(p, e, "capture launch"); }
   if (e2 != hipSuccess) return device_err(p, e2, "end capture");
   p->graph = g;
   HIPCHK(p, hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0), "graph instantiate");
