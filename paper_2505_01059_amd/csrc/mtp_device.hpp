@@ -70,14 +70,24 @@ struct PlanDesc {
 // multiplies with xor/permute, key bumped by the Weyl constants between rounds.
 struct Words4 { uint32_t w[4]; };
 
+// Word i (0..3) of a Philox block by selects: a runtime index into the array
+// would place it in scratch memory.
+__device__ __forceinline__ uint32_t word_at(const Words4& q, uint32_t i) {
+  const uint32_t a = (i & 1u) ? q.w[1] : q.w[0];
+  const uint32_t b = (i & 1u) ? q.w[3] : q.w[2];
+  return (i & 2u) ? b : a;
+}
+
 __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t k0, uint32_t k1) {
+  // each 32x32 -> 64-bit product is one v_mad_u64_u32 (both halves at once)
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
-    const uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    const uint64_t p0 = static_cast<uint64_t>(c0) * 0xD2511F53u;
+    const uint64_t p1 = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = static_cast<uint32_t>(p1); c2 = n2; c3 = static_cast<uint32_t>(p0);
     k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
   }
   Words4 r; r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
@@ -97,10 +107,11 @@ __device__ __forceinline__ float u01(uint32_t w) { return static_cast<float>(w >
 __device__ __forceinline__ float u01_open0(uint32_t w) { return static_cast<float>((w >> 8) + 1u) * 0x1p-24f; }
 
 // Box-Muller on the hardware transcendental unit: v_log gives log2 (times ln 2
-// for the natural log), and v_sin / v_cos take their argument in revolutions,
-// so the angle 2*pi*u2 is exactly u2 revolutions.
+// for the natural log), v_sqrt the radius (its argument is 0 or a normal
+// number), and v_sin / v_cos take their argument in revolutions, so the angle
+// 2*pi*u2 is exactly u2 revolutions.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
-  const float rad = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01_open0(a)));   // -2 ln u1
+  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01_open0(a)));   // -2 ln u1
   const float u2 = u01(b);
   z0 = rad * __builtin_amdgcn_cosf(u2);
   z1 = rad * __builtin_amdgcn_sinf(u2);
@@ -351,7 +362,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
         const int l = e / P.W, w = e - l * P.W;
         const uint32_t idx = static_cast<uint32_t>(w * P.n + j);
         const Words4 q = philox(idx >> 2, static_cast<uint32_t>(l), r, stream_c3(kTagZ, k), P.key0, P.key1);
-        const float z = fmaf(span, u01(q.w[idx & 3u]), lo);
+        const float z = fmaf(span, u01(word_at(q, idx & 3u)), lo);
         sm.z[e] = z;
         if (z_writer) P.Z[static_cast<size_t>(e) * P.n + j] = z;
       }
@@ -1477,30 +1488,32 @@ __device__ __forceinline__ uint32_t cost_order(float c) {
 constexpr int kTopkBins = 2048;      // radix digits of up to 11 bits
 constexpr int kTopkCache = 16384;    // batches up to this size keep their cost images in LDS
 constexpr int kTopkRankSort = 1024;  // elite sets up to this size are ordered by counting ranks
+constexpr int kTopkBoundary = 256;   // a boundary bin this small is ordered by counting ranks
 
 struct TopkSmem {
   uint32_t cache[kTopkCache];                 // cost images of the batch (when it fits)
   unsigned long long keys[kMaxElites];        // selected keys, unordered
-  unsigned long long sorted[kTopkRankSort];   // selected keys by rank
+  unsigned long long sorted[kTopkRankSort];   // selected keys by rank; the boundary bin before that
   uint32_t hist[kTopkBins];
   unsigned long long prefix;
   uint32_t rank;
-  uint32_t count;
+  uint32_t count, count2;
   uint32_t sel_count;
-  uint32_t lo, hi;
   float red[kTopkThreads / 64];
   uint32_t wlo[kTopkThreads / 64], whi[kTopkThreads / 64];
 };
 
-// Wave 0 finds the digit whose bin holds the rank-th key (1-based) of the
-// histogram hist[0..nbins); writes the digit (into the prefix at `shift`), the
-// rank left inside that bin and the bin's size to shared memory.
+// All BS threads find the digit whose bin holds the rank-th key (1-based) of
+// hist[0..nbins): each thread owns a run of consecutive bins, a wave scan and
+// the wave totals give every run's offset, and the one thread whose run holds
+// the rank writes the digit (into the prefix at `shift`), the rank left inside
+// that bin and the bin's size to shared memory.  The caller synchronises.
+template <int BS>
 __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t rank, unsigned long long prefix,
                                               int shift) {
-  const int lane = threadIdx.x;
-  if (lane >= 64) return;
-  const int per = nbins >= 64 ? nbins / 64 : 1;
-  const int first = lane * per;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (nbins + BS - 1) / BS;
+  const int first = tid * per;
   uint32_t tot = 0;
   for (int i = 0; i < per; ++i)
     if (first + i < nbins) tot += sm.hist[first + i];
@@ -1510,6 +1523,11 @@ __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t 
     const uint32_t v = __shfl_up(inc, o, 64);
     if (lane >= o) inc += v;
   }
+  if (lane == 63) sm.wlo[wave] = inc;
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < BS / 64 - 1; ++w)
+    if (w < wave) inc += sm.wlo[w];
   const uint32_t exc = inc - tot;
   if (exc < rank && rank <= inc) {
     uint32_t rr = rank - exc;
@@ -1524,13 +1542,71 @@ __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t 
   }
 }
 
+// Counting ranks of n distinct keys src[0..n) among themselves: tpk threads
+// share each key's comparisons (as many as the block allows, at most a wave),
+// then combine their counts with a butterfly.  sink(key, rank) runs once per key.
+template <int BS, class Sink>
+__device__ __forceinline__ void topk_rank(const unsigned long long* src, int n, Sink sink) {
+  int tpk = 1;
+  while (tpk < 64 && tpk * 2 * n <= BS) tpk <<= 1;
+  const int tid = threadIdx.x, sub = tid & (tpk - 1), per_pass = BS / tpk;
+  for (int i0 = 0; i0 < n; i0 += per_pass) {
+    const int i = i0 + tid / tpk;
+    const unsigned long long k = i < n ? src[i] : 0ull;
+    int r = 0;
+    if (i < n) {
+      int q = sub;
+      for (; q + 7 * tpk < n; q += 8 * tpk) {   // eight loads in flight
+        unsigned long long c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) c[u] = src[q + u * tpk];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r += c[u] < k ? 1 : 0;
+      }
+      for (; q < n; q += tpk) r += src[q] < k ? 1 : 0;
+    }
+    for (int o = 1; o < tpk; o <<= 1) r += __shfl_xor(r, o, 64);
+    if (i < n && sub == 0) sink(k, r);
+  }
+}
+
+// Appends every key (image << 32 | index) for which take(v, key) holds, with
+// v = image - lo, to dst at slots counted by *counter (one bump per wave).
+template <int BS, class Image, class Take>
+__device__ __forceinline__ void topk_gather(int B, uint32_t lo, Image image, Take take, uint32_t* counter,
+                                            unsigned long long* dst, uint32_t cap) {
+  for (int base = 0; base < B; base += BS) {
+    const int b = base + static_cast<int>(threadIdx.x);
+    unsigned long long key = 0ull;
+    bool t = false;
+    if (b < B) {
+      const uint32_t im = image(b);
+      key = (static_cast<unsigned long long>(im) << 32) | static_cast<uint32_t>(b);
+      t = take(im - lo, key);
+    }
+    const unsigned long long m = __ballot(t);
+    if (m != 0ull) {
+      const int lane = static_cast<int>(threadIdx.x) & 63;
+      const int leader = __ffsll(static_cast<long long>(m)) - 1;
+      uint32_t slot0 = 0u;
+      if (lane == leader) slot0 = atomicAdd(counter, static_cast<uint32_t>(__popcll(m)));
+      slot0 = static_cast<uint32_t>(__shfl(static_cast<int>(slot0), leader, 64));
+      const uint32_t slot = slot0 + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+      if (t && slot < cap) dst[slot] = key;
+    }
+  }
+}
+
 // Top-E by a radix select over the order-preserving 32-bit cost image, taken
 // relative to the batch minimum so that the first digit spreads the keys over
-// the bins instead of piling them on the few that share an exponent.  If no tie
-// straddles the elite boundary the elites are the keys with image <= c*;
-// otherwise a second radix over the index bits orders the ties by index.  The
-// E keys (image << 32 | index) are then ordered by counting ranks (all keys are
-// distinct), or by a bitonic network for very large E.
+// the bins instead of piling them on the few that share an exponent.  Once the
+// bin that holds the E-th key has at most kTopkBoundary keys (after the first
+// digit, for spread-out costs) the select stops: the keys of lower bins are
+// elites, and the rank-th smallest keys (image << 32 | index, all distinct) of
+// the boundary bin complete the set.  A bin that stays larger down to the last
+// digit holds equal images only; a radix over the index bits then orders those
+// ties.  The E keys are finally ordered by counting ranks, or by a bitonic
+// network for very large E.
 template <int BS>
 __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const int tid = threadIdx.x;
@@ -1538,13 +1614,22 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const bool cached = B <= kTopkCache;
   auto image = [&](int b) -> uint32_t { return cached ? sm.cache[b] : cost_order(P.cost[b]); };
 
-  // images, their minimum and maximum
+  // images, their minimum and maximum (four loads in flight per thread)
   uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-  for (int b = tid; b < B; b += BS) {
-    const uint32_t o = cost_order(P.cost[b]);
-    if (cached) sm.cache[b] = o;
-    lo = min(lo, o);
-    hi = max(hi, o);
+  for (int b0 = tid; b0 < B; b0 += 4 * BS) {
+    float c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = b0 + u * BS < B ? P.cost[b0 + u * BS] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * BS;
+      if (b < B) {
+        const uint32_t o = cost_order(c[u]);
+        if (cached) sm.cache[b] = o;
+        lo = min(lo, o);
+        hi = max(hi, o);
+      }
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -1552,32 +1637,31 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     hi = max(hi, static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), o, 64)));
   }
   if ((tid & 63) == 0) { sm.wlo[tid >> 6] = lo; sm.whi[tid >> 6] = hi; }
+  if (tid == 0) { sm.count = 0u; sm.count2 = 0u; }
   __syncthreads();
-  if (tid == 0) {
-    uint32_t l = sm.wlo[0], h = sm.whi[0];
-    for (int w = 1; w < BS / 64; ++w) { l = min(l, sm.wlo[w]); h = max(h, sm.whi[w]); }
-    sm.lo = l; sm.hi = h;
-  }
-  __syncthreads();
-  lo = sm.lo;
-  const uint32_t range = sm.hi - lo;
+#pragma unroll
+  for (int w = 0; w < BS / 64; ++w) { lo = min(lo, sm.wlo[w]); hi = max(hi, sm.whi[w]); }
+  const uint32_t range = hi - lo;
   const int bits = range == 0u ? 0 : 32 - __clz(static_cast<int>(range));
 
-  // radix select over v = image - lo, digits of up to 11 bits from the top
+  // radix select over v = image - lo, digits of up to 11 bits from the top,
+  // until the boundary bin is small enough to rank
   unsigned long long prefix = 0ull, mask = 0ull;
   uint32_t rank = static_cast<uint32_t>(E), sel = static_cast<uint32_t>(B);
-  for (int shift = bits; shift > 0;) {
+  int shift = bits;
+  while (shift > 0 && sel > static_cast<uint32_t>(kTopkBoundary)) {
     const int width = shift < 11 ? shift : 11;
     shift -= width;
     const int nb = 1 << width;
     for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
     __syncthreads();
+#pragma unroll 4
     for (int b = tid; b < B; b += BS) {
       const uint32_t v = image(b) - lo;
       if ((static_cast<unsigned long long>(v) & mask) == prefix) atomicAdd(&sm.hist[(v >> shift) & (nb - 1)], 1u);
     }
     __syncthreads();
-    topk_find_bin(sm, nb, rank, prefix, shift);
+    topk_find_bin<BS>(sm, nb, rank, prefix, shift);
     __syncthreads();
     prefix = sm.prefix;
     rank = sm.rank;
@@ -1585,63 +1669,54 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     mask |= static_cast<unsigned long long>(nb - 1) << shift;
     __syncthreads();
   }
-  const uint32_t cstar = lo + static_cast<uint32_t>(prefix);   // image of the E-th smallest cost
-  unsigned long long limit;   // elites are the keys <= limit
-  if (rank == sel) {
-    limit = (static_cast<unsigned long long>(cstar) << 32) | 0xFFFFFFFFull;
+
+  if (sel <= static_cast<uint32_t>(kTopkBoundary)) {
+    // lower bins: elites; boundary bin (top digits equal to the prefix): ranked.
+    // With no pass taken (B small) shift = bits, which may be 32: 64-bit shifts.
+    const unsigned long long pd = prefix >> shift;
+    const uint32_t below = static_cast<uint32_t>(E) - rank;
+    topk_gather<BS>(B, lo, image, [&](uint32_t v, unsigned long long) { return (static_cast<unsigned long long>(v) >> shift) < pd; }, &sm.count,
+                    sm.keys, static_cast<uint32_t>(kMaxElites));
+    topk_gather<BS>(B, lo, image, [&](uint32_t v, unsigned long long) { return (static_cast<unsigned long long>(v) >> shift) == pd; }, &sm.count2,
+                    sm.sorted, static_cast<uint32_t>(kTopkBoundary));
+    __syncthreads();
+    topk_rank<BS>(sm.sorted, static_cast<int>(sel), [&](unsigned long long k, int r) {
+      if (static_cast<uint32_t>(r) < rank) sm.keys[below + static_cast<uint32_t>(r)] = k;
+    });
   } else {
-    // ties at the boundary: radix over the index bits of the keys with image c*
-    unsigned long long kp = 0ull, km = 0ull;
-    for (int pass = 0; pass < 3; ++pass) {
-      const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0), nb = pass == 2 ? 1024 : 2048;
-      for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
-      __syncthreads();
-      for (int b = tid; b < B; b += BS) {
-        const unsigned long long ib = static_cast<uint32_t>(b);
-        if (image(b) == cstar && (ib & km) == kp) atomicAdd(&sm.hist[(ib >> sh) & static_cast<unsigned long long>(nb - 1)], 1u);
+    // the boundary bin holds one image c* only
+    const uint32_t cstar = lo + static_cast<uint32_t>(prefix);
+    unsigned long long limit;   // elites are the keys <= limit
+    if (rank == sel) {
+      limit = (static_cast<unsigned long long>(cstar) << 32) | 0xFFFFFFFFull;
+    } else {
+      // ties at the boundary: radix over the index bits of the keys with image c*
+      unsigned long long kp = 0ull, km = 0ull;
+      for (int pass = 0; pass < 3; ++pass) {
+        const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0), nb = pass == 2 ? 1024 : 2048;
+        for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
+        __syncthreads();
+        for (int b = tid; b < B; b += BS) {
+          const unsigned long long ib = static_cast<uint32_t>(b);
+          if (image(b) == cstar && (ib & km) == kp) atomicAdd(&sm.hist[(ib >> sh) & static_cast<unsigned long long>(nb - 1)], 1u);
+        }
+        __syncthreads();
+        topk_find_bin<BS>(sm, nb, rank, kp, sh);
+        __syncthreads();
+        kp = sm.prefix;
+        rank = sm.rank;
+        km |= static_cast<unsigned long long>(nb - 1) << sh;
+        __syncthreads();
       }
-      __syncthreads();
-      topk_find_bin(sm, nb, rank, kp, sh);
-      __syncthreads();
-      kp = sm.prefix;
-      rank = sm.rank;
-      km |= static_cast<unsigned long long>(nb - 1) << sh;
-      __syncthreads();
+      limit = (static_cast<unsigned long long>(cstar) << 32) | kp;
     }
-    limit = (static_cast<unsigned long long>(cstar) << 32) | kp;
-  }
-  // gather the E keys <= limit, one counter bump per wave
-  if (tid == 0) sm.count = 0u;
-  __syncthreads();
-  for (int base = 0; base < B; base += BS) {
-    const int b = base + tid;
-    unsigned long long key = 0ull;
-    bool take = false;
-    if (b < B) {
-      key = (static_cast<unsigned long long>(image(b)) << 32) | static_cast<uint32_t>(b);
-      take = key <= limit;
-    }
-    const unsigned long long m = __ballot(take);
-    if (m != 0ull) {
-      const int lane = tid & 63;
-      const int leader = __ffsll(static_cast<long long>(m)) - 1;
-      uint32_t slot0 = 0u;
-      if (lane == leader) slot0 = atomicAdd(&sm.count, static_cast<uint32_t>(__popcll(m)));
-      slot0 = static_cast<uint32_t>(__shfl(static_cast<int>(slot0), leader, 64));
-      const uint32_t slot = slot0 + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
-      if (take && slot < static_cast<uint32_t>(kMaxElites)) sm.keys[slot] = key;
-    }
+    topk_gather<BS>(B, lo, image, [&](uint32_t, unsigned long long key) { return key <= limit; }, &sm.count,
+                    sm.keys, static_cast<uint32_t>(kMaxElites));
   }
   __syncthreads();
   const unsigned long long* ord;
   if (E <= kTopkRankSort) {
-    // rank of each key among the E (keys are distinct)
-    for (int e = tid; e < E; e += BS) {
-      const unsigned long long k = sm.keys[e];
-      int r = 0;
-      for (int q = 0; q < E; ++q) r += sm.keys[q] < k ? 1 : 0;
-      sm.sorted[r] = k;
-    }
+    topk_rank<BS>(sm.keys, E, [&](unsigned long long k, int r) { sm.sorted[r] = k; });
     ord = sm.sorted;
   } else {
     int M = 1;
@@ -1664,7 +1739,9 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     ord = sm.keys;
   }
   __syncthreads();
-  // elites, costs and softmax weights w_e = exp(-(s_e - s_0)/lambda) / sum
+  // elites, costs and softmax weights w_e = exp(-(s_e - s_0)/lambda) / sum;
+  // the unnormalised weights wait in LDS (the image cache is free by now)
+  float* wbuf = reinterpret_cast<float*>(sm.cache);
   const uint32_t i0 = static_cast<uint32_t>(ord[0]);
   const float s0 = P.cost[i0 < static_cast<uint32_t>(B) ? i0 : 0u];
   const bool uniform = !(P.lam < INFINITY) || !(s0 < INFINITY);
@@ -1675,20 +1752,20 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     const float ce = P.cost[idx];
     P.eidx[e] = idx;
     P.ecost[e] = ce;
-    P.w[e] = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
+    wbuf[e] = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
   }
   // normalisation sum in an order fixed by E alone (independent of the block
   // size): lane l of wave 0 adds e = l, l+64, ... in turn, then a butterfly.
   __syncthreads();
   if (tid < 64) {
     float acc = 0.0f;
-    for (int e = tid; e < E; e += 64) acc += P.w[e];
+    for (int e = tid; e < E; e += 64) acc += wbuf[e];
     acc = wave_sum64(acc);
     if (tid == 0) sm.red[0] = acc;
   }
   __syncthreads();
   const float inv = 1.0f / sm.red[0];
-  for (int e = tid; e < E; e += BS) P.w[e] *= inv;
+  for (int e = tid; e < E; e += BS) P.w[e] = wbuf[e] * inv;
   if (tid == 0 && !(s0 < INFINITY)) atomicOr(&P.ctrl[2], 1u);
 }
 

@@ -312,7 +312,7 @@ int mtp::cand_time_chunk(int B, int T, int n) {
   constexpr long long kTargetWaves = 4096;
   const long long waves = static_cast<long long>((B + kCandThreads - 1) / kCandThreads) * n * (kCandThreads / 64);
   long long chunks = waves >= kTargetWaves ? 1 : (kTargetWaves + waves - 1) / waves;
-  chunks = std::min<long long>(chunks, std::max(1, T / 16));
+  chunks = std::min<long long>(chunks, std::max(1, T / 4));
   int tc = static_cast<int>((T + chunks - 1) / chunks);
   tc = (tc + 3) & ~3;
   return std::max(tc, 4);

@@ -221,11 +221,16 @@ def test_topk_sizes(E, torch_mod):
 
 
 @pytest.mark.parametrize("B, E, kind", [(70000, 512, "ties"), (20011, 1500, "uniform"), (3000, 100, "equal"),
-                                        (17000, 4096, "ties"), (16384, 1, "uniform")])
+                                        (17000, 4096, "ties"), (16384, 1, "uniform"), (30000, 2000, "clustered"),
+                                        (900, 50, "extremes"), (5000, 2500, "equal"), (12000, 300, "lognormal")])
 def test_topk_batches_beyond_the_lds_cache_and_degenerate(B, E, kind, torch_mod):
     """Top-E for batches larger than the cost cache (read from HBM every pass),
     with rounded costs (many ties across the elite boundary), all-equal costs
-    (only the index order decides) and the largest elite sets."""
+    (only the index order decides), the largest elite sets, costs packed into a
+    sliver of the range by one huge outlier (the first digit leaves more keys
+    than can be ranked, later digits split them), a small batch whose image
+    range spans all 32 bits (-inf and +inf: no digit pass at all) and costs over
+    many orders of magnitude."""
     import torch
     cfg = W.point_mass_config(n_tensor=B - 40, n_gauss=40, n_elites=E)
     _log(f"[topk] B={B} E={E} {kind}")
@@ -237,12 +242,20 @@ def test_topk_batches_beyond_the_lds_cache_and_degenerate(B, E, kind, torch_mod)
         s[rng.choice(B, 30, replace=False)] = np.inf
     elif kind == "equal":
         s = np.full(B, 1.5, np.float32)
+    elif kind == "clustered":
+        s = (1.0 + 1e-4 * rng.uniform(size=B)).astype(np.float32)
+        s[rng.choice(B, 3, replace=False)] = [1e30, np.inf, np.nan]
+    elif kind == "extremes":
+        s = rng.choice(np.array([-np.inf, np.inf, np.nan, 0.0, -0.0, 3.0, -7.5], np.float32), B)
+    elif kind == "lognormal":
+        s = np.exp(rng.normal(0.0, 5.0, size=B)).astype(np.float32)
     else:
         s = rng.uniform(0, 10, size=B).astype(np.float32)
     b["cost"].copy_(torch.from_numpy(s).cuda())
     plan.run_stage(2, 0, 0)
     torch_mod.cuda.synchronize()
-    assert np.array_equal(b["elite_idx"].cpu().numpy(), OP.top_elites(s.astype(np.float64), E))
+    want = OP.top_elites(np.where(s == 0, 0.0, s).astype(np.float64), E)
+    assert np.array_equal(b["elite_idx"].cpu().numpy(), want)
     plan.close()
 
 
