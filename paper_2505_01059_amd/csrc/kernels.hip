@@ -19,13 +19,41 @@ __global__ __launch_bounds__(kCandThreads) void k_paths(PlanDesc P, int k) {
 
 static int cand_chunk(const PlanDesc& P) { return P.tc < kTChunk ? P.tc : kTChunk; }
 
+// Candidate tiles holding local samples (the first ones) and the tile holding
+// the nominal mean (the last candidate).
+__host__ __device__ inline int local_tiles(const PlanDesc& P) { return (P.G - 1 + kCandThreads - 1) / kCandThreads; }
+__host__ __device__ inline int nominal_tile(const PlanDesc& P) { return (P.B - 1) / kCandThreads; }
+
 // grid (candidate tiles, joints, horizon chunks of P.tc steps); LDS sized for
-// the plan so that several workgroups fit on a compute unit
-__global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) {
+// the plan so that several workgroups fit on a compute unit.  With mode
+// kCandLocal the grid covers only the local tiles and the nominal tile.
+__global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k, int mode) {
   extern __shared__ float cand_lds[];
   const CandView v = cand_view_dyn(cand_lds, P.L, P.W, P.tc < kTChunk ? P.tc : kTChunk);
   const int t_begin = blockIdx.z * P.tc;
-  cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, t_begin, min(P.T, t_begin + P.tc), v);
+  int tile = blockIdx.x;
+  if (mode == kCandLocal && tile >= local_tiles(P)) tile = nominal_tile(P);
+  cand_tile(P, P.ctrl[0], k, blockIdx.y, tile * kCandThreads, t_begin, min(P.T, t_begin + P.tc), v, mode);
+}
+
+// Workgroups of a rollout launch beyond P.roll_blocks, each alone on its
+// compute unit (the launch asks for enough LDS to keep one workgroup per unit),
+// draw the tensor-path controls of iteration P.gen_k into P.U2 on the units the
+// rollout leaves idle: items (tensor tile, joint) over the whole horizon.
+__device__ __forceinline__ void gen_tensor_tiles(const PlanDesc& P) {
+  extern __shared__ float gen_lds[];
+  const CandView v = cand_view_dyn(gen_lds, P.L, P.W, P.T < kTChunk ? P.T : kTChunk);
+  PlanDesc Q = P;
+  Q.U = P.U2;
+  const int first = (P.G - 1) / kCandThreads;                  // tile of the first tensor path
+  const int last = (P.G - 1 + P.P - 1) / kCandThreads;         // tile of the last one
+  const int items = (last - first + 1) * P.n;
+  const int gens = static_cast<int>(gridDim.x) - P.roll_blocks;
+  const uint32_t r = P.ctrl[0];
+  for (int it = static_cast<int>(blockIdx.x) - P.roll_blocks; it < items; it += gens) {
+    const int tile = first + it / P.n, j = it - (it / P.n) * P.n;
+    cand_tile(Q, r, P.gen_k, j, tile * kCandThreads, 0, P.T, v, kCandTensor);
+  }
 }
 
 __global__ __launch_bounds__(kTopkThreads) void k_entropy(PlanDesc P, int k) {
@@ -49,22 +77,25 @@ __device__ __forceinline__ int xcd_contiguous_block(int g, int G) {
 }
 
 __global__ __launch_bounds__(kRollThreads) void k_rollout_point_mass(PlanDesc P) {
+  if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
   __shared__ PointMassSmem sm;
   stage_obstacles(P, sm);
   __syncthreads();
-  const int b = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
+  const int b = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
   if (b < P.B) rollout_point_mass_any(P, b, sm);
 }
 
 template <int N, bool CONTACT>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_chain(PlanDesc P) {
-  const int b = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
+  if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
+  const int b = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
   if (b < P.B) rollout_chain<N, CONTACT>(P, b);
 }
 
 template <int N, bool CONTACT>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_chain_pair(PlanDesc P) {
-  const int g = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
+  if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
+  const int g = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
   const int b = g >> 1;
   if (b < P.B) rollout_chain_pair<N, CONTACT>(P, b, (g & 1) != 0);
 }
@@ -90,7 +121,8 @@ __global__ __launch_bounds__(64) void k_seg_init(SegCtl* ctl) {
 
 template <int N>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_chain_quad(PlanDesc P) {
-  const int g = xcd_contiguous_block(blockIdx.x, gridDim.x) * kRollThreads + threadIdx.x;
+  if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
+  const int g = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
   const int b = g >> 2;
   if (b < P.B) rollout_chain_quad<N>(P, b, g & 3);
 }
@@ -133,16 +165,63 @@ int supported_chain_links(int* out, int cap) {
   return cnt;
 }
 
-static hipError_t launch_rollout(const PlanDesc& P, hipStream_t st) {
-  const dim3 grid((P.B + kRollThreads - 1) / kRollThreads);
+// Workgroups of the rollout kernel proper (one to four lanes per candidate).
+int rollout_blocks(const PlanDesc& P) {
+  const long long lanes_per = is_quad_chain(P.dyn, P.n_links) ? 4 : is_pair_chain(P.dyn, P.n_links) ? 2 : 1;
+  return static_cast<int>((lanes_per * P.B + kRollThreads - 1) / kRollThreads);
+}
+
+// LDS of a rollout launch that also draws tensor-path controls: the candidate
+// tile's arrays over the whole horizon, and enough to leave room for only one
+// workgroup per compute unit (160 KB each), so that no generator workgroup
+// shares a unit, and its SIMDs, with rollout waves.
+static size_t gen_lds_bytes(const PlanDesc& P) {
+  constexpr size_t kOnePerUnit = 96 * 1024;
+  const size_t tile = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, P.T < kTChunk ? P.T : kTChunk));
+  return tile > kOnePerUnit ? tile : kOnePerUnit;
+}
+
+// The rollout of P.U; with gen_k >= 0 the launch adds workgroups up to
+// P.gen_grid that draw iteration gen_k's tensor-path controls into P.U2.
+static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) {
+  PlanDesc P = P0;
+  if (is_pair_chain(P.dyn, P.n_links) && P.seg_ctl != nullptr && P.seg_grid > 0) {
+    k_seg_init<<<1, 64, 0, st>>>(P.seg_ctl);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (P.dyn == kChain) {
+      switch (P.n_links) {
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, false><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+        MTP_CHAIN_LINKS(X)
+#undef X
+        default: break;
+      }
+      return hipErrorInvalidValue;
+    }
+    switch (P.n_links) {
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, true><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+      MTP_CONTACT_LINKS(X)
+#undef X
+      default: break;
+    }
+    return hipErrorInvalidValue;
+  }
+  P.roll_blocks = rollout_blocks(P);
+  P.gen_k = gen_k;
+  int blocks = P.roll_blocks;
+  size_t lds = 0;
+  if (gen_k >= 0 && P.U2 != nullptr && P.gen_grid > P.roll_blocks) {
+    blocks = P.gen_grid;
+    lds = gen_lds_bytes(P);
+  }
+  const dim3 grid(blocks);
   if (P.dyn == kPointMass) {
-    k_rollout_point_mass<<<grid, kRollThreads, 0, st>>>(P);
+    k_rollout_point_mass<<<grid, kRollThreads, lds, st>>>(P);
     return hipGetLastError();
   }
   if (is_quad_chain(P.dyn, P.n_links)) {
-    const dim3 qgrid((4 * P.B + kRollThreads - 1) / kRollThreads);
     switch (P.n_links) {
-#define X(N) case N: if constexpr (quad_chain_links<N>()) { k_rollout_chain_quad<N><<<qgrid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (quad_chain_links<N>()) { k_rollout_chain_quad<N><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
       MTP_CHAIN_LINKS(X)
 #undef X
       default: break;
@@ -150,38 +229,16 @@ static hipError_t launch_rollout(const PlanDesc& P, hipStream_t st) {
     return hipErrorInvalidValue;
   }
   if (is_pair_chain(P.dyn, P.n_links)) {
-    if (P.seg_ctl != nullptr && P.seg_grid > 0) {
-      k_seg_init<<<1, 64, 0, st>>>(P.seg_ctl);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      if (P.dyn == kChain) {
-        switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, false><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
-          MTP_CHAIN_LINKS(X)
-#undef X
-          default: break;
-        }
-        return hipErrorInvalidValue;
-      }
-      switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, true><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
-        MTP_CONTACT_LINKS(X)
-#undef X
-        default: break;
-      }
-      return hipErrorInvalidValue;
-    }
-    const dim3 pgrid((2 * P.B + kRollThreads - 1) / kRollThreads);
     if (P.dyn == kChain) {
       switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, false><<<pgrid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, false><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
         MTP_CHAIN_LINKS(X)
 #undef X
         default: break;
       }
     } else {
       switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, true><<<pgrid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, true><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
         MTP_CONTACT_LINKS(X)
 #undef X
         default: break;
@@ -191,7 +248,7 @@ static hipError_t launch_rollout(const PlanDesc& P, hipStream_t st) {
   }
   if (P.dyn == kChain) {
     switch (P.n_links) {
-#define X(N) case N: if constexpr (!pair_chain_links<N>() && !quad_chain_links<N>()) { k_rollout_chain<N, false><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (!pair_chain_links<N>() && !quad_chain_links<N>()) { k_rollout_chain<N, false><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
       MTP_CHAIN_LINKS(X)
 #undef X
       default: break;
@@ -199,12 +256,27 @@ static hipError_t launch_rollout(const PlanDesc& P, hipStream_t st) {
     return hipErrorInvalidValue;
   }
   switch (P.n_links) {
-#define X(N) case N: if constexpr (!pair_chain_links<N>()) { k_rollout_chain<N, true><<<grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (!pair_chain_links<N>()) { k_rollout_chain<N, true><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
     MTP_CONTACT_LINKS(X)
 #undef X
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+static hipError_t launch_candidates(const PlanDesc& P, int k, int mode, hipStream_t st) {
+  if (P.P > 0 && P.wor && mode != kCandLocal) {
+    k_paths<<<(P.P + kCandThreads - 1) / kCandThreads, kCandThreads, 0, st>>>(P, k);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int all_tiles = (P.B + kCandThreads - 1) / kCandThreads;
+  int tiles = all_tiles;
+  if (mode == kCandLocal) tiles = nominal_tile(P) < local_tiles(P) ? local_tiles(P) : local_tiles(P) + 1;
+  const dim3 grid(tiles, P.n, (P.T + P.tc - 1) / P.tc);
+  const size_t lds = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, cand_chunk(P)));
+  k_candidates<<<grid, kCandThreads, lds, st>>>(P, k, mode);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_ctrl(const PlanDesc& P, uint32_t r, int shift, const float* x0_src, hipStream_t st) {
@@ -219,19 +291,10 @@ hipError_t launch_shift(const PlanDesc& P, hipStream_t st) {
 
 hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
   switch (stage) {
-    case 0: {
-      if (P.P > 0 && P.wor) {
-        k_paths<<<(P.P + kCandThreads - 1) / kCandThreads, kCandThreads, 0, st>>>(P, k);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-      }
-      const dim3 grid((P.B + kCandThreads - 1) / kCandThreads, P.n, (P.T + P.tc - 1) / P.tc);
-      const size_t lds = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, cand_chunk(P)));
-      k_candidates<<<grid, kCandThreads, lds, st>>>(P, k);
-      return hipGetLastError();
-    }
+    case 0:
+      return launch_candidates(P, k, kCandAll, st);
     case 1:
-      return launch_rollout(P, st);
+      return launch_rollout(P, st, -1);
     case 2:
       k_topk<<<1, kTopkThreads, 0, st>>>(P);
       if (P.diag & 1) {
@@ -251,6 +314,25 @@ hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
   }
 }
 
+// Stage `stage` of iteration k within a run of iterations [k0, k1).  With the
+// overlap (P.U2 set) iteration k works on U (k - k0 even) or U2 (odd); its
+// rollout also draws iteration k+1's tensor-path controls into the other
+// buffer on the compute units the rollout leaves idle, and iteration k+1's
+// candidate stage then adds only the local samples and the nominal mean.  The
+// values are those of the plain sequence: the tensor paths do not depend on
+// the sampling distribution.
+hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st) {
+  const bool overlap = P.U2 != nullptr;
+  if (!overlap) return launch_stage(P, stage, k, st);
+  PlanDesc Pk = P;
+  if ((k - k0) & 1) { Pk.U = P.U2; Pk.U2 = P.U; }
+  switch (stage) {
+    case 0: return launch_candidates(Pk, k, k > k0 ? kCandLocal : kCandAll, st);
+    case 1: return launch_rollout(Pk, st, k + 1 < k1 ? k + 1 : -1);
+    default: return launch_stage(Pk, stage, k, st);
+  }
+}
+
 template <typename F>
 static hipError_t seg_grid_for(F kernel, const PlanDesc& P, int* grid) {
   int dev = 0, cus = 0, occ = 0;
@@ -260,6 +342,16 @@ static hipError_t seg_grid_for(F kernel, const PlanDesc& P, int* grid) {
   if (e != hipSuccess) return e;
   *grid = (occ > 0 ? occ : 1) * (cus > 0 ? cus : 1);
   (void)P;
+  return hipSuccess;
+}
+
+hipError_t gen_configure(PlanDesc* P) {
+  if (P->U2 == nullptr) return hipSuccess;
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  P->gen_grid = cus;
   return hipSuccess;
 }
 

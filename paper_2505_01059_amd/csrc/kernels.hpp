@@ -12,9 +12,17 @@ hipError_t launch_set_ctrl(const PlanDesc& P, uint32_t r, int shift, const float
 hipError_t launch_shift(const PlanDesc& P, hipStream_t st);
 // stage: 0 candidates, 1 rollout, 2 top-E, 3 refit (the replan index is read from P.ctrl[0])
 hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st);
+// Stage of iteration k in a run of iterations [k0, k1) (next iteration's tensor
+// paths drawn during the rollout when the plan has a second U buffer).
+hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st);
+// Workgroups of the (not time-sliced) rollout kernel of a plan.
+int rollout_blocks(const PlanDesc& P);
 // Grid and segment count of the time-sliced pair-lane rollout for the current
 // device (no-op for plans that do not use it).
 hipError_t seg_configure(PlanDesc* P);
+// Workgroups of a rollout launch that also draws the next tensor paths: one per
+// compute unit of the current device (no-op for plans without a second U buffer).
+hipError_t gen_configure(PlanDesc* P);
 // defined in plan.cpp
 int segment_count(int groups, int resident_waves);
 

@@ -63,6 +63,12 @@ struct PlanDesc {
   uint32_t* seg_done;    // [groups] segments completed, tagged with the launch epoch
   float* seg_state;      // [(n + 1)][groups][64] angles, rates and cost between segments
   int32_t seg_S, seg_len, seg_grid;
+  // rollout launches that also draw the next iteration's tensor-path controls
+  // (see gen_tensor_tiles): the first roll_blocks workgroups roll out, the rest
+  // write the tensor-path controls of iteration gen_k into U2
+  float* U2;             // second [T][n][ldU] buffer, or null
+  int32_t roll_blocks, gen_k;
+  int32_t gen_grid;      // workgroups of such a launch: one per compute unit
 };
 
 // ------------------------------------------------------------------ Philox
@@ -333,21 +339,27 @@ __device__ __forceinline__ void path_tile(const PlanDesc& P, uint32_t r, int k, 
     if (l < L) P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(x[l]);
 }
 
+// Which candidates a tile writes: all, only the tensor paths (they do not
+// depend on the sampling distribution, so they can be drawn an iteration
+// ahead), or only the local samples and the nominal mean.
+constexpr int kCandAll = 0, kCandTensor = 1, kCandLocal = 2;
+
 // Candidates [b0, b0 + kCandThreads) of joint j over steps [t_begin, t_end)
 // (t_begin a multiple of 4).  Tensor paths read their layer indices from I.
 // Every thread of the tile must call this (it synchronises the workgroup).
 __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, int j, int b0, int t_begin,
-                                          int t_end, const CandView& sm) {
+                                          int t_end, const CandView& sm, int mode = kCandAll) {
   const int tid = threadIdx.x;
   const int b = b0 + tid;
   const int G1 = P.G - 1;                       // local samples [0, G1)
   const int tens_lo = G1, tens_hi = G1 + P.P;   // tensor paths [G1, G1+P)
-  const bool tile_has_tensor = (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
+  const bool tile_has_tensor = mode != kCandLocal && (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
   const float lo = P.u_min, hi = P.u_max;
   const size_t ld = static_cast<size_t>(P.ldU);
   const bool live = b < P.B;
-  const bool is_local = live && b < G1;
-  const bool is_tensor = live && b >= tens_lo && b < tens_hi;
+  const bool is_local = mode != kCandTensor && live && b < G1;
+  const bool is_tensor = mode != kCandLocal && live && b >= tens_lo && b < tens_hi;
+  const bool is_nominal = mode != kCandTensor && live && b >= tens_hi;
 
   if (tile_has_tensor) {
     if (P.wor) {
@@ -455,7 +467,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           __builtin_nontemporal_store(clampf(v, lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
         }
       }
-    } else if (live) {
+    } else if (is_nominal) {
       // nominal mean
 #pragma unroll 4
       for (int i = 0; i < tn; ++i) __builtin_nontemporal_store(clampf(sm.tmu[i], lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);

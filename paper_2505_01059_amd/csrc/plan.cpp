@@ -120,7 +120,7 @@ bool validate_config(const mtp_config* c, std::string* why, mtp_status* code) {
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-Layout compute_layout(const mtp_config& c) {
+Layout compute_layout(const mtp_config& c, bool plan) {
   Layout L{};
   const size_t T = c.horizon, n = c.ctrl_dim, d = c.state_dim;
   const size_t B = static_cast<size_t>(c.n_tensor) + c.n_gauss;
@@ -154,6 +154,8 @@ Layout compute_layout(const mtp_config& c) {
   L.w = take(static_cast<size_t>(c.n_elites) * 4);
   L.X = c.n_debug_states > 0 ? take(T * d * static_cast<size_t>(c.n_debug_states) * 4) : 0;
   L.seg_state = L.segmented ? take((n + 1) * groups * 64 * 4) : 0;
+  L.overlap = plan && uses_gen_overlap(c);
+  L.U2 = L.overlap ? take(T * n * L.ldU * 4) : 0;
   L.transient = off;
   L.total = L.resident + L.transient;
   return L;
@@ -275,6 +277,19 @@ void mtp::set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8
   P->w = reinterpret_cast<float*>(tb + L.w);
   P->X = c.n_debug_states > 0 ? reinterpret_cast<float*>(tb + L.X) : nullptr;
   P->seg_state = L.segmented ? reinterpret_cast<float*>(tb + L.seg_state) : nullptr;
+  P->U2 = L.overlap ? reinterpret_cast<float*>(tb + L.U2) : nullptr;
+}
+
+bool mtp::uses_gen_overlap(const mtp_config& c) {
+  constexpr long long kUnits = 256;     // compute units
+  constexpr long long kMinFree = 32;    // units left for drawing the next tensor paths
+  if (c.n_iters < 2 || c.sample_wor || c.n_tensor < 1024 || uses_segmented_rollout(c)) return false;
+  const long long B = static_cast<long long>(c.n_tensor) + c.n_gauss;
+  const bool chain = c.dynamics == MTP_DYN_CHAIN || c.dynamics == MTP_DYN_CHAIN_CONTACT;
+  const bool quad = c.dynamics == MTP_DYN_CHAIN && c.n_links >= 5 && c.n_links <= 8;
+  const bool pair = chain && c.n_links >= 10 && (c.n_links % 2) == 0;
+  const long long lanes = (quad ? 4 : pair ? 2 : 1) * B;
+  return (lanes + kRollThreads - 1) / kRollThreads <= kUnits - kMinFree;
 }
 
 bool mtp::uses_segmented_rollout(const mtp_config& c) {
@@ -348,6 +363,7 @@ PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uin
   P.seg_ctl = L.segmented ? reinterpret_cast<SegCtl*>(base + L.seg_ctl) : nullptr;
   P.seg_done = L.segmented ? reinterpret_cast<uint32_t*>(base + L.seg_done) : nullptr;
   P.seg_S = 0; P.seg_len = 0; P.seg_grid = 0;   // set by the launcher's device query (seg_configure)
+  P.roll_blocks = 0; P.gen_k = -1; P.gen_grid = 0;   // gen_grid: device query (gen_configure)
   if (tb != nullptr) set_transient(&P, c, L, tb);
   return P;
 }
@@ -390,7 +406,7 @@ mtp_status mtp::upload_plan_tables(const mtp_config& c, const PlanDesc& P, const
 hipError_t mtp::enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStream_t st) {
   for (int k = k_begin; k < k_end; ++k)
     for (int stage = 0; stage < 4; ++stage) {
-      const hipError_t e = launch_stage(P, stage, k, st);
+      const hipError_t e = launch_iteration_stage(P, stage, k, k_begin, k_end, st);
       if (e != hipSuccess) return e;
     }
   return hipSuccess;
@@ -430,7 +446,7 @@ static hipError_t enqueue_iterations_plan(mtp_plan* p, int k0, int k1) {
       hipError_t e = take_event(p, &a);
       if (e == hipSuccess) e = take_event(p, &b);
       if (e == hipSuccess) e = hipEventRecord(a, p->stream);
-      if (e == hipSuccess) e = launch_stage(p->P, stage, k, p->stream);
+      if (e == hipSuccess) e = launch_iteration_stage(p->P, stage, k, k0, k1, p->stream);
       if (e == hipSuccess) e = hipEventRecord(b, p->stream);
       if (e != hipSuccess) return e;
       p->pending.push_back({stage, a, b});
@@ -446,7 +462,7 @@ extern "C" {
 
 size_t mtp_workspace_bytes(const mtp_config* cfg) {
   if (!validate_config(cfg, nullptr, nullptr)) return 0;
-  return compute_layout(*cfg).total;
+  return compute_layout(*cfg, true).total;
 }
 
 size_t mtp_transient_bytes(const mtp_config* cfg) {
@@ -473,7 +489,7 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
   std::string why;
   mtp_status code = MTP_OK;
   if (!validate_config(cfg, &why, &code)) return code;
-  const Layout lay = compute_layout(*cfg);
+  const Layout lay = compute_layout(*cfg, true);
   if (d_workspace == nullptr || ws_bytes < lay.total || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
     return MTP_ERR_WORKSPACE;
   mtp_plan* p = new (std::nothrow) mtp_plan();
@@ -495,7 +511,7 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
     delete p;
     return s;
   }
-  if (seg_configure(&p->P) != hipSuccess) {
+  if (seg_configure(&p->P) != hipSuccess || gen_configure(&p->P) != hipSuccess) {
     delete p;
     return MTP_ERR_DEVICE;
   }

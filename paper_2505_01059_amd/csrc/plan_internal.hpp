@@ -20,14 +20,17 @@ namespace mtp {
 struct Layout {
   size_t ldU;
   size_t ctrl, x0, mu, sigma, tmp, action, basis, span, task, sparams, entropy, seg_ctl, seg_done;   // resident
-  size_t Z, I, U, cost, eidx, ecost, w, X, seg_state;                                       // transient
+  size_t Z, I, U, cost, eidx, ecost, w, X, seg_state, U2;                                   // transient
   bool segmented;   // the rollout is time-sliced (see uses_segmented_rollout)
+  bool overlap;     // second U buffer: next tensor paths drawn during the rollout (see uses_gen_overlap)
   size_t resident, transient;
   size_t total;   // resident + transient
 };
 
 bool validate_config(const mtp_config* c, std::string* why, mtp_status* code);
-Layout compute_layout(const mtp_config& c);
+// plan: the layout of a single plan (which may add the second U buffer); the
+// batched kernel and the server's transient slabs use the plain one.
+Layout compute_layout(const mtp_config& c, bool plan = false);
 void build_tables(const mtp_config& c, std::vector<float>* basis, std::vector<int32_t>* span);
 mtp_status upload_plan_tables(const mtp_config& c, const PlanDesc& P, const float* task, const float* sparams,
                               hipStream_t st, std::string* err);
@@ -39,6 +42,11 @@ void set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* t
 // per candidate) without randomised replicas whose launch has more waves than
 // the chip has SIMDs.
 bool uses_segmented_rollout(const mtp_config& c);
+// Whether a single plan draws the next iteration's tensor-path controls during
+// each rollout: more than one iteration, with-replacement paths (at least 1024),
+// no time slicing, and a rollout that leaves at least 32 of the 256 compute
+// units free.
+bool uses_gen_overlap(const mtp_config& c);
 // Segments of the time-sliced rollout for a given number of resident waves.
 int segment_count(int groups, int resident_waves);
 // Rounds of the without-replacement path permutation: 2 L ceil(log2 W).

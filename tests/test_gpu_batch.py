@@ -40,6 +40,27 @@ def small_mix():
     ]
 
 
+def overlap_mix():
+    """Plans for which the single-plan path draws each next iteration's tensor
+    paths during the rollout (at least 1024 tensor paths, a rollout that leaves
+    compute units free, more than one iteration), with odd and even iteration
+    counts (the last iteration in either U buffer), a tile shared by local and
+    tensor candidates, every rollout form and every interpolation."""
+    return [
+        W.chain_config(name="o_c7", interp=W.AKIMA, n_tensor=1100, n_gauss=101, horizon=40, n_elites=40,
+                       n_iters=3, seed=21),
+        W.chain_config(name="o_c7b", interp=W.BSPLINE, n_tensor=2048, n_gauss=256, horizon=33, n_elites=64,
+                       n_iters=4, seed=22),
+        W.point_mass_config(name="o_pm", n_tensor=3000, n_gauss=77, horizon=45, n_elites=32, n_iters=5, seed=23),
+        W.chain_config(name="o_c12", n_links=12, interp=W.BSPLINE, n_tensor=1500, n_gauss=100, horizon=32,
+                       n_layers=6, n_width=20, n_elites=30, n_iters=2, seed=24),
+        W.chain_contact_config(name="o_k4", n_links=4, n_tensor=1200, n_gauss=64, horizon=30, n_layers=6,
+                               n_width=16, n_elites=16, n_iters=3, seed=25),
+        W.chain_config(name="o_c3", n_links=3, interp=W.LINEAR, n_tensor=1024, n_gauss=1, horizon=20,
+                       n_elites=8, n_iters=2, seed=26),
+    ]
+
+
 def standalone(cfg, x0, replans, shift=1):
     import torch
     import paper_2505_01059_amd as mtp
@@ -74,6 +95,36 @@ def test_batch_equals_standalone(use_graph):
         assert np.array_equal(acts[i], a), c.name
         if c.diagnostics:
             assert np.array_equal(b["entropy"].cpu().numpy(), ent), c.name
+    bt.close()
+
+
+def test_overlapped_tensor_paths_equal_the_plain_sequence():
+    """Single plans that draw iteration k+1's tensor paths during iteration k's
+    rollout (graph replay and the stage-timed launch sequence) give the bits of
+    the batched kernel, which runs the stages one after the other."""
+    import torch
+    import paper_2505_01059_amd as mtp
+    cfgs = overlap_mix()
+    x0s = [W.initial_state(c, seed=i) for i, c in enumerate(cfgs)]
+    _log(f"[overlap] {len(cfgs)} instances")
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    xp = bt.pack_x0(x0s)
+    for r in range(2):
+        bt.replan(xp, shift=1)
+    acts = bt.actions()
+    for i, c in enumerate(cfgs):
+        b = bt.buffers(i)
+        for timed in (False, True):
+            p = mtp.Plan(c, device="cuda:0")
+            p.set_stage_timing(timed)
+            for r in range(2):
+                p.replan(x0s[i], shift=1, replan_idx=r)
+            torch.cuda.synchronize()
+            pb = p.buffers()
+            assert np.array_equal(pb["mu"].cpu().numpy(), b["mu"].cpu().numpy()), (c.name, timed)
+            assert np.array_equal(pb["sigma"].cpu().numpy(), b["sigma"].cpu().numpy()), (c.name, timed)
+            assert np.array_equal(p.action(), acts[i]), (c.name, timed)
+            p.close()
     bt.close()
 
 
