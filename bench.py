@@ -138,7 +138,7 @@ def main():
         return copy_probe(args.copy_probe_mib, max(args.steps, 1))
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(instances shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
+              "(instances shard across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -214,7 +214,8 @@ def main():
         "config": {"workload": args.workload, "candidates": B, "tensor": cfg.n_tensor,
                    "gaussian": cfg.n_gauss, "horizon": T, "ctrl_dim": cfg.ctrl_dim,
                    "layers": cfg.n_layers, "width": cfg.n_width, "elites": cfg.n_elites,
-                   "iters": K, "interp": "akima" if cfg.interp else "bspline"},
+                   "iters": K, "interp": W.INTERP_NAMES[int(cfg.interp)],
+                   "overlap_tensor_paths": plan.draws_ahead()},
         "replans_per_s": args.steps / wall,
         "latency_ms_p50": round(p50, 4), "latency_ms_p99": round(p99, 4),
         "stage_ms_per_launch": stage_ms,

@@ -209,6 +209,16 @@ mtp_status mtp_set_stage_timing(mtp_plan* p, int32_t enable);
 mtp_status mtp_get_stage_times(mtp_plan* p, double* h_ms4, uint64_t* h_count4);
 
 mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
+
+/* 1 if the plan draws each next CEM iteration's tensor-path controls during the
+ * current iteration's rollout, else 0 (decided at creation from the config: more
+ * than one iteration, paths with replacement, at least 1024 of them, and a
+ * rollout grid that leaves at least 32 of the 256 compute units free).  Such a
+ * plan's workspace holds a second [T][n][ldU] candidate buffer; the U buffer of
+ * mtp_get_buffers still holds the candidates of the last iteration run.  The
+ * results are the same bits either way (Alg. 2: the tensor paths do not depend
+ * on the sampling distribution being refitted). */
+int32_t mtp_plan_draws_ahead(const mtp_plan* p);
 /* Status flags of the last replan: bit 0 = every elite cost was +inf (weights fell back to uniform). */
 mtp_status mtp_get_flags(mtp_plan* p, uint32_t* h_flags);
 mtp_status mtp_plan_destroy(mtp_plan* p);

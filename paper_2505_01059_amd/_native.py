@@ -77,6 +77,7 @@ def load():
         "mtp_run_stage": (c_int32, [P, c_int32, c_uint32, c_int32]),
         "mtp_set_x0": (c_int32, [P, P]),
         "mtp_set_graph_mode": (c_int32, [P, c_int32]),
+        "mtp_plan_draws_ahead": (c_int32, [P]),
         "mtp_get_buffers": (c_int32, [P, P]),
         "mtp_get_flags": (c_int32, [P, POINTER(c_uint32)]),
         "mtp_plan_destroy": (c_int32, [P]),
@@ -302,6 +303,10 @@ class Plan:
 
     def run_stage(self, stage, replan_idx, k):
         _check(self.lib, self.lib.mtp_run_stage(self.handle, int(stage), int(replan_idx), int(k)), self.handle)
+
+    def draws_ahead(self):
+        """Whether each rollout also draws the next iteration's tensor-path controls."""
+        return bool(self.lib.mtp_plan_draws_ahead(self.handle))
 
     def set_graph_mode(self, on):
         _check(self.lib, self.lib.mtp_set_graph_mode(self.handle, 1 if on else 0), self.handle)

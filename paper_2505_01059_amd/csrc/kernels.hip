@@ -315,7 +315,8 @@ hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
 }
 
 // Stage `stage` of iteration k within a run of iterations [k0, k1).  With the
-// overlap (P.U2 set) iteration k works on U (k - k0 even) or U2 (odd); its
+// overlap (P.U2 set) iteration k works on U (k1 - 1 - k even, so the last
+// iteration always ends in U) or U2 (odd); its
 // rollout also draws iteration k+1's tensor-path controls into the other
 // buffer on the compute units the rollout leaves idle, and iteration k+1's
 // candidate stage then adds only the local samples and the nominal mean.  The
@@ -325,7 +326,7 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
   const bool overlap = P.U2 != nullptr;
   if (!overlap) return launch_stage(P, stage, k, st);
   PlanDesc Pk = P;
-  if ((k - k0) & 1) { Pk.U = P.U2; Pk.U2 = P.U; }
+  if ((k1 - 1 - k) & 1) { Pk.U = P.U2; Pk.U2 = P.U; }
   switch (stage) {
     case 0: return launch_candidates(Pk, k, k > k0 ? kCandLocal : kCandAll, st);
     case 1: return launch_rollout(Pk, st, k + 1 < k1 ? k + 1 : -1);

@@ -116,6 +116,7 @@ def test_overlapped_tensor_paths_equal_the_plain_sequence():
         b = bt.buffers(i)
         for timed in (False, True):
             p = mtp.Plan(c, device="cuda:0")
+            assert p.draws_ahead(), c.name
             p.set_stage_timing(timed)
             for r in range(2):
                 p.replan(x0s[i], shift=1, replan_idx=r)
@@ -124,6 +125,9 @@ def test_overlapped_tensor_paths_equal_the_plain_sequence():
             assert np.array_equal(pb["mu"].cpu().numpy(), b["mu"].cpu().numpy()), (c.name, timed)
             assert np.array_equal(pb["sigma"].cpu().numpy(), b["sigma"].cpu().numpy()), (c.name, timed)
             assert np.array_equal(p.action(), acts[i]), (c.name, timed)
+            # the U buffer holds the last iteration's candidates in both
+            B = c.n_samples
+            assert np.array_equal(pb["U"][:, :, :B].cpu().numpy(), b["U"][:, :, :B].cpu().numpy()), (c.name, timed)
             p.close()
     bt.close()
 
