@@ -171,14 +171,18 @@ int rollout_blocks(const PlanDesc& P) {
   return static_cast<int>((lanes_per * P.B + kRollThreads - 1) / kRollThreads);
 }
 
+// LDS that leaves room for only one workgroup per compute unit (160 KB each).
+// A rollout launch with fewer workgroups than units asks for it so that no two
+// of its workgroups, or a rollout and a generator workgroup, share a unit and
+// its SIMDs (the dispatcher was seen to pair workgroups on a unit now and
+// then, which doubles those waves' time).
+constexpr size_t kOnePerUnitLds = 96 * 1024;
+
 // LDS of a rollout launch that also draws tensor-path controls: the candidate
-// tile's arrays over the whole horizon, and enough to leave room for only one
-// workgroup per compute unit (160 KB each), so that no generator workgroup
-// shares a unit, and its SIMDs, with rollout waves.
+// tile's arrays over the whole horizon, at least kOnePerUnitLds.
 static size_t gen_lds_bytes(const PlanDesc& P) {
-  constexpr size_t kOnePerUnit = 96 * 1024;
   const size_t tile = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, P.T < kTChunk ? P.T : kTChunk));
-  return tile > kOnePerUnit ? tile : kOnePerUnit;
+  return tile > kOnePerUnitLds ? tile : kOnePerUnitLds;
 }
 
 // The rollout of P.U; with gen_k >= 0 the launch adds workgroups up to
@@ -213,6 +217,8 @@ static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) 
   if (gen_k >= 0 && P.U2 != nullptr && P.gen_grid > P.roll_blocks) {
     blocks = P.gen_grid;
     lds = gen_lds_bytes(P);
+  } else if (P.roll_blocks < P.gen_grid) {
+    lds = kOnePerUnitLds;
   }
   const dim3 grid(blocks);
   if (P.dyn == kPointMass) {
@@ -347,7 +353,6 @@ static hipError_t seg_grid_for(F kernel, const PlanDesc& P, int* grid) {
 }
 
 hipError_t gen_configure(PlanDesc* P) {
-  if (P->U2 == nullptr) return hipSuccess;
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -20,8 +20,9 @@ int rollout_blocks(const PlanDesc& P);
 // Grid and segment count of the time-sliced pair-lane rollout for the current
 // device (no-op for plans that do not use it).
 hipError_t seg_configure(PlanDesc* P);
-// Workgroups of a rollout launch that also draws the next tensor paths: one per
-// compute unit of the current device (no-op for plans without a second U buffer).
+// Compute units of the current device: the workgroups of a rollout launch that
+// also draws the next tensor paths, and the bound below which rollout launches
+// keep one workgroup per unit.
 hipError_t gen_configure(PlanDesc* P);
 // defined in plan.cpp
 int segment_count(int groups, int resident_waves);

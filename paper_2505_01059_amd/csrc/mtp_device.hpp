@@ -68,7 +68,7 @@ struct PlanDesc {
   // write the tensor-path controls of iteration gen_k into U2
   float* U2;             // second [T][n][ldU] buffer, or null
   int32_t roll_blocks, gen_k;
-  int32_t gen_grid;      // workgroups of such a launch: one per compute unit
+  int32_t gen_grid;      // compute units: workgroups of such a launch (one per unit)
 };
 
 // ------------------------------------------------------------------ Philox
