@@ -329,7 +329,9 @@ hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
 // values are those of the plain sequence: the tensor paths do not depend on
 // the sampling distribution.
 hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st) {
-  const bool overlap = P.U2 != nullptr;
+  // the plan's layout assumed a 256-unit chip; a device without a free unit
+  // beyond the rollout's workgroups runs the plain sequence
+  const bool overlap = P.U2 != nullptr && P.gen_grid > rollout_blocks(P);
   if (!overlap) return launch_stage(P, stage, k, st);
   PlanDesc Pk = P;
   if ((k1 - 1 - k) & 1) { Pk.U = P.U2; Pk.U2 = P.U; }

@@ -611,7 +611,9 @@ mtp_status mtp_run_stage(mtp_plan* p, int32_t stage, uint32_t replan_idx, int32_
   return MTP_OK;
 }
 
-int32_t mtp_plan_draws_ahead(const mtp_plan* p) { return (p != nullptr && p->lay.overlap) ? 1 : 0; }
+int32_t mtp_plan_draws_ahead(const mtp_plan* p) {
+  return (p != nullptr && p->lay.overlap && p->P.gen_grid > rollout_blocks(p->P)) ? 1 : 0;
+}
 
 mtp_status mtp_set_graph_mode(mtp_plan* p, int32_t use_graph) {
   if (p == nullptr) return MTP_ERR_INVALID_ARG;
