@@ -100,6 +100,16 @@ __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
   return r;
 }
 
+// A device buffer pointer typed in the global address space.  Accesses through
+// it compile to global memory instructions even where the pointer was read from
+// memory (the persistent kernel's descriptor table) and would otherwise be a
+// flat access; flat accesses also count against the LDS wait counter, so every
+// LDS wait that follows one waits for it to reach memory as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+
 constexpr uint32_t kTagZ = 1, kTagI = 2, kTagEps = 3, kTagPerm = 4;
 
 __device__ __forceinline__ uint32_t stream_c3(uint32_t tag, int k) {
@@ -349,6 +359,9 @@ constexpr int kCandAll = 0, kCandTensor = 1, kCandLocal = 2;
 // Every thread of the tile must call this (it synchronises the workgroup).
 __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, int j, int b0, int t_begin,
                                           int t_end, const CandView& sm, int mode = kCandAll) {
+  const auto Ug = gptr(P.U);
+  const auto Zg = gptr(P.Z);
+  const auto Ig = gptr(P.I);
   const int tid = threadIdx.x;
   const int b = b0 + tid;
   const int G1 = P.G - 1;                       // local samples [0, G1)
@@ -364,7 +377,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
   if (tile_has_tensor) {
     if (P.wor) {
       // graph column of joint j, drawn by the path tiles
-      for (int e = tid; e < P.L * P.W; e += kCandThreads) sm.z[e] = P.Z[static_cast<size_t>(e) * P.n + j];
+      for (int e = tid; e < P.L * P.W; e += kCandThreads) sm.z[e] = Zg[static_cast<size_t>(e) * P.n + j];
     } else {
       // draw the graph column of joint j here; the tile holding the first tensor
       // path stores it to Z
@@ -376,7 +389,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
         const Words4 q = philox(idx >> 2, static_cast<uint32_t>(l), r, stream_c3(kTagZ, k), P.key0, P.key1);
         const float z = fmaf(span, u01(word_at(q, idx & 3u)), lo);
         sm.z[e] = z;
-        if (z_writer) P.Z[static_cast<size_t>(e) * P.n + j] = z;
+        if (z_writer) Zg[static_cast<size_t>(e) * P.n + j] = z;
       }
     }
   }
@@ -384,7 +397,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
   if (is_tensor) {
     const int pp = b - G1;
     if (P.wor) {
-      for (int l = 0; l < P.L; ++l) sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + P.I[static_cast<size_t>(l) * P.P + pp]];
+      for (int l = 0; l < P.L; ++l) sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + Ig[static_cast<size_t>(l) * P.P + pp]];
     } else {
       // Alg. 1 indices drawn here; the tiles of joint 0 and the first horizon chunk store I
       const bool i_writer = j == 0 && t_begin == 0;
@@ -397,7 +410,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           if (l < P.L) {
             const uint32_t wi = __umulhi(q.w[c], static_cast<uint32_t>(P.W));
             sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + wi];
-            if (i_writer) P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(wi);
+            if (i_writer) Ig[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(wi);
           }
         }
       }
@@ -409,11 +422,11 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
     const int tn = min(sm.chunk, t_end - t0);
     for (int i = tid; i < tn; i += kCandThreads) {
       const int o = (t0 + i) * P.n + j;
-      sm.ts[i] = P.span[t0 + i];
-      sm.tmu[i] = P.mu[o];
-      sm.tsg[i] = P.sigma[o];
+      sm.ts[i] = gptr(P.span)[t0 + i];
+      sm.tmu[i] = gptr(P.mu)[o];
+      sm.tsg[i] = gptr(P.sigma)[o];
     }
-    for (int i = tid; i < tn * kBasisStride; i += kCandThreads) sm.tb[i] = P.basis[t0 * kBasisStride + i];
+    for (int i = tid; i < tn * kBasisStride; i += kCandThreads) sm.tb[i] = gptr(P.basis)[t0 * kBasisStride + i];
     __syncthreads();
     if (is_local) {
       // local sample g = b: u = clip(mu + sigma * eps), four steps per Philox block
@@ -429,7 +442,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           const int t = 4 * tq + c;
           if (t < t0 + tn) {
             const int i = t - t0;
-            __builtin_nontemporal_store(clampf(fmaf(sm.tsg[i], z[c], sm.tmu[i]), lo, hi), &P.U[(t * P.n + j) * ld + b]);
+            __builtin_nontemporal_store(clampf(fmaf(sm.tsg[i], z[c], sm.tmu[i]), lo, hi), &Ug[(t * P.n + j) * ld + b]);
           }
         }
       }
@@ -443,7 +456,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           v = fmaf(bw[1], sm.ctrl[(s0 + 1) * kCandThreads + tid], v);
           v = fmaf(bw[2], sm.ctrl[(s0 + 2) * kCandThreads + tid], v);
           v = fmaf(bw[3], sm.ctrl[(s0 + 3) * kCandThreads + tid], v);
-          __builtin_nontemporal_store(clampf(v, lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
+          __builtin_nontemporal_store(clampf(v, lo, hi), &Ug[((t0 + i) * P.n + j) * ld + b]);
         }
       } else if (P.interp != kAkima) {
         const int np1 = P.interp == kLinear ? 2 : P.p + 1;
@@ -453,7 +466,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           const float* bw = sm.tb + i * kBasisStride;
           float v = 0.0f;
           for (int q = 0; q < np1; ++q) v = fmaf(bw[q], sm.ctrl[(s0 + q) * kCandThreads + tid], v);
-          __builtin_nontemporal_store(clampf(v, lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
+          __builtin_nontemporal_store(clampf(v, lo, hi), &Ug[((t0 + i) * P.n + j) * ld + b]);
         }
       } else {
 #pragma unroll 4
@@ -464,13 +477,13 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
           v = fmaf(h[1], sm.slope[iv * kCandThreads + tid], v);
           v = fmaf(h[2], sm.ctrl[(iv + 1) * kCandThreads + tid], v);
           v = fmaf(h[3], sm.slope[(iv + 1) * kCandThreads + tid], v);
-          __builtin_nontemporal_store(clampf(v, lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
+          __builtin_nontemporal_store(clampf(v, lo, hi), &Ug[((t0 + i) * P.n + j) * ld + b]);
         }
       }
     } else if (is_nominal) {
       // nominal mean
 #pragma unroll 4
-      for (int i = 0; i < tn; ++i) __builtin_nontemporal_store(clampf(sm.tmu[i], lo, hi), &P.U[((t0 + i) * P.n + j) * ld + b]);
+      for (int i = 0; i < tn; ++i) __builtin_nontemporal_store(clampf(sm.tmu[i], lo, hi), &Ug[((t0 + i) * P.n + j) * ld + b]);
     }
     __syncthreads();
   }
@@ -1621,17 +1634,18 @@ __device__ __forceinline__ void topk_gather(int B, uint32_t lo, Image image, Tak
 // network for very large E.
 template <int BS>
 __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
+  const auto cost = gptr(P.cost);
   const int tid = threadIdx.x;
   const int B = P.B, E = P.E;
   const bool cached = B <= kTopkCache;
-  auto image = [&](int b) -> uint32_t { return cached ? sm.cache[b] : cost_order(P.cost[b]); };
+  auto image = [&](int b) -> uint32_t { return cached ? sm.cache[b] : cost_order(cost[b]); };
 
   // images, their minimum and maximum (four loads in flight per thread)
   uint32_t lo = 0xFFFFFFFFu, hi = 0u;
   for (int b0 = tid; b0 < B; b0 += 4 * BS) {
     float c[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) c[u] = b0 + u * BS < B ? P.cost[b0 + u * BS] : 0.0f;
+    for (int u = 0; u < 4; ++u) c[u] = b0 + u * BS < B ? cost[b0 + u * BS] : 0.0f;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int b = b0 + u * BS;
@@ -1755,15 +1769,15 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   // the unnormalised weights wait in LDS (the image cache is free by now)
   float* wbuf = reinterpret_cast<float*>(sm.cache);
   const uint32_t i0 = static_cast<uint32_t>(ord[0]);
-  const float s0 = P.cost[i0 < static_cast<uint32_t>(B) ? i0 : 0u];
+  const float s0 = cost[i0 < static_cast<uint32_t>(B) ? i0 : 0u];
   const bool uniform = !(P.lam < INFINITY) || !(s0 < INFINITY);
   for (int e = tid; e < E; e += BS) {
     uint32_t uidx = static_cast<uint32_t>(ord[e]);
     if (uidx >= static_cast<uint32_t>(B)) { uidx = 0u; atomicOr(&P.ctrl[2], 2u); }   // never expected
     const int idx = static_cast<int>(uidx);
-    const float ce = P.cost[idx];
-    P.eidx[e] = idx;
-    P.ecost[e] = ce;
+    const float ce = cost[idx];
+    gptr(P.eidx)[e] = idx;
+    gptr(P.ecost)[e] = ce;
     wbuf[e] = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
   }
   // normalisation sum in an order fixed by E alone (independent of the block
@@ -1777,7 +1791,7 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   }
   __syncthreads();
   const float inv = 1.0f / sm.red[0];
-  for (int e = tid; e < E; e += BS) P.w[e] = wbuf[e] * inv;
+  for (int e = tid; e < E; e += BS) gptr(P.w)[e] = wbuf[e] * inv;
   if (tid == 0 && !(s0 < INFINITY)) atomicOr(&P.ctrl[2], 1u);
 }
 
@@ -1840,22 +1854,24 @@ constexpr int kUpdKeep = 16;
 __device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
   const int lane = threadIdx.x & 63;
   const size_t ld = static_cast<size_t>(P.ldU);
-  const float* row = P.U + static_cast<size_t>(o) * ld;
+  const auto row = gptr(P.U) + static_cast<size_t>(o) * ld;
+  const auto eidx = gptr(P.eidx);
+  const auto w = gptr(P.w);
   float keep[kUpdKeep];
   float m = 0.0f;
   if (P.E <= 64 * kUpdKeep) {
 #pragma unroll
     for (int q = 0; q < kUpdKeep; ++q) {
       const int e = lane + 64 * q;
-      keep[q] = e < P.E ? row[P.eidx[e]] : 0.0f;
+      keep[q] = e < P.E ? row[eidx[e]] : 0.0f;
     }
 #pragma unroll
     for (int q = 0; q < kUpdKeep; ++q) {
       const int e = lane + 64 * q;
-      if (e < P.E) m = fmaf(P.w[e], keep[q], m);
+      if (e < P.E) m = fmaf(w[e], keep[q], m);
     }
   } else {
-    for (int e = lane; e < P.E; e += 64) m = fmaf(P.w[e], row[P.eidx[e]], m);
+    for (int e = lane; e < P.E; e += 64) m = fmaf(w[e], row[eidx[e]], m);
   }
   m = wave_sum64(m);
   float v = 0.0f;
@@ -1865,22 +1881,23 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
       const int e = lane + 64 * q;
       if (e < P.E) {
         const float dv = keep[q] - m;
-        v = fmaf(P.w[e], dv * dv, v);
+        v = fmaf(w[e], dv * dv, v);
       }
     }
   } else {
     for (int e = lane; e < P.E; e += 64) {
-      const float dv = row[P.eidx[e]] - m;
-      v = fmaf(P.w[e], dv * dv, v);
+      const float dv = row[eidx[e]] - m;
+      v = fmaf(w[e], dv * dv, v);
     }
   }
   v = wave_sum64(v);
   if (lane == 0) {
     const float sd = fmaxf(sqrtf(v), P.sigma_min);
-    const float mu_old = P.mu[o], sg_old = P.sigma[o];
-    P.mu[o] = fmaf(P.alpha, mu_old - m, m);
-    P.sigma[o] = fmaf(P.alpha, sg_old - sd, sd);
-    if (o < P.n) P.action[o] = row[P.eidx[0]];   // first control of the best candidate
+    const auto mu = gptr(P.mu), sigma = gptr(P.sigma);
+    const float mu_old = mu[o], sg_old = sigma[o];
+    mu[o] = fmaf(P.alpha, mu_old - m, m);
+    sigma[o] = fmaf(P.alpha, sg_old - sd, sd);
+    if (o < P.n) gptr(P.action)[o] = row[eidx[0]];   // first control of the best candidate
   }
 }
 
