@@ -1595,30 +1595,50 @@ __device__ __forceinline__ void topk_rank(const unsigned long long* src, int n, 
   }
 }
 
-// Appends every key (image << 32 | index) for which take(v, key) holds, with
-// v = image - lo, to dst at slots counted by *counter (one bump per wave).
-template <int BS, class Image, class Take>
-__device__ __forceinline__ void topk_gather(int B, uint32_t lo, Image image, Take take, uint32_t* counter,
+// Appends key to dst, at slots counted by *counter (one bump per wave), on the
+// lanes where t holds.  Every lane of the wave must call it.
+__device__ __forceinline__ void wave_append(bool t, unsigned long long key, uint32_t* counter,
+                                            unsigned long long* dst, uint32_t cap) {
+  const unsigned long long m = __ballot(t);
+  if (m == 0ull) return;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int leader = __ffsll(static_cast<long long>(m)) - 1;
+  uint32_t slot0 = 0u;
+  if (lane == leader) slot0 = atomicAdd(counter, static_cast<uint32_t>(__popcll(m)));
+  slot0 = static_cast<uint32_t>(__shfl(static_cast<int>(slot0), leader, 64));
+  const uint32_t slot = slot0 + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+  if (t && slot < cap) dst[slot] = key;
+}
+
+// Appends every key (image << 32 | index) <= limit to dst.
+template <int BS, class Image>
+__device__ __forceinline__ void topk_gather(int B, Image image, unsigned long long limit, uint32_t* counter,
                                             unsigned long long* dst, uint32_t cap) {
   for (int base = 0; base < B; base += BS) {
     const int b = base + static_cast<int>(threadIdx.x);
-    unsigned long long key = 0ull;
-    bool t = false;
+    const unsigned long long key =
+        b < B ? (static_cast<unsigned long long>(image(b)) << 32) | static_cast<uint32_t>(b) : ~0ull;
+    wave_append(b < B && key <= limit, key, counter, dst, cap);
+  }
+}
+
+// One sweep, two lists: the keys whose digits above `shift` (of v = image - lo)
+// are below the boundary bin's, and the keys of the boundary bin itself.
+template <int BS, class Image>
+__device__ __forceinline__ void topk_gather_split(int B, uint32_t lo, Image image, int shift,
+                                                  unsigned long long pd, uint32_t* c_lo, unsigned long long* d_lo,
+                                                  uint32_t cap_lo, uint32_t* c_b, unsigned long long* d_b,
+                                                  uint32_t cap_b) {
+  for (int base = 0; base < B; base += BS) {
+    const int b = base + static_cast<int>(threadIdx.x);
+    unsigned long long key = 0ull, hv = 0ull;
     if (b < B) {
       const uint32_t im = image(b);
       key = (static_cast<unsigned long long>(im) << 32) | static_cast<uint32_t>(b);
-      t = take(im - lo, key);
+      hv = static_cast<unsigned long long>(im - lo) >> shift;
     }
-    const unsigned long long m = __ballot(t);
-    if (m != 0ull) {
-      const int lane = static_cast<int>(threadIdx.x) & 63;
-      const int leader = __ffsll(static_cast<long long>(m)) - 1;
-      uint32_t slot0 = 0u;
-      if (lane == leader) slot0 = atomicAdd(counter, static_cast<uint32_t>(__popcll(m)));
-      slot0 = static_cast<uint32_t>(__shfl(static_cast<int>(slot0), leader, 64));
-      const uint32_t slot = slot0 + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
-      if (t && slot < cap) dst[slot] = key;
-    }
+    wave_append(b < B && hv < pd, key, c_lo, d_lo, cap_lo);
+    wave_append(b < B && hv == pd, key, c_b, d_b, cap_b);
   }
 }
 
@@ -1701,10 +1721,8 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     // With no pass taken (B small) shift = bits, which may be 32: 64-bit shifts.
     const unsigned long long pd = prefix >> shift;
     const uint32_t below = static_cast<uint32_t>(E) - rank;
-    topk_gather<BS>(B, lo, image, [&](uint32_t v, unsigned long long) { return (static_cast<unsigned long long>(v) >> shift) < pd; }, &sm.count,
-                    sm.keys, static_cast<uint32_t>(kMaxElites));
-    topk_gather<BS>(B, lo, image, [&](uint32_t v, unsigned long long) { return (static_cast<unsigned long long>(v) >> shift) == pd; }, &sm.count2,
-                    sm.sorted, static_cast<uint32_t>(kTopkBoundary));
+    topk_gather_split<BS>(B, lo, image, shift, pd, &sm.count, sm.keys, static_cast<uint32_t>(kMaxElites), &sm.count2,
+                          sm.sorted, static_cast<uint32_t>(kTopkBoundary));
     __syncthreads();
     topk_rank<BS>(sm.sorted, static_cast<int>(sel), [&](unsigned long long k, int r) {
       if (static_cast<uint32_t>(r) < rank) sm.keys[below + static_cast<uint32_t>(r)] = k;
@@ -1736,8 +1754,7 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
       }
       limit = (static_cast<unsigned long long>(cstar) << 32) | kp;
     }
-    topk_gather<BS>(B, lo, image, [&](uint32_t, unsigned long long key) { return key <= limit; }, &sm.count,
-                    sm.keys, static_cast<uint32_t>(kMaxElites));
+    topk_gather<BS>(B, image, limit, &sm.count, sm.keys, static_cast<uint32_t>(kMaxElites));
   }
   __syncthreads();
   const unsigned long long* ord;
