@@ -58,6 +58,12 @@ def overlap_mix():
                                n_width=16, n_elites=16, n_iters=3, seed=25),
         W.chain_config(name="o_c3", n_links=3, interp=W.LINEAR, n_tensor=1024, n_gauss=1, horizon=20,
                        n_elites=8, n_iters=2, seed=26),
+        # local samples end exactly on a tile boundary (G - 1 = 256)
+        W.point_mass_config(name="o_pm257", interp=W.AKIMA, n_tensor=1500, n_gauss=257, horizon=36,
+                            n_elites=24, n_iters=3, seed=27),
+        # randomised replicas on the one-lane contact rollout
+        W.chain_contact_config(name="o_k7r2", n_links=7, n_tensor=1100, n_gauss=90, horizon=28, n_layers=5,
+                               n_width=12, n_elites=20, n_iters=2, seed=28, n_replicas=2),
     ]
 
 
