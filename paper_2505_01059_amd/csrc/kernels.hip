@@ -19,21 +19,13 @@ __global__ __launch_bounds__(kCandThreads) void k_paths(PlanDesc P, int k) {
 
 static int cand_chunk(const PlanDesc& P) { return P.tc < kTChunk ? P.tc : kTChunk; }
 
-// Candidate tiles holding local samples (the first ones) and the tile holding
-// the nominal mean (the last candidate).
-__host__ __device__ inline int local_tiles(const PlanDesc& P) { return (P.G - 1 + kCandThreads - 1) / kCandThreads; }
-__host__ __device__ inline int nominal_tile(const PlanDesc& P) { return (P.B - 1) / kCandThreads; }
-
 // grid (candidate tiles, joints, horizon chunks of P.tc steps); LDS sized for
-// the plan so that several workgroups fit on a compute unit.  With mode
-// kCandLocal the grid covers only the local tiles and the nominal tile.
-__global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k, int mode) {
+// the plan so that several workgroups fit on a compute unit
+__global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) {
   extern __shared__ float cand_lds[];
   const CandView v = cand_view_dyn(cand_lds, P.L, P.W, P.tc < kTChunk ? P.tc : kTChunk);
   const int t_begin = blockIdx.z * P.tc;
-  int tile = blockIdx.x;
-  if (mode == kCandLocal && tile >= local_tiles(P)) tile = nominal_tile(P);
-  cand_tile(P, P.ctrl[0], k, blockIdx.y, tile * kCandThreads, t_begin, min(P.T, t_begin + P.tc), v, mode);
+  cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, t_begin, min(P.T, t_begin + P.tc), v);
 }
 
 // Workgroups of a rollout launch beyond P.roll_blocks, each alone on its
@@ -135,6 +127,17 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {
 __global__ __launch_bounds__(kUpdThreads) void k_update(PlanDesc P) {
   const int o = blockIdx.x * (kUpdThreads / 64) + (threadIdx.x >> 6);
   if (o < P.T * P.n) update_output(P, o);
+}
+
+// Refit of iteration k, then, from each refitted (t, j), iteration k_next's
+// local samples and nominal mean into P.U2 (its tensor paths were drawn during
+// iteration k's rollout).
+__global__ __launch_bounds__(kUpdThreads) void k_update_next(PlanDesc P, int k_next) {
+  const int o = blockIdx.x * (kUpdThreads / 64) + (threadIdx.x >> 6);
+  if (o >= P.T * P.n) return;
+  float mn, sn;
+  update_output(P, o, &mn, &sn);
+  local_after_refit(P, P.U2, o, k_next, mn, sn);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -270,18 +273,15 @@ static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) 
   return hipErrorInvalidValue;
 }
 
-static hipError_t launch_candidates(const PlanDesc& P, int k, int mode, hipStream_t st) {
-  if (P.P > 0 && P.wor && mode != kCandLocal) {
+static hipError_t launch_candidates(const PlanDesc& P, int k, hipStream_t st) {
+  if (P.P > 0 && P.wor) {
     k_paths<<<(P.P + kCandThreads - 1) / kCandThreads, kCandThreads, 0, st>>>(P, k);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int all_tiles = (P.B + kCandThreads - 1) / kCandThreads;
-  int tiles = all_tiles;
-  if (mode == kCandLocal) tiles = nominal_tile(P) < local_tiles(P) ? local_tiles(P) : local_tiles(P) + 1;
-  const dim3 grid(tiles, P.n, (P.T + P.tc - 1) / P.tc);
+  const dim3 grid((P.B + kCandThreads - 1) / kCandThreads, P.n, (P.T + P.tc - 1) / P.tc);
   const size_t lds = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, cand_chunk(P)));
-  k_candidates<<<grid, kCandThreads, lds, st>>>(P, k, mode);
+  k_candidates<<<grid, kCandThreads, lds, st>>>(P, k);
   return hipGetLastError();
 }
 
@@ -298,7 +298,7 @@ hipError_t launch_shift(const PlanDesc& P, hipStream_t st) {
 hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
   switch (stage) {
     case 0:
-      return launch_candidates(P, k, kCandAll, st);
+      return launch_candidates(P, k, st);
     case 1:
       return launch_rollout(P, st, -1);
     case 2:
@@ -322,12 +322,12 @@ hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
 
 // Stage `stage` of iteration k within a run of iterations [k0, k1).  With the
 // overlap (P.U2 set) iteration k works on U (k1 - 1 - k even, so the last
-// iteration always ends in U) or U2 (odd); its
-// rollout also draws iteration k+1's tensor-path controls into the other
-// buffer on the compute units the rollout leaves idle, and iteration k+1's
-// candidate stage then adds only the local samples and the nominal mean.  The
-// values are those of the plain sequence: the tensor paths do not depend on
-// the sampling distribution.
+// iteration always ends in U) or U2 (odd); its rollout also draws iteration
+// k+1's tensor-path controls into the other buffer on the compute units the
+// rollout leaves idle, and its refit writes iteration k+1's local samples and
+// nominal mean there from each refitted (t, j), so iteration k+1 launches no
+// candidate kernel.  The values are those of the plain sequence: the tensor
+// paths do not depend on the sampling distribution.
 hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st) {
   // the plan's layout assumed a 256-unit chip; a device without a free unit
   // beyond the rollout's workgroups runs the plain sequence
@@ -336,8 +336,14 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
   PlanDesc Pk = P;
   if ((k1 - 1 - k) & 1) { Pk.U = P.U2; Pk.U2 = P.U; }
   switch (stage) {
-    case 0: return launch_candidates(Pk, k, k > k0 ? kCandLocal : kCandAll, st);
+    case 0: return k > k0 ? hipSuccess : launch_candidates(Pk, k, st);
     case 1: return launch_rollout(Pk, st, k + 1 < k1 ? k + 1 : -1);
+    case 3: {
+      if (k + 1 >= k1) return launch_stage(Pk, stage, k, st);
+      const int outs = Pk.T * Pk.n, per = kUpdThreads / 64;
+      k_update_next<<<(outs + per - 1) / per, kUpdThreads, 0, st>>>(Pk, k + 1);
+      return hipGetLastError();
+    }
     default: return launch_stage(Pk, stage, k, st);
   }
 }

@@ -349,10 +349,9 @@ __device__ __forceinline__ void path_tile(const PlanDesc& P, uint32_t r, int k, 
     if (l < L) P.I[static_cast<size_t>(l) * P.P + pp] = static_cast<uint8_t>(x[l]);
 }
 
-// Which candidates a tile writes: all, only the tensor paths (they do not
-// depend on the sampling distribution, so they can be drawn an iteration
-// ahead), or only the local samples and the nominal mean.
-constexpr int kCandAll = 0, kCandTensor = 1, kCandLocal = 2;
+// Which candidates a tile writes: all, or only the tensor paths (they do not
+// depend on the sampling distribution, so they can be drawn an iteration ahead).
+constexpr int kCandAll = 0, kCandTensor = 1;
 
 // Candidates [b0, b0 + kCandThreads) of joint j over steps [t_begin, t_end)
 // (t_begin a multiple of 4).  Tensor paths read their layer indices from I.
@@ -366,12 +365,12 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
   const int b = b0 + tid;
   const int G1 = P.G - 1;                       // local samples [0, G1)
   const int tens_lo = G1, tens_hi = G1 + P.P;   // tensor paths [G1, G1+P)
-  const bool tile_has_tensor = mode != kCandLocal && (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
+  const bool tile_has_tensor = (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
   const float lo = P.u_min, hi = P.u_max;
   const size_t ld = static_cast<size_t>(P.ldU);
   const bool live = b < P.B;
   const bool is_local = mode != kCandTensor && live && b < G1;
-  const bool is_tensor = mode != kCandLocal && live && b >= tens_lo && b < tens_hi;
+  const bool is_tensor = live && b >= tens_lo && b < tens_hi;
   const bool is_nominal = mode != kCandTensor && live && b >= tens_hi;
 
   if (tile_has_tensor) {
@@ -1812,6 +1811,33 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   if (tid == 0 && !(s0 < INFINITY)) atomicOr(&P.ctrl[2], 1u);
 }
 
+// Iteration k_next's candidates that depend on the refitted distribution, at
+// output o = (t, j): the local samples b < G-1 (the same Philox words and
+// arithmetic as cand_tile: block (j, t / 4) of sample b, word pair by t mod 4)
+// and the nominal mean (candidate B-1), from the mean and std just refitted.
+// One wave; U is iteration k_next's candidate buffer.
+__device__ __forceinline__ void local_after_refit(const PlanDesc& P, float* U, int o, int k_next, float mu_t,
+                                                  float sg_t) {
+  const int lane = threadIdx.x & 63;
+  const int t = o / P.n, j = o - t * P.n;
+  const int Tq = (P.T + 3) >> 2, tq = t >> 2, c = t & 3;
+  const auto Ug = gptr(U);
+  const size_t row = static_cast<size_t>(o) * static_cast<size_t>(P.ldU);
+  const uint32_t r = P.ctrl[0];
+  const float lo = P.u_min, hi = P.u_max;
+  const int G1 = P.G - 1;
+  for (int b = lane; b < G1; b += 64) {
+    const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
+                            stream_c3(kTagEps, k_next), P.key0, P.key1);
+    float z0, z1;
+    if (c < 2) box_muller(q.w[0], q.w[1], z0, z1);
+    else box_muller(q.w[2], q.w[3], z0, z1);
+    const float z = (c & 1) ? z1 : z0;
+    __builtin_nontemporal_store(clampf(fmaf(sg_t, z, mu_t), lo, hi), &Ug[row + b]);
+  }
+  if (lane == 0) __builtin_nontemporal_store(clampf(mu_t, lo, hi), &Ug[row + (P.B - 1)]);
+}
+
 // ------------------------------------------------------------------ cost entropy
 // H = -sum_j P_j log P_j with P_j = exp(J_j) / sum_l exp(J_l) over the finite
 // rollout costs J of one iteration (the exploration diagnostic of Section 5.1),
@@ -1868,7 +1894,9 @@ __device__ __forceinline__ void entropy_block(const PlanDesc& P, int k, EntropyS
 // the second pass would double the line traffic); larger elite sets re-read.
 constexpr int kUpdKeep = 16;
 
-__device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
+// Refits output o = (t, j); every lane returns the new mean and std, lane 0 stores them.
+__device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* mu_new = nullptr,
+                                              float* sg_new = nullptr) {
   const int lane = threadIdx.x & 63;
   const size_t ld = static_cast<size_t>(P.ldU);
   const auto row = gptr(P.U) + static_cast<size_t>(o) * ld;
@@ -1908,12 +1936,16 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o) {
     }
   }
   v = wave_sum64(v);
+  const float sd = fmaxf(sqrtf(v), P.sigma_min);
+  const auto mu = gptr(P.mu), sigma = gptr(P.sigma);
+  const float mu_old = mu[o], sg_old = sigma[o];
+  const float mn = fmaf(P.alpha, mu_old - m, m);
+  const float sn = fmaf(P.alpha, sg_old - sd, sd);
+  if (mu_new) *mu_new = mn;
+  if (sg_new) *sg_new = sn;
   if (lane == 0) {
-    const float sd = fmaxf(sqrtf(v), P.sigma_min);
-    const auto mu = gptr(P.mu), sigma = gptr(P.sigma);
-    const float mu_old = mu[o], sg_old = sigma[o];
-    mu[o] = fmaf(P.alpha, mu_old - m, m);
-    sigma[o] = fmaf(P.alpha, sg_old - sd, sd);
+    mu[o] = mn;
+    sigma[o] = sn;
     if (o < P.n) gptr(P.action)[o] = row[eidx[0]];   // first control of the best candidate
   }
 }
