@@ -129,15 +129,23 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(PlanDesc P) {
   if (o < P.T * P.n) update_output(P, o);
 }
 
-// Refit of iteration k, then, from each refitted (t, j), iteration k_next's
-// local samples and nominal mean into P.U2 (its tensor paths were drawn during
-// iteration k's rollout).
+// Refit of iteration k, one (t, j) output per workgroup, and from it iteration
+// k_next's local samples and nominal mean at (t, j) into P.U2 (its tensor paths
+// were drawn during iteration k's rollout).  Wave 0 refits while every thread
+// draws the normals of its share of the local samples.
 __global__ __launch_bounds__(kUpdThreads) void k_update_next(PlanDesc P, int k_next) {
-  const int o = blockIdx.x * (kUpdThreads / 64) + (threadIdx.x >> 6);
-  if (o >= P.T * P.n) return;
-  float mn, sn;
-  update_output(P, o, &mn, &sn);
-  local_after_refit(P, P.U2, o, k_next, mn, sn);
+  __shared__ float mom[2];
+  const int o = blockIdx.x;
+  const uint32_t r = P.ctrl[0];
+  float z[kLocalKeep];
+  local_normals<kUpdThreads>(P, o, k_next, r, z);
+  if (threadIdx.x < 64) {
+    float mn, sn;
+    update_output(P, o, &mn, &sn);
+    if (threadIdx.x == 0) { mom[0] = mn; mom[1] = sn; }
+  }
+  __syncthreads();
+  local_store<kUpdThreads>(P, P.U2, o, k_next, r, z, mom[0], mom[1]);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -340,8 +348,7 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
     case 1: return launch_rollout(Pk, st, k + 1 < k1 ? k + 1 : -1);
     case 3: {
       if (k + 1 >= k1) return launch_stage(Pk, stage, k, st);
-      const int outs = Pk.T * Pk.n, per = kUpdThreads / 64;
-      k_update_next<<<(outs + per - 1) / per, kUpdThreads, 0, st>>>(Pk, k + 1);
+      k_update_next<<<Pk.T * Pk.n, kUpdThreads, 0, st>>>(Pk, k + 1);
       return hipGetLastError();
     }
     default: return launch_stage(Pk, stage, k, st);

@@ -1815,27 +1815,48 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
 // output o = (t, j): the local samples b < G-1 (the same Philox words and
 // arithmetic as cand_tile: block (j, t / 4) of sample b, word pair by t mod 4)
 // and the nominal mean (candidate B-1), from the mean and std just refitted.
-// One wave; U is iteration k_next's candidate buffer.
-__device__ __forceinline__ void local_after_refit(const PlanDesc& P, float* U, int o, int k_next, float mu_t,
-                                                  float sg_t) {
-  const int lane = threadIdx.x & 63;
+// The normals do not depend on the refit: local_normals draws a thread's share
+// (samples tid, tid + BS, ...; the first kLocalKeep kept in registers) while
+// the refit runs, local_store writes them once the moments are known.
+constexpr int kLocalKeep = 8;
+
+__device__ __forceinline__ float local_normal(const PlanDesc& P, int o, int b, int k_next, uint32_t r) {
   const int t = o / P.n, j = o - t * P.n;
   const int Tq = (P.T + 3) >> 2, tq = t >> 2, c = t & 3;
+  const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
+                          stream_c3(kTagEps, k_next), P.key0, P.key1);
+  float z0, z1;
+  if (c < 2) box_muller(q.w[0], q.w[1], z0, z1);
+  else box_muller(q.w[2], q.w[3], z0, z1);
+  return (c & 1) ? z1 : z0;
+}
+
+template <int BS>
+__device__ __forceinline__ void local_normals(const PlanDesc& P, int o, int k_next, uint32_t r,
+                                              float (&z)[kLocalKeep]) {
+  const int G1 = P.G - 1;
+#pragma unroll
+  for (int i = 0; i < kLocalKeep; ++i) {
+    const int b = static_cast<int>(threadIdx.x) + i * BS;
+    z[i] = b < G1 ? local_normal(P, o, b, k_next, r) : 0.0f;
+  }
+}
+
+template <int BS>
+__device__ __forceinline__ void local_store(const PlanDesc& P, float* U, int o, int k_next, uint32_t r,
+                                            const float (&z)[kLocalKeep], float mu_t, float sg_t) {
   const auto Ug = gptr(U);
   const size_t row = static_cast<size_t>(o) * static_cast<size_t>(P.ldU);
-  const uint32_t r = P.ctrl[0];
   const float lo = P.u_min, hi = P.u_max;
   const int G1 = P.G - 1;
-  for (int b = lane; b < G1; b += 64) {
-    const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
-                            stream_c3(kTagEps, k_next), P.key0, P.key1);
-    float z0, z1;
-    if (c < 2) box_muller(q.w[0], q.w[1], z0, z1);
-    else box_muller(q.w[2], q.w[3], z0, z1);
-    const float z = (c & 1) ? z1 : z0;
-    __builtin_nontemporal_store(clampf(fmaf(sg_t, z, mu_t), lo, hi), &Ug[row + b]);
+#pragma unroll
+  for (int i = 0; i < kLocalKeep; ++i) {
+    const int b = static_cast<int>(threadIdx.x) + i * BS;
+    if (b < G1) __builtin_nontemporal_store(clampf(fmaf(sg_t, z[i], mu_t), lo, hi), &Ug[row + b]);
   }
-  if (lane == 0) __builtin_nontemporal_store(clampf(mu_t, lo, hi), &Ug[row + (P.B - 1)]);
+  for (int b = static_cast<int>(threadIdx.x) + kLocalKeep * BS; b < G1; b += BS)
+    __builtin_nontemporal_store(clampf(fmaf(sg_t, local_normal(P, o, b, k_next, r), mu_t), lo, hi), &Ug[row + b]);
+  if (threadIdx.x == 0) __builtin_nontemporal_store(clampf(mu_t, lo, hi), &Ug[row + (P.B - 1)]);
 }
 
 // ------------------------------------------------------------------ cost entropy
