@@ -330,6 +330,10 @@ int mtp::cand_time_chunk(int B, int T, int n) {
   chunks = std::min<long long>(chunks, std::max(1, T / 4));
   int tc = static_cast<int>((T + chunks - 1) / chunks);
   tc = (tc + 3) & ~3;
+  // long horizons: chunks of at most 64 steps even when the grid is large
+  // (a few per cent faster on the 256-step, 24-link workload than whole horizons)
+  constexpr int kMaxChunk = 64;
+  tc = std::min(tc, kMaxChunk);
   return std::max(tc, 4);
 }
 
