@@ -30,13 +30,13 @@ double work_estimate(const mtp_config& c) {
   return B * c.horizon * per_step * c.n_iters;
 }
 
-uint32_t items_for(const mtp_config& c, int k_begin, int k_end) {
+uint32_t items_for(const mtp_config& c, int k_begin, int k_end, bool cand_split) {
   const int B = c.n_tensor + c.n_gauss;
   const bool quad = is_quad_chain(c.dynamics, c.n_links);
   const bool pair = is_pair_chain(c.dynamics, c.n_links);
   const int Pn = c.n_tensor;
   const uint32_t per_iter = host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhPaths, quad, pair, c.sample_wor != 0) +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhCand, quad, pair, false) +
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhCand, quad, pair, false, cand_split) +
                             host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhRoll, quad, pair, false) + 1u +
                             host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhUpd, quad, pair, false);
   return 1u + per_iter * static_cast<uint32_t>(k_end - k_begin);
@@ -71,7 +71,7 @@ bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string
     }
     L->lays.push_back(compute_layout(cfgs[i]));
     const int k_cap = max_iters_per_launch > 0 ? std::min(max_iters_per_launch, cfgs[i].n_iters) : cfgs[i].n_iters;
-    L->capacity += items_for(cfgs[i], 0, k_cap);
+    L->capacity += items_for(cfgs[i], 0, k_cap, true);   // sized for split candidate items
     L->x0_total += cfgs[i].state_dim;
     L->act_total += cfgs[i].ctrl_dim;
   }
@@ -439,7 +439,21 @@ mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_activ
     c.shift = sh;
     c.x0_off = (d_x0_packed != nullptr && kb == 0) ? x0_offsets[i] : -1;
     b->h_order[a] = i;
-    total += items_for(b->cfgs[i], kb, ke);
+  }
+  // Few active instances leave most workgroups idle while their candidate
+  // tiles run, each tile covering all joints one after another: then every
+  // (tile, joint) becomes an item of its own.  With many instances the tiles
+  // stay whole (n times fewer items through the one queue counter).
+  uint32_t cand_tiles = 0;
+  for (int a = 0; a < n_active; ++a) {
+    const mtp_config& c = b->cfgs[h_active[a]];
+    cand_tiles += static_cast<uint32_t>((c.n_tensor + c.n_gauss + kCandThreads - 1) / kCandThreads);
+  }
+  const uint32_t split = cand_tiles < static_cast<uint32_t>(b->grid) ? 1u : 0u;
+  for (int a = 0; a < n_active; ++a) {
+    const int i = h_active[a];
+    b->h_ictl[i].cand_split = split;
+    total += items_for(b->cfgs[i], h_k_begin[a], h_k_end[a], split != 0);
   }
   if (total > b->lay.capacity) {
     b->err = "step needs more queue items than the batch was sized for";

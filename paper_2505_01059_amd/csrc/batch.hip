@@ -18,11 +18,12 @@
 
 namespace mtp {
 
-__device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phase) {
+__device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phase, uint32_t cand_split) {
   switch (phase) {
     case kPhShift: return 1u;
     case kPhPaths: return (P.P > 0 && P.wor) ? static_cast<uint32_t>((P.P + kCandThreads - 1) / kCandThreads) : 1u;
-    case kPhCand: return static_cast<uint32_t>((P.B + kCandThreads - 1) / kCandThreads);
+    case kPhCand:
+      return static_cast<uint32_t>((P.B + kCandThreads - 1) / kCandThreads) * (cand_split ? static_cast<uint32_t>(P.n) : 1u);
     case kPhRoll: {
       const int per = is_quad_chain(P.dyn, P.n_links)   ? kBatchThreads / 4
                       : is_pair_chain(P.dyn, P.n_links) ? kBatchThreads / 2
@@ -143,7 +144,9 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
     if (sh.abort) break;
     __threadfence();
     const uint32_t inst = __builtin_amdgcn_readfirstlane(sh.item.inst);
-    const uint32_t phase = __builtin_amdgcn_readfirstlane(sh.item.phase);
+    const uint32_t phase_word = __builtin_amdgcn_readfirstlane(sh.item.phase);
+    const uint32_t phase = phase_word & kItemPhaseMask;
+    const uint32_t split = phase_word >> kItemSplitShift;   // the instance's candidate split, carried by its items
     const uint32_t k = __builtin_amdgcn_readfirstlane(sh.item.k);
     const uint32_t tile = __builtin_amdgcn_readfirstlane(sh.item.tile);
     const PlanDesc P = descs[inst];
@@ -153,14 +156,19 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         shift_block<kBatchThreads>(P, static_cast<int>(P.ctrl[1]));
         break;
       case kPhPaths:
-        path_tile(P, P.ctrl[0], static_cast<int>(k), static_cast<int>(tile), static_cast<int>(phase_tiles(P, kPhPaths)),
+        path_tile(P, P.ctrl[0], static_cast<int>(k), static_cast<int>(tile), static_cast<int>(phase_tiles(P, kPhPaths, split)),
                   sm.path);
         break;
       case kPhCand: {
+        // an item is a candidate tile with all its joints, or (split, when few
+        // instances are active) one joint of a tile
         const uint32_t r = P.ctrl[0];
         const CandView v = cand_view(sm.cand);
-        for (int j = 0; j < P.n; ++j) {
-          cand_tile(P, r, static_cast<int>(k), j, static_cast<int>(tile) * kCandThreads, 0, P.T, v);
+        const int ct = split ? static_cast<int>(tile) / P.n : static_cast<int>(tile);
+        const int j0 = split ? static_cast<int>(tile) - ct * P.n : 0;
+        const int j1 = split ? j0 + 1 : P.n;
+        for (int j = j0; j < j1; ++j) {
+          cand_tile(P, r, static_cast<int>(k), j, ct * kCandThreads, 0, P.T, v);
           __syncthreads();
         }
         break;
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
 
     if (tid == 0) {
       sh.publish = 0;
-      const uint32_t nt = phase_tiles(P, phase);
+      const uint32_t nt = phase_tiles(P, phase, split);
       const uint32_t done = atomicAdd(&ictl[inst].done, 1u) + 1u;
       if (done == nt) {
         __threadfence();
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         if (phase == kPhUpd && nk >= ictl[inst].k_end) {
           atomicAdd(&ctl->finished, 1u);
         } else {
-          const uint32_t m = phase_tiles(P, nph);
+          const uint32_t m = phase_tiles(P, nph, split);
           sh.pub_pos = atomicAdd(&ctl->tail, m);
           sh.pub_count = m;
           sh.pub_phase = nph;
@@ -221,7 +229,7 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
       if (p0 + m <= ctl->capacity) {
         for (uint32_t t = tid; t < m; t += kBatchThreads) {
           BatchItem it;
-          it.inst = inst; it.phase = sh.pub_phase; it.k = sh.pub_k; it.tile = t;
+          it.inst = inst; it.phase = sh.pub_phase | (split << kItemSplitShift); it.k = sh.pub_k; it.tile = t;
           queue[p0 + t] = it;
         }
         __threadfence();
@@ -259,7 +267,10 @@ __global__ __launch_bounds__(64) void k_batch_init(const PlanDesc* __restrict__ 
   if (tid == 0) {
     const uint32_t epoch = ctl->epoch + 1u;   // ctl is rewritten by the host-side reset below
     BatchItem it;
-    it.inst = static_cast<uint32_t>(i); it.phase = kPhShift; it.k = ic.k_begin; it.tile = 0u;
+    it.inst = static_cast<uint32_t>(i);
+    it.phase = kPhShift | (ic.cand_split << kItemSplitShift);
+    it.k = ic.k_begin;
+    it.tile = 0u;
     queue[slot] = it;
     ready[slot] = epoch;
   }

@@ -14,8 +14,9 @@ constexpr int kUpdOutputsPerTile = 64;   // refit outputs per queue item
 enum : uint32_t { kPhShift = 0, kPhPaths = 1, kPhCand = 2, kPhRoll = 3, kPhTopk = 4, kPhUpd = 5 };
 
 struct BatchItem {
-  uint32_t inst, phase, k, tile;
+  uint32_t inst, phase, k, tile;   // phase: the stage in the low bits, the candidate split above
 };
+constexpr uint32_t kItemSplitShift = 16, kItemPhaseMask = 0xFFFFu;
 
 struct BatchCtl {
   uint32_t head;       // next queue position to take
@@ -36,7 +37,7 @@ struct InstCtl {
   int32_t shift;       // warm-start shift applied when k_begin == 0
   int32_t x0_off;      // offset of this instance's x0 in the packed input (-1: keep)
   int32_t act_off;     // offset of its action in the packed output
-  int32_t pad;
+  uint32_t cand_split; // 1: one candidate item per (tile, joint), 0: per tile (all joints)
 };
 
 struct BatchLaunch {
@@ -78,11 +79,13 @@ const char* batch_error(const mtp_batch* b);
 hipStream_t batch_stream(const mtp_batch* b);
 
 // host mirror of the per-phase tile counts
-inline uint32_t host_phase_tiles(int B, int P, int T, int n, uint32_t phase, bool quad, bool pair, bool wor) {
+inline uint32_t host_phase_tiles(int B, int P, int T, int n, uint32_t phase, bool quad, bool pair, bool wor,
+                                 bool cand_split = false) {
   switch (phase) {
     case kPhShift: return 1u;
     case kPhPaths: return (P > 0 && wor) ? static_cast<uint32_t>((P + kCandThreads - 1) / kCandThreads) : 1u;
-    case kPhCand: return static_cast<uint32_t>((B + kCandThreads - 1) / kCandThreads);
+    case kPhCand:
+      return static_cast<uint32_t>((B + kCandThreads - 1) / kCandThreads) * (cand_split ? static_cast<uint32_t>(n) : 1u);
     case kPhRoll: {
       const int per = quad ? kBatchThreads / 4 : (pair ? kBatchThreads / 2 : kBatchThreads);
       return static_cast<uint32_t>((B + per - 1) / per);
