@@ -142,7 +142,9 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
     }
     __syncthreads();
     if (sh.abort) break;
-    __threadfence();
+    // acquire: the item's inputs were released by the workgroups that made
+    // them (only an invalidation here, no write-back)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t inst = __builtin_amdgcn_readfirstlane(sh.item.inst);
     const uint32_t phase_word = __builtin_amdgcn_readfirstlane(sh.item.phase);
     const uint32_t phase = phase_word & kItemPhaseMask;
@@ -193,10 +195,13 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         break;
       }
     }
-    __threadfence();
+    // release the item's results: after the barrier (every wave's stores have
+    // reached the L2) one wave writes the L2 back for the other XCDs, instead
+    // of every wave doing it
     __syncthreads();
 
     if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       sh.publish = 0;
       const uint32_t nt = phase_tiles(P, phase, split);
       const uint32_t done = atomicAdd(&ictl[inst].done, 1u) + 1u;
