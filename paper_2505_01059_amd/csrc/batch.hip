@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
       const uint32_t nt = phase_tiles(P, phase, split);
       const uint32_t done = atomicAdd(&ictl[inst].done, 1u) + 1u;
       if (done == nt) {
-        __threadfence();
+        // acquire the other tiles' results (released before their counts)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         atomicExch(&ictl[inst].done, 0u);
         uint32_t nph, nk;
         if (phase == kPhShift) {
@@ -237,9 +238,14 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
           it.inst = inst; it.phase = sh.pub_phase | (split << kItemSplitShift); it.k = sh.pub_k; it.tile = t;
           queue[p0 + t] = it;
         }
-        __threadfence();
-        for (uint32_t t = tid; t < m; t += kBatchThreads)
-          __hip_atomic_store(&ready[p0 + t], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // one release (one L2 write-back) in wave 0, which then sets the ready
+        // flags: the barrier orders every wave's queue entries before it
+        __syncthreads();
+        if (tid < 64) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          for (uint32_t t = tid; t < m; t += 64)
+            __hip_atomic_store(&ready[p0 + t], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       } else if (tid == 0) {
         atomicOr(&ctl->error, 2u);   // queue overflow: items are never published, waiters time out
       }
