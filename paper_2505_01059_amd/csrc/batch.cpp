@@ -38,7 +38,7 @@ uint32_t items_for(const mtp_config& c, int k_begin, int k_end, bool cand_split)
   const uint32_t per_iter = host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhPaths, quad, pair, c.sample_wor != 0) +
                             host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhCand, quad, pair, false, cand_split) +
                             host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhRoll, quad, pair, false) + 1u +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhUpd, quad, pair, false);
+                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhUpd, quad, pair, false, cand_split);
   return 1u + per_iter * static_cast<uint32_t>(k_end - k_begin);
 }
 
@@ -441,9 +441,10 @@ mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_activ
     b->h_order[a] = i;
   }
   // Few active instances leave most workgroups idle while their candidate
-  // tiles run, each tile covering all joints one after another: then every
-  // (tile, joint) becomes an item of its own.  With many instances the tiles
-  // stay whole (n times fewer items through the one queue counter).
+  // tiles run, each tile covering all joints one after another, and while
+  // their refit items run 64 outputs each: then every (tile, joint) and every
+  // four outputs become items of their own.  With many instances the items
+  // stay large (far fewer of them through the one queue counter).
   uint32_t cand_tiles = 0;
   for (int a = 0; a < n_active; ++a) {
     const mtp_config& c = b->cfgs[h_active[a]];

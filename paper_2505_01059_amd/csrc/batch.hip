@@ -31,7 +31,10 @@ __device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phas
       return static_cast<uint32_t>((P.B + per - 1) / per);
     }
     case kPhTopk: return 1u;
-    default: return static_cast<uint32_t>((P.T * P.n + kUpdOutputsPerTile - 1) / kUpdOutputsPerTile);
+    default: {
+      const int per = cand_split ? kUpdOutputsPerTileSplit : kUpdOutputsPerTile;
+      return static_cast<uint32_t>((P.T * P.n + per - 1) / per);
+    }
   }
 }
 
@@ -187,8 +190,9 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         break;
       default: {
         const int wave = tid >> 6;
-        const int base = static_cast<int>(tile) * kUpdOutputsPerTile;
-        for (int m = wave; m < kUpdOutputsPerTile; m += kBatchThreads / 64) {
+        const int per = split ? kUpdOutputsPerTileSplit : kUpdOutputsPerTile;
+        const int base = static_cast<int>(tile) * per;
+        for (int m = wave; m < per; m += kBatchThreads / 64) {
           const int o = base + m;
           if (o < P.T * P.n) update_output(P, o);
         }

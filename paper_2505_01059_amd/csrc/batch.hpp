@@ -10,6 +10,7 @@ namespace mtp {
 
 constexpr int kBatchThreads = 256;       // workgroup of the persistent kernel
 constexpr int kUpdOutputsPerTile = 64;   // refit outputs per queue item
+constexpr int kUpdOutputsPerTileSplit = kBatchThreads / 64;   // ... with split items: one per wave
 
 enum : uint32_t { kPhShift = 0, kPhPaths = 1, kPhCand = 2, kPhRoll = 3, kPhTopk = 4, kPhUpd = 5 };
 
@@ -37,7 +38,7 @@ struct InstCtl {
   int32_t shift;       // warm-start shift applied when k_begin == 0
   int32_t x0_off;      // offset of this instance's x0 in the packed input (-1: keep)
   int32_t act_off;     // offset of its action in the packed output
-  uint32_t cand_split; // 1: one candidate item per (tile, joint), 0: per tile (all joints)
+  uint32_t cand_split; // 1: small items (candidates per (tile, joint), refit per 4 outputs), 0: large
 };
 
 struct BatchLaunch {
@@ -91,7 +92,10 @@ inline uint32_t host_phase_tiles(int B, int P, int T, int n, uint32_t phase, boo
       return static_cast<uint32_t>((B + per - 1) / per);
     }
     case kPhTopk: return 1u;
-    default: return static_cast<uint32_t>((T * n + kUpdOutputsPerTile - 1) / kUpdOutputsPerTile);
+    default: {
+      const int per = cand_split ? kUpdOutputsPerTileSplit : kUpdOutputsPerTile;
+      return static_cast<uint32_t>((T * n + per - 1) / per);
+    }
   }
 }
 
