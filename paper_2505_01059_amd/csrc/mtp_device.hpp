@@ -797,10 +797,13 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
   for (int k = 0; k < N; ++k) u[k] = ub[k * ld];
   float cost = 0.0f;
   for (int t = 0; t < P.T; ++t) {
+    // next step's controls, loaded a whole step ahead; the last step re-reads
+    // its own row (no select on the loaded values, which would make the wave
+    // wait for the loads at once)
     float un[N];
-    const bool more = (t + 1 < P.T);
+    const int tn = (t + 1 < P.T) ? t + 1 : t;
 #pragma unroll
-    for (int k = 0; k < N; ++k) un[k] = more ? ub[((t + 1) * N + k) * ld] : 0.0f;
+    for (int k = 0; k < N; ++k) un[k] = ub[(tn * N + k) * ld];
 
     // classical RK4 with the control held: stage s evaluates at
     // phi_s = phi + c_s dt omega_{s-1},  omega_s = omega + c_s dt k_{s-1}
@@ -1282,10 +1285,13 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
 #pragma unroll
   for (int i = 0; i < M; ++i) u[i] = ub[(t0 * N + pair_link<N>(B, i)) * ld];
   for (int t = t0; t < t1; ++t) {
+    // next step's controls, loaded a whole step ahead; the last step re-reads
+    // its own row (no select on the loaded values, which would make the wave
+    // wait for the loads at once)
     float un[M];
-    const bool more = (t + 1 < t1);
+    const int tn = (t + 1 < t1) ? t + 1 : t;
 #pragma unroll
-    for (int i = 0; i < M; ++i) un[i] = more ? ub[((t + 1) * N + pair_link<N>(B, i)) * ld] : 0.0f;
+    for (int i = 0; i < M; ++i) un[i] = ub[(tn * N + pair_link<N>(B, i)) * ld];
     // torque terms (u_k - u_{k+1}) / l_k: the distal neighbour is local i+1 in lane A
     // (the other lane's link at the middle) and local i-1 in lane B (none at the tip)
     float q[M];
