@@ -212,7 +212,7 @@ mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
 
 /* 1 if the plan draws each next CEM iteration's tensor-path controls during the
  * current iteration's rollout, else 0 (decided at creation from the config: more
- * than one iteration, paths with replacement, at least 1024 of them, and a
+ * than one iteration, tensor paths drawn with replacement, and a
  * rollout grid that leaves at least 32 of the 256 compute units free; on a
  * device with fewer units than that the plan runs the plain sequence).  Such a
  * plan's workspace holds a second [T][n][ldU] candidate buffer; the U buffer of

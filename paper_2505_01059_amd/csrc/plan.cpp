@@ -283,7 +283,7 @@ void mtp::set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8
 bool mtp::uses_gen_overlap(const mtp_config& c) {
   constexpr long long kUnits = 256;     // compute units
   constexpr long long kMinFree = 32;    // units left for drawing the next tensor paths
-  if (c.n_iters < 2 || c.sample_wor || c.n_tensor < 1024 || uses_segmented_rollout(c)) return false;
+  if (c.n_iters < 2 || c.sample_wor || c.n_tensor < 1 || uses_segmented_rollout(c)) return false;
   const long long B = static_cast<long long>(c.n_tensor) + c.n_gauss;
   const bool chain = c.dynamics == MTP_DYN_CHAIN || c.dynamics == MTP_DYN_CHAIN_CONTACT;
   const bool quad = c.dynamics == MTP_DYN_CHAIN && c.n_links >= 5 && c.n_links <= 8;

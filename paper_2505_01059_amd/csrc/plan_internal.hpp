@@ -43,7 +43,7 @@ void set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* t
 // the chip has SIMDs.
 bool uses_segmented_rollout(const mtp_config& c);
 // Whether a single plan draws the next iteration's tensor-path controls during
-// each rollout: more than one iteration, with-replacement paths (at least 1024),
+// each rollout: more than one iteration, with-replacement tensor paths,
 // no time slicing, and a rollout that leaves at least 32 of the 256 compute
 // units free.
 bool uses_gen_overlap(const mtp_config& c);
