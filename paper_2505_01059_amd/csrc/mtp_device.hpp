@@ -143,6 +143,18 @@ __device__ __forceinline__ void hw_sincos(float x, float* s, float* c) {
   *c = __builtin_amdgcn_cosf(rev);
 }
 
+// sin and cos of an angle given in revolutions, with no reduction: for the
+// rollouts that keep their angles reduced, whose arguments stay within a few
+// revolutions of [0, 1), well inside the instructions' input domain.
+__device__ __forceinline__ void rev_sincos(float rev, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(rev);
+  *c = __builtin_amdgcn_cosf(rev);
+}
+
+constexpr float kTwoPi = 6.283185307179586f;
+constexpr float kInvTwoPi = 0.15915494309189535f;
+constexpr float kTwoPiSq = 39.47841760435743f;
+
 // ------------------------------------------------------------------ candidates
 // Tile = joint j, candidates [b0, b0 + kCandThreads).  Writes U[t][j][b] for
 // every candidate of the tile: local Gaussian samples (noise stream tag 3),
@@ -905,6 +917,8 @@ __host__ __device__ constexpr bool is_quad_chain(int dyn, int n) { return dyn ==
 // acceleration with the same instructions as real rows.
 struct QuadChain {
   float l0, l1, invl0, invl1;   // own links r0 = 2s, r1 = 2s+1 (padded: 1)
+  float cw0, cw1;               // (2 pi)^2 l: centripetal weight of a rate in rev/s
+  float ra0, ra1;               // 1 / (2 pi l): accelerations out in rev/s^2
   float De, Do;                 // diagonals of rows r0, r1 (padded: 1)
   float imD0, imD1;             // im[r0] + im[r0-1], im[r1] + im[r0] (padded: 0)
   float imU0;                   // im[r0]: coupling r0 - r1 (0 unless r1 exists)
@@ -919,7 +933,8 @@ __device__ __forceinline__ float qmul(float a, float b) { return qperm<CTRL>(a) 
 
 // Accelerations of the lane's two links from the stage angles' sin/cos, the
 // stage angular velocities and the per-step torque terms
-// q0, q1 (own links), qp (link r0-1), qn (link r1+1).
+// q0, q1 (own links), qp (link r0-1), qn (link r1+1).  Rates come in and
+// accelerations go out in revolutions (per second, per second squared).
 __device__ __forceinline__ void quad_accel(float s0, float c0, float s1, float c1, float w0, float w1, float q0,
                                            float q1, float qp, float qn, const QuadChain& K, float& a0, float& a1) {
   const float sN = qperm<kQNext1>(s0), cN = qperm<kQNext1>(c0);
@@ -930,9 +945,9 @@ __device__ __forceinline__ void quad_accel(float s0, float c0, float s1, float c
   const float Cp = qperm<kQPrev1>(Cn1), Sp = qperm<kQPrev1>(Sn1);   // links r0-1, r0
   // tension rows r0 (even) and r1 (odd): Lo x_{r-1} + D x_r + Up x_{r+1} = R
   const float Ue = -K.imU0 * Cn0, Le = -K.impV * Cp;
-  const float Re = fmaf(K.l0 * w0, w0, fmaf(-K.imU0 * q1, Sn0, fmaf(K.impV * qp, Sp, K.g0 * c0)));
+  const float Re = fmaf(K.cw0 * w0, w0, fmaf(-K.imU0 * q1, Sn0, fmaf(K.impV * qp, Sp, K.g0 * c0)));
   const float Uo = -K.imU1 * Cn1, Lo = Ue;
-  const float Ro = fmaf(K.l1 * w1, w1, fmaf(-K.imU1 * qn, Sn1, K.imU0 * q0 * Sn0));
+  const float Ro = fmaf(K.cw1 * w1, w1, fmaf(-K.imU1 * qn, Sn1, K.imU0 * q0 * Sn0));
   // eliminate the even unknowns from the odd rows
   const float iDe = __builtin_amdgcn_rcpf(K.De);
   const float al = Lo * iDe;
@@ -972,8 +987,8 @@ __device__ __forceinline__ void quad_accel(float s0, float c0, float s1, float c
   float A1 = K.imD1 * q1;
   A1 = fmaf(-K.imU1, fmaf(xe_next, Sn1, qn * Cn1), A1);
   A1 = fmaf(-K.imU0, fmaf(-xe, Sn0, q0 * Cn0), A1);
-  a0 = A0 * K.invl0;
-  a1 = A1 * K.invl1;
+  a0 = A0 * K.ra0;
+  a1 = A1 * K.ra1;
 }
 
 // One candidate b per quad; s is the lane within the quad.  All four lanes of a
@@ -994,6 +1009,10 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
   K.l1 = v1 ? tk[5 + N + r1] : 1.0f;
   K.invl0 = 1.0f / K.l0;
   K.invl1 = 1.0f / K.l1;
+  K.cw0 = kTwoPiSq * K.l0;
+  K.cw1 = kTwoPiSq * K.l1;
+  K.ra0 = kInvTwoPi * K.invl0;
+  K.ra1 = kInvTwoPi * K.invl1;
   K.De = v0 ? im0 + imp : 1.0f;
   K.Do = v1 ? im1 + im0 : 1.0f;
   K.imD0 = v0 ? im0 + imp : 0.0f;
@@ -1006,11 +1025,19 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
   K.v1f = v1 ? 1.0f : 0.0f;
   K.nxt1f = nxt1 ? 1.0f : 0.0f;
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
-  float ph0 = v0 ? P.x0[r0] : 0.0f, ph1 = v1 ? P.x0[r1] : 0.0f;
-  float om0 = v0 ? P.x0[N + r0] : 0.0f, om1 = v1 ? P.x0[N + r1] : 0.0f;
+  // Angles and rates are carried in revolutions (per second): v_sin / v_cos
+  // take revolutions, so a stage angle goes to them as it is.  The own angles
+  // are kept reduced to [0, 1) (once per step), which holds every stage
+  // argument within a step's motion of that range; the whole turns taken off
+  // are only tracked for the state output.
+  float ph0 = v0 ? kInvTwoPi * P.x0[r0] : 0.0f, ph1 = v1 ? kInvTwoPi * P.x0[r1] : 0.0f;
+  float om0 = v0 ? kInvTwoPi * P.x0[N + r0] : 0.0f, om1 = v1 ? kInvTwoPi * P.x0[N + r1] : 0.0f;
+  float turn0 = floorf(ph0), turn1 = floorf(ph1);
+  ph0 -= turn0;
+  ph1 -= turn1;
   float s0, c0, s1, c1;
-  hw_sincos(ph0, &s0, &c0);
-  hw_sincos(ph1, &s1, &c1);
+  rev_sincos(ph0, &s0, &c0);
+  rev_sincos(ph1, &s1, &c1);
   // controls of padded rows are read from the last real row and zeroed by v0f/v1f
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* p0 = P.U + b + static_cast<size_t>(v0 ? r0 : N - 1) * ld;
@@ -1033,28 +1060,31 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     float k0, k1;
     quad_accel(s0, c0, s1, c1, om0, om1, q0, q1, qp, qn, K, k0, k1);
     float aph0 = om0, aph1 = om1, aom0 = k0, aom1 = k1, oms0 = om0, oms1 = om1;
-#pragma unroll 1
-    for (int stage = 1; stage < 4; ++stage) {
-      const float h = (stage == 3) ? dt : hdt;
+    // one RK4 stage at offset h with weight wgt; the two half-step stages share
+    // a loop body and the full step follows with its constants in place
+    auto stage = [&](float h, float wgt) {
       float ss0, cc0, ss1, cc1;
-      hw_sincos(fmaf(h, oms0, ph0), &ss0, &cc0);
-      hw_sincos(fmaf(h, oms1, ph1), &ss1, &cc1);
+      rev_sincos(fmaf(h, oms0, ph0), &ss0, &cc0);
+      rev_sincos(fmaf(h, oms1, ph1), &ss1, &cc1);
       oms0 = fmaf(h, k0, om0);
       oms1 = fmaf(h, k1, om1);
       quad_accel(ss0, cc0, ss1, cc1, oms0, oms1, q0, q1, qp, qn, K, k0, k1);
-      const float wgt = (stage == 3) ? 1.0f : 2.0f;
       aph0 = fmaf(wgt, oms0, aph0);
       aph1 = fmaf(wgt, oms1, aph1);
       aom0 = fmaf(wgt, k0, aom0);
       aom1 = fmaf(wgt, k1, aom1);
-    }
+    };
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) stage(hdt, 2.0f);
+    stage(dt, 1.0f);
     // padded rows have zero velocity and acceleration, so their angle stays 0
-    ph0 = fmaf(dt6, aph0, ph0);
+    const float pu0 = fmaf(dt6, aph0, ph0), pu1 = fmaf(dt6, aph1, ph1);
+    ph0 = __builtin_amdgcn_fractf(pu0);
+    ph1 = __builtin_amdgcn_fractf(pu1);
     om0 = fmaf(dt6, aom0, om0);
-    ph1 = fmaf(dt6, aph1, ph1);
     om1 = fmaf(dt6, aom1, om1);
-    hw_sincos(ph0, &s0, &c0);
-    hw_sincos(ph1, &s1, &c1);
+    rev_sincos(ph0, &s0, &c0);
+    rev_sincos(ph1, &s1, &c1);
     const float l0v = K.v0f * K.l0, l1v = K.v1f * K.l1;
     float ex = fmaf(l0v, s0, l1v * s1);
     float ey = -fmaf(l0v, c0, l1v * c1);
@@ -1067,8 +1097,10 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     if (b < P.n_dbg) {
       float* X = P.X + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
-      if (v0) { X[(t * 2 * N + r0) * ldx] = ph0; X[(t * 2 * N + N + r0) * ldx] = om0; }
-      if (v1) { X[(t * 2 * N + r1) * ldx] = ph1; X[(t * 2 * N + N + r1) * ldx] = om1; }
+      turn0 += floorf(pu0);
+      turn1 += floorf(pu1);
+      if (v0) { X[(t * 2 * N + r0) * ldx] = kTwoPi * (turn0 + ph0); X[(t * 2 * N + N + r0) * ldx] = kTwoPi * om0; }
+      if (v1) { X[(t * 2 * N + r1) * ldx] = kTwoPi * (turn1 + ph1); X[(t * 2 * N + N + r1) * ldx] = kTwoPi * om1; }
     }
     u0 = un0;
     u1 = un1;

@@ -182,6 +182,45 @@ def test_rollout_stage(name, torch_mod):
     plan.close()
 
 
+SPIN_NAMES = ["chain7_akima", "chain2", "deg_chain3_linear", "chain12", "chain24"]
+
+
+@pytest.mark.parametrize("name", SPIN_NAMES)
+def test_rollout_spinning_start(name, torch_mod):
+    """Rollout from angles of many turns either way and fast rates: the chain
+    rollouts keep their angles reduced to one turn internally, and the state
+    output must still give the unreduced angles."""
+    cfg = CONFIGS[name].replace(horizon=16)
+    _log(f"[rollout spin] {name}")
+    nd = min(8, cfg.n_samples)
+    plan = make_plan(cfg, n_debug_states=nd)
+    mu, sg = random_state(cfg, 5)
+    _, _, U_ref = OP.candidates(cfg, mu.astype(np.float64), sg.astype(np.float64), 1, 0)
+    U32 = U_ref.astype(np.float32).astype(np.float64)
+    b = plan.buffers()
+    H.write_U(b, U32)
+    n = cfg.n_links
+    rng = np.random.default_rng(11)
+    phi = rng.uniform(-40.0, 40.0, size=n)
+    phi[0] = -0.0
+    phi[-1] = 2.0 * np.pi
+    om = rng.uniform(-12.0, 12.0, size=n)
+    x0 = np.concatenate([phi, om]).astype(np.float32)
+    plan.set_x0(x0)
+    plan.run_stage(1, 1, 0)
+    torch_mod.cuda.synchronize()
+    s = b["cost"].cpu().numpy()
+    s_ref, X_ref = OP.rollout(cfg, x0, U32, keep_states=True)
+    flagged = H.switching_flags(cfg, x0, U32)
+    H.assert_costs(cfg, s, s_ref, flagged)
+    X = b["X"].cpu().numpy().transpose(2, 0, 1).astype(np.float64)
+    Xr = X_ref[:nd]
+    okx = np.abs(X - Xr) <= 1e-4 * np.maximum(1.0, np.abs(Xr))
+    assert okx.all(), f"state trajectory mismatch, max {np.max(np.abs(X - Xr))}"
+    _log(f"  max |dX| {np.max(np.abs(X - Xr)):.3e}, |phi| up to {np.max(np.abs(Xr[..., :n])):.1f}")
+    plan.close()
+
+
 def test_topk_stage_exact_with_ties(torch_mod):
     import torch
     cfg = W.point_mass_config(n_tensor=5000, n_gauss=1000, n_elites=300)
