@@ -61,7 +61,7 @@ struct PlanDesc {
   // time-sliced pair-lane rollout (long chains, launches of more waves than SIMDs); null when unused
   struct SegCtl* seg_ctl;
   uint32_t* seg_done;    // [groups] segments completed, tagged with the launch epoch
-  float* seg_state;      // [(n + 1)][groups][64] angles, rates and cost between segments
+  float* seg_state;      // [(3n/2 + 1)][groups][64] angles, rates, cost and turns between segments
   int32_t seg_S, seg_len, seg_grid;
   // rollout launches that also draw the next iteration's tensor-path controls
   // (see gen_tensor_tiles): the first roll_blocks workgroups roll out, the rest
@@ -1168,12 +1168,6 @@ __device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N>& 
   for (int i = 0; i <= M; ++i) K.im[i] = (i == 0 && !K.B) ? 0.0f : 1.0f / m[pair_node_mass<N>(K.B, i)];
 }
 
-// sin and cos of phi + half revolution
-__device__ __forceinline__ void hw_sincos_off(float x, float half, float* s, float* c) {
-  const float rev = __builtin_amdgcn_fractf(fmaf(x, 0.15915494309189535f, half));
-  *s = __builtin_amdgcn_sinf(rev);
-  *c = __builtin_amdgcn_cosf(rev);
-}
 
 // Local-frame accelerations of the lane's M links from the local sin/cos, the
 // angular velocities and the per-step torque terms q (q_o: the other lane's
@@ -1298,19 +1292,26 @@ __device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts
   }
 }
 
-// Steps [t0, t1) of candidate b from the physical angles ph and rates om of the
-// lane's links (updated in place), adding each step's cost to `cost`.
+// Steps [t0, t1) of candidate b from the lane's link angles ph and rates om
+// (updated in place), adding each step's cost to `cost`.  Angles are carried
+// in revolutions of the lane's local frame (lane B's are offset by half a
+// turn) and reduced to [0, 1) after every step, so a stage angle goes to
+// v_sin / v_cos as it is; rates stay in rad/s, and the stage offsets h / 2pi
+// are uniform.  `turn` holds the whole turns taken off, kept up to date only
+// for recorded candidates (the state output gives physical radians).
 template <int N, bool CONTACT>
 __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N>& K, int b, float (&ph)[N / 2],
-                                           float (&om)[N / 2], float& cost, int t0, int t1, bool record) {
+                                           float (&om)[N / 2], float (&turn)[N / 2], float& cost, int t0, int t1,
+                                           bool record) {
   constexpr int M = N / 2;
   const bool B = K.B;
   const float* tk = P.task;
   const float wg = tk[1], wu = tk[2], tgx = tk[3], tgy = tk[4];
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
+  const float dtr = kInvTwoPi * dt, hdtr = kInvTwoPi * hdt, dt6r = kInvTwoPi * dt6;
   float s[M], c[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) hw_sincos_off(ph[i], K.half, &s[i], &c[i]);
+  for (int i = 0; i < M; ++i) rev_sincos(ph[i], &s[i], &c[i]);
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* ub = P.U + b;
   float u[M];
@@ -1346,10 +1347,11 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
 #pragma unroll 1
     for (int stage = 1; stage < 4; ++stage) {
       const float h = (stage == 3) ? dt : hdt;
+      const float hr = (stage == 3) ? dtr : hdtr;
       float s2[M], c2[M];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        hw_sincos_off(fmaf(h, oms[i], ph[i]), K.half, &s2[i], &c2[i]);
+        rev_sincos(fmaf(hr, oms[i], ph[i]), &s2[i], &c2[i]);
         oms[i] = fmaf(h, kk[i], om[i]);
       }
       pair_accel<N, CONTACT>(s2, c2, oms, q, q_o, K, kk);
@@ -1361,11 +1363,13 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
       }
     }
     float ex = 0.0f, ey = 0.0f, uu = 0.0f;
+    float pu[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      ph[i] = fmaf(dt6, aph[i], ph[i]);
+      pu[i] = fmaf(dt6r, aph[i], ph[i]);
+      ph[i] = __builtin_amdgcn_fractf(pu[i]);
       om[i] = fmaf(dt6, aom[i], om[i]);
-      hw_sincos_off(ph[i], K.half, &s[i], &c[i]);
+      rev_sincos(ph[i], &s[i], &c[i]);
       ex = fmaf(K.l[i], s[i], ex);
       ey = fmaf(-K.l[i], c[i], ey);
       uu = fmaf(u[i], u[i], uu);
@@ -1384,7 +1388,8 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         const int k = pair_link<N>(B, i);
-        X[(t * 2 * N + k) * ldx] = ph[i];
+        turn[i] += floorf(pu[i]);
+        X[(t * 2 * N + k) * ldx] = kTwoPi * ((turn[i] + ph[i]) - K.half);
         X[(t * 2 * N + N + k) * ldx] = om[i];
       }
     }
@@ -1393,12 +1398,17 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
   }
 }
 
+// Start state of the lane's links: angles in revolutions of the local frame,
+// reduced to [0, 1), with the whole turns taken off; rates in rad/s.
 template <int N>
-__device__ __forceinline__ void pair_start(const PlanDesc& P, bool B, float (&ph)[N / 2], float (&om)[N / 2]) {
+__device__ __forceinline__ void pair_start(const PlanDesc& P, const PairConsts<N>& K, float (&ph)[N / 2],
+                                           float (&om)[N / 2], float (&turn)[N / 2]) {
 #pragma unroll
   for (int i = 0; i < N / 2; ++i) {
-    const int k = pair_link<N>(B, i);
-    ph[i] = P.x0[k];
+    const int k = pair_link<N>(K.B, i);
+    const float r = fmaf(P.x0[k], kInvTwoPi, K.half);
+    turn[i] = floorf(r);
+    ph[i] = r - turn[i];
     om[i] = P.x0[N + k];
   }
 }
@@ -1421,10 +1431,10 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
       pair_load_masses<N>(sp, K);
       K.muf = sp[N];
     }
-    float ph[M], om[M];
-    pair_start<N>(P, B, ph, om);
+    float ph[M], om[M], turn[M];
+    pair_start<N>(P, K, ph, om, turn);
     float cost = 0.0f;
-    pair_steps<N, CONTACT>(P, K, b, ph, om, cost, 0, P.T, rep == 0);
+    pair_steps<N, CONTACT>(P, K, b, ph, om, turn, cost, 0, P.T, rep == 0);
     total += cost;
   }
   if (!B) P.cost[b] = finite_or_inf(R == 1 ? total : total / static_cast<float>(R));
@@ -1449,8 +1459,9 @@ struct SegCtl {
 
 __device__ __forceinline__ uint32_t seg_tag(uint32_t epoch, int done) { return (epoch << 8) | static_cast<uint32_t>(done); }
 
-// One wave: lanes 2c, 2c+1 hold candidate g*32 + c.  `state` holds (2M + 1)
-// floats per lane per group, laid out [k][group][lane].
+// One wave: lanes 2c, 2c+1 hold candidate g*32 + c.  `state` holds 3M + 1
+// floats per lane per group, laid out [k][group][lane]: angles, rates, cost so
+// far, and the whole turns of recorded candidates.
 template <int N, bool CONTACT>
 __device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl* ctl, uint32_t* done, float* state,
                                                        int S, int seg_len, uint64_t wait_ticks) {
@@ -1495,28 +1506,32 @@ __device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl
       pair_load_masses<N>(sp, K);
       K.muf = sp[N];
     }
-    float ph[M], om[M], cost;
+    float ph[M], om[M], turn[M], cost;
     const size_t gl = static_cast<size_t>(g) * 64 + static_cast<size_t>(lane);
     const size_t kstride = static_cast<size_t>(groups) * 64;
+    // the whole turns travel between segments only where states are recorded
+    const bool rec = live && b < P.n_dbg;
     if (seg == 0) {
-      pair_start<N>(P, B, ph, om);
+      pair_start<N>(P, K, ph, om, turn);
       cost = 0.0f;
     } else {
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         ph[i] = state[i * kstride + gl];
         om[i] = state[(M + i) * kstride + gl];
+        turn[i] = rec ? state[(2 * M + 1 + i) * kstride + gl] : 0.0f;
       }
       cost = state[2 * M * kstride + gl];
     }
     const int t0 = seg * seg_len;
     const int t1 = min(P.T, t0 + seg_len);
-    pair_steps<N, CONTACT>(P, K, b, ph, om, cost, t0, t1, live);
+    pair_steps<N, CONTACT>(P, K, b, ph, om, turn, cost, t0, t1, live);
     if (seg + 1 < S) {
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         state[i * kstride + gl] = ph[i];
         state[(M + i) * kstride + gl] = om[i];
+        if (rec) state[(2 * M + 1 + i) * kstride + gl] = turn[i];
       }
       state[2 * M * kstride + gl] = cost;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
