@@ -135,14 +135,6 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
 
-// sin and cos of an angle in radians on the hardware transcendental unit: the
-// angle is turned into revolutions, reduced to [0, 1) and fed to v_sin / v_cos.
-__device__ __forceinline__ void hw_sincos(float x, float* s, float* c) {
-  const float rev = __builtin_amdgcn_fractf(x * 0.15915494309189535f);
-  *s = __builtin_amdgcn_sinf(rev);
-  *c = __builtin_amdgcn_cosf(rev);
-}
-
 // sin and cos of an angle given in revolutions, with no reduction: for the
 // rollouts that keep their angles reduced, whose arguments stay within a few
 // revolutions of [0, 1), well inside the instructions' input domain.
@@ -784,6 +776,7 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
   }
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
+  const float dtr = kInvTwoPi * dt, hdtr = kInvTwoPi * hdt, dt6r = kInvTwoPi * dt6;
   // randomised models: the candidate's cost is the mean over R rollouts
   const int R = CONTACT ? P.R : 1;
   float total = 0.0f;
@@ -795,12 +788,18 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     for (int k = 0; k < N; ++k) K.im[k] = 1.0f / sp[k];
     K.muf = sp[N];
   }
-  float ph[N], om[N], s[N], c[N];
+  // Angles are carried in revolutions, reduced to [0, 1) after every step, so a
+  // stage angle goes to v_sin / v_cos as it is; rates stay in rad/s and the
+  // stage offsets h / 2pi are uniform.  The whole turns taken off are kept up
+  // to date only for recorded candidates (the state output gives radians).
+  float ph[N], om[N], turn[N], s[N], c[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    ph[k] = P.x0[k];
+    const float r = kInvTwoPi * P.x0[k];
+    turn[k] = floorf(r);
+    ph[k] = r - turn[k];
     om[k] = P.x0[N + k];
-    hw_sincos(ph[k], &s[k], &c[k]);
+    rev_sincos(ph[k], &s[k], &c[k]);
   }
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* ub = P.U + b;
@@ -830,10 +829,11 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
 #pragma unroll 1
     for (int stage = 1; stage < 4; ++stage) {
       const float h = (stage == 3) ? dt : hdt;
+      const float hr = (stage == 3) ? dtr : hdtr;
       float s2[N], c2[N];
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        hw_sincos(fmaf(h, oms[k], ph[k]), &s2[k], &c2[k]);
+        rev_sincos(fmaf(hr, oms[k], ph[k]), &s2[k], &c2[k]);
         oms[k] = fmaf(h, kk[k], om[k]);
       }
       chain_accel<N, CONTACT>(s2, c2, oms, u, K, kk);
@@ -844,16 +844,18 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
         aom[k] = fmaf(wgt, kk[k], aom[k]);
       }
     }
+    float pu[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      ph[k] = fmaf(dt6, aph[k], ph[k]);
+      pu[k] = fmaf(dt6r, aph[k], ph[k]);
+      ph[k] = __builtin_amdgcn_fractf(pu[k]);
       om[k] = fmaf(dt6, aom[k], om[k]);
     }
     // cost of the new state (its sin/cos also start the next step)
     float ex = 0.0f, ey = 0.0f, uu = 0.0f;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      hw_sincos(ph[k], &s[k], &c[k]);
+      rev_sincos(ph[k], &s[k], &c[k]);
       ex = fmaf(K.l[k], s[k], ex);
       ey = fmaf(-K.l[k], c[k], ey);
       uu = fmaf(u[k], u[k], uu);
@@ -865,7 +867,8 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
       const size_t ldx = static_cast<size_t>(P.n_dbg);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        X[(t * 2 * N + k) * ldx] = ph[k];
+        turn[k] += floorf(pu[k]);
+        X[(t * 2 * N + k) * ldx] = kTwoPi * (turn[k] + ph[k]);
         X[(t * 2 * N + N + k) * ldx] = om[k];
       }
     }
