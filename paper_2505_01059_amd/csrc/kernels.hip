@@ -68,7 +68,14 @@ __device__ __forceinline__ int xcd_contiguous_block(int g, int G) {
   return x * per + min(x, rem) + i;
 }
 
-__global__ __launch_bounds__(kRollThreads) void k_rollout_point_mass(PlanDesc P) {
+// Rollout kernels come in two builds.  ONE: the launch puts at most one
+// workgroup (one wave per SIMD) on a compute unit, so the compiler is told to
+// schedule for a single resident wave (more registers, more independent work
+// in flight); otherwise the usual occupancy target.
+#define MTP_ROLL_WAVES(one) __attribute__((amdgpu_waves_per_eu(1, (one) ? 1 : 8)))
+
+template <bool ONE>
+__global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE) void k_rollout_point_mass(PlanDesc P) {
   if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
   __shared__ PointMassSmem sm;
   stage_obstacles(P, sm);
@@ -77,15 +84,15 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_point_mass(PlanDesc P)
   if (b < P.B) rollout_point_mass_any(P, b, sm);
 }
 
-template <int N, bool CONTACT>
-__global__ __launch_bounds__(kRollThreads) void k_rollout_chain(PlanDesc P) {
+template <int N, bool CONTACT, bool ONE>
+__global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE) void k_rollout_chain(PlanDesc P) {
   if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
   const int b = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
   if (b < P.B) rollout_chain<N, CONTACT>(P, b);
 }
 
-template <int N, bool CONTACT>
-__global__ __launch_bounds__(kRollThreads) void k_rollout_chain_pair(PlanDesc P) {
+template <int N, bool CONTACT, bool ONE>
+__global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE || N >= 20) void k_rollout_chain_pair(PlanDesc P) {
   if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
   const int g = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
   const int b = g >> 1;
@@ -96,7 +103,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_chain_pair(PlanDesc P)
 constexpr uint64_t kSegWaitTicks = 1000000000ull;   // 10 s of the 100 MHz wall clock
 
 template <int N, bool CONTACT>
-__global__ __launch_bounds__(kRollThreads) void k_rollout_pair_seg(PlanDesc P) {
+__global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(N >= 20) void k_rollout_pair_seg(PlanDesc P) {
   rollout_pair_segmented<N, CONTACT>(P, P.seg_ctl, P.seg_done, P.seg_state, P.seg_S, P.seg_len, kSegWaitTicks);
   if (threadIdx.x == 0 && __hip_atomic_load(&P.seg_ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
     atomicOr(&P.ctrl[2], 4u);
@@ -111,8 +118,8 @@ __global__ __launch_bounds__(64) void k_seg_init(SegCtl* ctl) {
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(kRollThreads) void k_rollout_chain_quad(PlanDesc P) {
+template <int N, bool ONE>
+__global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE) void k_rollout_chain_quad(PlanDesc P) {
   if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
   const int g = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
   const int b = g >> 2;
@@ -196,6 +203,9 @@ static size_t gen_lds_bytes(const PlanDesc& P) {
   return tile > kOnePerUnitLds ? tile : kOnePerUnitLds;
 }
 
+template <bool ONE>
+static hipError_t launch_rollout_kernel(const PlanDesc& P, dim3 grid, size_t lds, hipStream_t st);
+
 // The rollout of P.U; with gen_k >= 0 the launch adds workgroups up to
 // P.gen_grid that draw iteration gen_k's tensor-path controls into P.U2.
 static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) {
@@ -232,13 +242,19 @@ static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) 
     lds = kOnePerUnitLds;
   }
   const dim3 grid(blocks);
+  // a launch with LDS reserved holds one workgroup per unit
+  return lds != 0 ? launch_rollout_kernel<true>(P, grid, lds, st) : launch_rollout_kernel<false>(P, grid, lds, st);
+}
+
+template <bool ONE>
+static hipError_t launch_rollout_kernel(const PlanDesc& P, dim3 grid, size_t lds, hipStream_t st) {
   if (P.dyn == kPointMass) {
-    k_rollout_point_mass<<<grid, kRollThreads, lds, st>>>(P);
+    k_rollout_point_mass<ONE><<<grid, kRollThreads, lds, st>>>(P);
     return hipGetLastError();
   }
   if (is_quad_chain(P.dyn, P.n_links)) {
     switch (P.n_links) {
-#define X(N) case N: if constexpr (quad_chain_links<N>()) { k_rollout_chain_quad<N><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (quad_chain_links<N>()) { k_rollout_chain_quad<N, ONE><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
       MTP_CHAIN_LINKS(X)
 #undef X
       default: break;
@@ -248,14 +264,14 @@ static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) 
   if (is_pair_chain(P.dyn, P.n_links)) {
     if (P.dyn == kChain) {
       switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, false><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, false, ONE><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
         MTP_CHAIN_LINKS(X)
 #undef X
         default: break;
       }
     } else {
       switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, true><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_chain_pair<N, true, ONE><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
         MTP_CONTACT_LINKS(X)
 #undef X
         default: break;
@@ -265,7 +281,7 @@ static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) 
   }
   if (P.dyn == kChain) {
     switch (P.n_links) {
-#define X(N) case N: if constexpr (!pair_chain_links<N>() && !quad_chain_links<N>()) { k_rollout_chain<N, false><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (!pair_chain_links<N>() && !quad_chain_links<N>()) { k_rollout_chain<N, false, ONE><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
       MTP_CHAIN_LINKS(X)
 #undef X
       default: break;
@@ -273,7 +289,7 @@ static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) 
     return hipErrorInvalidValue;
   }
   switch (P.n_links) {
-#define X(N) case N: if constexpr (!pair_chain_links<N>()) { k_rollout_chain<N, true><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
+#define X(N) case N: if constexpr (!pair_chain_links<N>()) { k_rollout_chain<N, true, ONE><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
     MTP_CONTACT_LINKS(X)
 #undef X
     default: break;
