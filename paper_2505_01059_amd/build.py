@@ -10,7 +10,14 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmtp.so")
 
-SOURCES = ["kernels.hip", "plan.cpp", "batch.hip", "batch.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "rollout_quad.hip", "plan.cpp", "batch.hip", "batch.cpp", "server.cpp"]
+# The batched persistent kernel and the quad-lane rollout run one wave per SIMD,
+# and LLVM's iterative ILP scheduler orders their long dependent chains better
+# than the default (measured: 256-instance batched replan 86.1 -> 82.2 ms).
+EXTRA_FLAGS = {
+    "batch.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "rollout_quad.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+}
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off: plain float code only
@@ -28,7 +35,7 @@ def hipcc():
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *HIP_FLAGS, *EXTRA_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile of {src} failed:\n{r.stderr}")
@@ -37,7 +44,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -1,6 +1,7 @@
 // Single-plan kernels of one MTP replan for gfx950 and their host launchers.
 // Each kernel is a thin grid over the stage tiles of mtp_device.hpp.
 #include "kernels.hpp"
+#include "rollout_grid.hpp"
 
 namespace mtp {
 
@@ -28,26 +29,6 @@ __global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) 
   cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, t_begin, min(P.T, t_begin + P.tc), v);
 }
 
-// Workgroups of a rollout launch beyond P.roll_blocks, each alone on its
-// compute unit (the launch asks for enough LDS to keep one workgroup per unit),
-// draw the tensor-path controls of iteration P.gen_k into P.U2 on the units the
-// rollout leaves idle: items (tensor tile, joint) over the whole horizon.
-__device__ __forceinline__ void gen_tensor_tiles(const PlanDesc& P) {
-  extern __shared__ float gen_lds[];
-  const CandView v = cand_view_dyn(gen_lds, P.L, P.W, P.T < kTChunk ? P.T : kTChunk);
-  PlanDesc Q = P;
-  Q.U = P.U2;
-  const int first = (P.G - 1) / kCandThreads;                  // tile of the first tensor path
-  const int last = (P.G - 1 + P.P - 1) / kCandThreads;         // tile of the last one
-  const int items = (last - first + 1) * P.n;
-  const int gens = static_cast<int>(gridDim.x) - P.roll_blocks;
-  const uint32_t r = P.ctrl[0];
-  for (int it = static_cast<int>(blockIdx.x) - P.roll_blocks; it < items; it += gens) {
-    const int tile = first + it / P.n, j = it - (it / P.n) * P.n;
-    cand_tile(Q, r, P.gen_k, j, tile * kCandThreads, 0, P.T, v, kCandTensor);
-  }
-}
-
 __global__ __launch_bounds__(kTopkThreads) void k_entropy(PlanDesc P, int k) {
   __shared__ EntropySmem sm;
   entropy_block<kTopkThreads>(P, k, sm);
@@ -57,23 +38,6 @@ __global__ __launch_bounds__(kTopkThreads) void k_entropy(PlanDesc P, int k) {
 // SIMDs of a compute unit, while single-wave workgroups sharing a unit were seen
 // to stack two waves on one SIMD now and then, doubling the time of a launch
 // with fewer waves than SIMDs.
-// The dispatcher hands workgroup g to XCD g mod 8, and each XCD has its own L2.
-// Giving each XCD one contiguous run of workgroup indices keeps the U rows of
-// neighbouring candidates, and the lines they share, in one L2.  A bijection of
-// [0, G) for any G.
-__device__ __forceinline__ int xcd_contiguous_block(int g, int G) {
-  constexpr int kXcds = 8;
-  const int x = g % kXcds, i = g / kXcds;
-  const int per = G / kXcds, rem = G % kXcds;
-  return x * per + min(x, rem) + i;
-}
-
-// Rollout kernels come in two builds.  ONE: the launch puts at most one
-// workgroup (one wave per SIMD) on a compute unit, so the compiler is told to
-// schedule for a single resident wave (more registers, more independent work
-// in flight); otherwise the usual occupancy target.
-#define MTP_ROLL_WAVES(one) __attribute__((amdgpu_waves_per_eu(1, (one) ? 1 : 8)))
-
 template <bool ONE>
 __global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE) void k_rollout_point_mass(PlanDesc P) {
   if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
@@ -116,14 +80,6 @@ __global__ __launch_bounds__(64) void k_seg_init(SegCtl* ctl) {
     ctl->error = 0u;
     ctl->epoch = ctl->epoch + 1u;
   }
-}
-
-template <int N, bool ONE>
-__global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE) void k_rollout_chain_quad(PlanDesc P) {
-  if (static_cast<int>(blockIdx.x) >= P.roll_blocks) { gen_tensor_tiles(P); return; }
-  const int g = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
-  const int b = g >> 2;
-  if (b < P.B) rollout_chain_quad<N>(P, b, g & 3);
 }
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {
@@ -252,15 +208,7 @@ static hipError_t launch_rollout_kernel(const PlanDesc& P, dim3 grid, size_t lds
     k_rollout_point_mass<ONE><<<grid, kRollThreads, lds, st>>>(P);
     return hipGetLastError();
   }
-  if (is_quad_chain(P.dyn, P.n_links)) {
-    switch (P.n_links) {
-#define X(N) case N: if constexpr (quad_chain_links<N>()) { k_rollout_chain_quad<N, ONE><<<grid, kRollThreads, lds, st>>>(P); return hipGetLastError(); } break;
-      MTP_CHAIN_LINKS(X)
-#undef X
-      default: break;
-    }
-    return hipErrorInvalidValue;
-  }
+  if (is_quad_chain(P.dyn, P.n_links)) return launch_rollout_quad(P, grid, lds, st, ONE);
   if (is_pair_chain(P.dyn, P.n_links)) {
     if (P.dyn == kChain) {
       switch (P.n_links) {

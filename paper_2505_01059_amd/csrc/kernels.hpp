@@ -15,6 +15,9 @@ hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st);
 // Stage of iteration k in a run of iterations [k0, k1) (next iteration's tensor
 // paths drawn during the rollout when the plan has a second U buffer).
 hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st);
+// Quad-lane chain rollout (rollout_quad.hip); one: the launch holds one
+// workgroup per compute unit.
+hipError_t launch_rollout_quad(const PlanDesc& P, dim3 grid, size_t lds, hipStream_t st, bool one);
 // Workgroups of the (not time-sliced) rollout kernel of a plan.
 int rollout_blocks(const PlanDesc& P);
 // Grid and segment count of the time-sliced pair-lane rollout for the current
