@@ -1047,7 +1047,8 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
   const float* p1 = P.U + b + static_cast<size_t>(v1 ? r1 : N - 1) * ld;
   const size_t row = static_cast<size_t>(N) * ld;
   float u0 = K.v0f * *p0, u1 = K.v1f * *p1;
-  float cost = 0.0f;
+  float cost = 0.0f;   // goal term; the control term is summed per lane (uacc) and joined once
+  float uacc = 0.0f;
   for (int t = 0; t < P.T; ++t) {
     // next step's controls (the last step re-reads its own row)
     const size_t adv = (t + 1 < P.T) ? row : 0;
@@ -1091,12 +1092,11 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     const float l0v = K.v0f * K.l0, l1v = K.v1f * K.l1;
     float ex = fmaf(l0v, s0, l1v * s1);
     float ey = -fmaf(l0v, c0, l1v * c1);
-    const float uu = fmaf(u0, u0, u1 * u1);
+    uacc = fmaf(u0, u0, fmaf(u1, u1, uacc));
     ex = quad_sum(ex);
     ey = quad_sum(ey);
-    const float uus = quad_sum(uu);
     const float dx = ex - tx, dy = ey - ty;
-    cost += fmaf(wg, fmaf(dx, dx, dy * dy), wu * uus);
+    cost = fmaf(wg, fmaf(dx, dx, dy * dy), cost);
     if (b < P.n_dbg) {
       float* X = P.X + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
@@ -1108,6 +1108,7 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     u0 = un0;
     u1 = un1;
   }
+  cost = fmaf(wu, quad_sum(uacc), cost);
   if (s == 0) P.cost[b] = finite_or_inf(cost);
 }
 
@@ -1715,14 +1716,14 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const bool cached = B <= kTopkCache;
   auto image = [&](int b) -> uint32_t { return cached ? sm.cache[b] : cost_order(cost[b]); };
 
-  // images, their minimum and maximum (four loads in flight per thread)
+  // images, their minimum and maximum (eight loads in flight per thread)
   uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-  for (int b0 = tid; b0 < B; b0 += 4 * BS) {
-    float c[4];
+  for (int b0 = tid; b0 < B; b0 += 8 * BS) {
+    float c[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) c[u] = b0 + u * BS < B ? cost[b0 + u * BS] : 0.0f;
+    for (int u = 0; u < 8; ++u) c[u] = b0 + u * BS < B ? cost[b0 + u * BS] : 0.0f;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int b = b0 + u * BS;
       if (b < B) {
         const uint32_t o = cost_order(c[u]);
