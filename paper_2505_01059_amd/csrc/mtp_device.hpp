@@ -574,11 +574,14 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
     const float dx = px - gx, dy = py - gy;
     float c = wg * fmaf(dx, dx, dy * dy);
     if constexpr (NOBS > 0) {
+      // four partial sums: the obstacle terms form four short chains, not one long one
+      float pc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int o = 0; o < NOBS; ++o) {
         const float ox = px - ocx[o], oy = py - ocy[o];
-        c += (fmaf(ox, ox, oy * oy) < orr[o]) ? pen : 0.0f;
+        pc[o & 3] += (fmaf(ox, ox, oy * oy) < orr[o]) ? pen : 0.0f;
       }
+      c += (pc[0] + pc[1]) + (pc[2] + pc[3]);
     } else {
       for (int o = 0; o < n_obs; ++o) {
         const float ox = px - obs[3 * o], oy = py - obs[3 * o + 1];
@@ -602,13 +605,14 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
 
 // Obstacle-table size class of a point-mass plan: 8, 16, 32 in registers, 0 in LDS.
 __device__ __host__ __forceinline__ int point_mass_obs_class(int n_obs) {
-  return n_obs <= 8 ? 8 : (n_obs <= 16 ? 16 : (n_obs <= 32 ? 32 : 0));
+  return n_obs <= 8 ? 8 : (n_obs <= 16 ? 16 : (n_obs <= 20 ? 20 : (n_obs <= 32 ? 32 : 0)));
 }
 
 __device__ __forceinline__ void rollout_point_mass_any(const PlanDesc& P, int b, const PointMassSmem& sm) {
   switch (point_mass_obs_class(static_cast<int>(P.task[5]))) {
     case 8: rollout_point_mass<8>(P, b, sm); return;
     case 16: rollout_point_mass<16>(P, b, sm); return;
+    case 20: rollout_point_mass<20>(P, b, sm); return;
     case 32: rollout_point_mass<32>(P, b, sm); return;
     default: rollout_point_mass<0>(P, b, sm); return;
   }
