@@ -221,6 +221,29 @@ def test_rollout_spinning_start(name, torch_mod):
     plan.close()
 
 
+@pytest.mark.parametrize("n_obs", [0, 3, 12, 20, 27, 40])
+def test_point_mass_obstacle_classes(n_obs, torch_mod):
+    """Obstacle tables of every register class (8, 16, 20, 32) and the LDS
+    path beyond 32, against the oracle's costs."""
+    cfg = W.point_mass_config(name=f"pm_obs{n_obs}", n_tensor=300, n_gauss=20, horizon=40, n_iters=2,
+                              n_obstacles=n_obs, seed=7)
+    _log(f"[point mass obstacles] {n_obs}")
+    plan = make_plan(cfg, n_debug_states=4)
+    mu, sg = random_state(cfg, 9)
+    _, _, U_ref = OP.candidates(cfg, mu.astype(np.float64), sg.astype(np.float64), 1, 0)
+    U32 = U_ref.astype(np.float32).astype(np.float64)
+    b = plan.buffers()
+    H.write_U(b, U32)
+    x0 = W.initial_state(cfg, seed=2)
+    plan.set_x0(x0)
+    plan.run_stage(1, 1, 0)
+    torch_mod.cuda.synchronize()
+    s = b["cost"].cpu().numpy()
+    s_ref = OP.rollout(cfg, x0, U32)
+    H.assert_costs(cfg, s, s_ref, np.zeros(cfg.n_samples, bool))
+    plan.close()
+
+
 def test_topk_stage_exact_with_ties(torch_mod):
     import torch
     cfg = W.point_mass_config(n_tensor=5000, n_gauss=1000, n_elites=300)
