@@ -1570,6 +1570,12 @@ __device__ __forceinline__ uint32_t cost_order(float c) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// Inverse of cost_order on its images: the cost itself, except that NaN comes
+// back as +inf and -0 as +0 (callers read those two cases from memory).
+__device__ __forceinline__ float order_cost(uint32_t o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
 constexpr int kTopkBins = 2048;      // radix digits of up to 11 bits
 constexpr int kTopkCache = 16384;    // batches up to this size keep their cost images in LDS
 constexpr int kTopkRankSort = 1024;  // elite sets up to this size are ordered by counting ranks
@@ -1720,14 +1726,15 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   const bool cached = B <= kTopkCache;
   auto image = [&](int b) -> uint32_t { return cached ? sm.cache[b] : cost_order(cost[b]); };
 
-  // images, their minimum and maximum (eight loads in flight per thread)
+  // images, their minimum and maximum (up to eight loads in flight per thread)
   uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-  for (int b0 = tid; b0 < B; b0 += 8 * BS) {
-    float c[8];
+  constexpr int kLoads = 8;
+  for (int b0 = tid; b0 < B; b0 += kLoads * BS) {
+    float c[kLoads];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = b0 + u * BS < B ? cost[b0 + u * BS] : 0.0f;
+    for (int u = 0; u < kLoads; ++u) c[u] = b0 + u * BS < B ? cost[b0 + u * BS] : 0.0f;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kLoads; ++u) {
       const int b = b0 + u * BS;
       if (b < B) {
         const uint32_t o = cost_order(c[u]);
@@ -1845,14 +1852,20 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
   // elites, costs and softmax weights w_e = exp(-(s_e - s_0)/lambda) / sum;
   // the unnormalised weights wait in LDS (the image cache is free by now)
   float* wbuf = reinterpret_cast<float*>(sm.cache);
+  // elite costs come back from their keys' images; +inf (also NaN) and zero
+  // (also -0) are read from memory to keep the cost as it was
+  auto elite_cost = [&](unsigned long long key, int idx) -> float {
+    const float v = order_cost(static_cast<uint32_t>(key >> 32));
+    return (v == 0.0f || v == INFINITY) ? cost[idx] : v;
+  };
   const uint32_t i0 = static_cast<uint32_t>(ord[0]);
-  const float s0 = cost[i0 < static_cast<uint32_t>(B) ? i0 : 0u];
+  const float s0 = elite_cost(ord[0], static_cast<int>(i0 < static_cast<uint32_t>(B) ? i0 : 0u));
   const bool uniform = !(P.lam < INFINITY) || !(s0 < INFINITY);
   for (int e = tid; e < E; e += BS) {
     uint32_t uidx = static_cast<uint32_t>(ord[e]);
     if (uidx >= static_cast<uint32_t>(B)) { uidx = 0u; atomicOr(&P.ctrl[2], 2u); }   // never expected
     const int idx = static_cast<int>(uidx);
-    const float ce = cost[idx];
+    const float ce = elite_cost(ord[e], idx);
     gptr(P.eidx)[e] = idx;
     gptr(P.ecost)[e] = ce;
     wbuf[e] = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
