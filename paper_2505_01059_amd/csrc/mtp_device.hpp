@@ -1997,6 +1997,9 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
   const auto row = gptr(P.U) + static_cast<size_t>(o) * ld;
   const auto eidx = gptr(P.eidx);
   const auto w = gptr(P.w);
+  // the old moments do not depend on the gathers: their loads go out first
+  const auto mu = gptr(P.mu), sigma = gptr(P.sigma);
+  const float mu_old = mu[o], sg_old = sigma[o];
   float keep[kUpdKeep];
   float m = 0.0f;
   if (P.E <= 64 * kUpdKeep) {
@@ -2032,8 +2035,6 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
   }
   v = wave_sum64(v);
   const float sd = fmaxf(sqrtf(v), P.sigma_min);
-  const auto mu = gptr(P.mu), sigma = gptr(P.sigma);
-  const float mu_old = mu[o], sg_old = sigma[o];
   const float mn = fmaf(P.alpha, mu_old - m, m);
   const float sn = fmaf(P.alpha, sg_old - sd, sd);
   if (mu_new) *mu_new = mn;
@@ -2041,7 +2042,8 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
   if (lane == 0) {
     mu[o] = mn;
     sigma[o] = sn;
-    if (o < P.n) gptr(P.action)[o] = row[eidx[0]];   // first control of the best candidate
+    // first control of the best candidate (lane 0 gathered elite 0 already)
+    if (o < P.n) gptr(P.action)[o] = P.E <= 64 * kUpdKeep ? keep[0] : row[eidx[0]];
   }
 }
 
