@@ -220,7 +220,9 @@ mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
  * results are the same bits either way (Alg. 2: the tensor paths do not depend
  * on the sampling distribution being refitted). */
 int32_t mtp_plan_draws_ahead(const mtp_plan* p);
-/* Status flags of the last replan: bit 0 = every elite cost was +inf (weights fell back to uniform). */
+/* Status flags of the last replan: bit 0 = every elite cost was +inf (weights fell back to uniform);
+ * bit 1 = an elite index out of range (never expected); bit 2 = a wait of the time-sliced rollout
+ * timed out (results of that replan are not valid). */
 mtp_status mtp_get_flags(mtp_plan* p, uint32_t* h_flags);
 mtp_status mtp_plan_destroy(mtp_plan* p);
 
