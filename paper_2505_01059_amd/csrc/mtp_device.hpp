@@ -1719,7 +1719,7 @@ __device__ __forceinline__ void topk_gather_split(int B, uint32_t lo, Image imag
 // ties.  The E keys are finally ordered by counting ranks, or by a bitonic
 // network for very large E.
 template <int BS>
-__device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
+__device__ __forceinline__ const unsigned long long* topk_select(const PlanDesc& P, TopkSmem& sm) {
   const auto cost = gptr(P.cost);
   const int tid = threadIdx.x;
   const int B = P.B, E = P.E;
@@ -1848,6 +1848,37 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     }
     ord = sm.keys;
   }
+  return ord;
+}
+
+// Batches of at most one key per thread: every key counts the keys below it
+// (broadcast LDS reads), and that count is its place in the order; the keys
+// are distinct, so this is the same exact order as the radix path's.
+template <int BS>
+__device__ __forceinline__ const unsigned long long* topk_select_small(const PlanDesc& P, TopkSmem& sm) {
+  const auto cost = gptr(P.cost);
+  const int tid = threadIdx.x;
+  const int B = P.B, E = P.E;
+  unsigned long long* all = reinterpret_cast<unsigned long long*>(sm.cache);
+  const unsigned long long key =
+      tid < B ? (static_cast<unsigned long long>(cost_order(cost[tid])) << 32) | static_cast<uint32_t>(tid) : ~0ull;
+  if (tid < B) all[tid] = key;
+  __syncthreads();
+  if (tid < B) {
+    int rank = 0;
+#pragma unroll 8
+    for (int j = 0; j < B; ++j) rank += all[j] < key ? 1 : 0;
+    if (rank < E) sm.sorted[rank] = key;
+  }
+  return sm.sorted;
+}
+
+template <int BS>
+__device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
+  const auto cost = gptr(P.cost);
+  const int tid = threadIdx.x;
+  const int B = P.B, E = P.E;
+  const unsigned long long* ord = B <= BS ? topk_select_small<BS>(P, sm) : topk_select<BS>(P, sm);
   __syncthreads();
   // elites, costs and softmax weights w_e = exp(-(s_e - s_0)/lambda) / sum;
   // the unnormalised weights wait in LDS (the image cache is free by now)

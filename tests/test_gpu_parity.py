@@ -267,6 +267,34 @@ def test_topk_stage_exact_with_ties(torch_mod):
     plan.close()
 
 
+@pytest.mark.parametrize("B, E", [(1, 1), (2, 1), (64, 64), (700, 300), (1024, 1024), (1024, 5), (1025, 17)])
+def test_topk_small_batches_with_ties(B, E, torch_mod):
+    """Batches of at most one key per thread take the counting-rank path, one
+    above that the radix path: both against the oracle's order, with NaN, +inf,
+    -0 and exact ties."""
+    import torch
+    cfg = W.point_mass_config(n_tensor=B - 1, n_gauss=1, n_elites=E)
+    plan = make_plan(cfg)
+    b = plan.buffers()
+    rng = np.random.default_rng(B + E)
+    s = np.round(rng.normal(size=B), 1).astype(np.float32)
+    for val, cnt in ((np.nan, B // 10), (np.inf, B // 10), (-0.0, B // 20), (0.0, B // 20)):
+        if cnt:
+            s[rng.choice(B, cnt, replace=False)] = val
+    b["cost"].copy_(torch.from_numpy(s).cuda())
+    plan.run_stage(2, 0, 0)
+    torch_mod.cuda.synchronize()
+    want = OP.top_elites(np.where(s == 0, 0.0, s).astype(np.float64), E)
+    assert np.array_equal(b["elite_idx"].cpu().numpy(), want)
+    ec = b["elite_cost"].cpu().numpy() if "elite_cost" in b else None
+    if ec is not None:
+        assert np.array_equal(ec.view(np.uint32), s[want].view(np.uint32)), "elite costs not returned as they were"
+    w = b["weights"].cpu().numpy()
+    w_ref = OP.softmax_weights(s[want].astype(np.float64), float(cfg.temperature))
+    np.testing.assert_allclose(w, w_ref, rtol=1e-5, atol=1e-7)
+    plan.close()
+
+
 @pytest.mark.parametrize("E", [1, 7, 64, 511, 4096])
 def test_topk_sizes(E, torch_mod):
     import torch
