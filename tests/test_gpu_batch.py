@@ -197,3 +197,42 @@ def test_mix_of_256_sampled_against_standalone():
         assert np.array_equal(b["mu"].cpu().numpy(), mu), cfgs[i].name
         assert np.array_equal(acts[i], a), cfgs[i].name
     bt.close()
+
+
+def large_launch_mix():
+    """Plans whose rollout launch fills the chip (at least one workgroup per
+    compute unit), so the single plan uses the rollout build that targets the
+    usual occupancy rather than the one-wave-per-SIMD build: quad-lane,
+    one-lane, point-mass and pair-lane with replicas (not time-sliced)."""
+    return [
+        W.chain_config(name="L_c7", interp=W.AKIMA, n_tensor=19000, n_gauss=1001, horizon=12, n_elites=64,
+                       n_iters=2, seed=31),
+        W.chain_config(name="L_c2", n_links=2, n_tensor=68000, n_gauss=2000, horizon=8, n_layers=4, n_width=8,
+                       n_elites=32, n_iters=2, seed=32),
+        W.point_mass_config(name="L_pm", n_tensor=68000, n_gauss=2000, horizon=8, n_elites=32, n_iters=2,
+                            seed=33),
+        W.chain_contact_config(name="L_k24r2", n_tensor=34000, n_gauss=1000, horizon=6, n_elites=32, n_iters=2,
+                               seed=34, n_replicas=2),
+    ]
+
+
+def test_large_launches_equal_the_batch():
+    import torch
+    import paper_2505_01059_amd as mtp
+    cfgs = large_launch_mix()
+    x0s = [W.initial_state(c, seed=40 + i) for i, c in enumerate(cfgs)]
+    _log(f"[large launches] {[c.name for c in cfgs]}")
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    bt.replan(bt.pack_x0(x0s), shift=1)
+    acts = bt.actions()
+    for i, c in enumerate(cfgs):
+        p = mtp.Plan(c, device="cuda:0")
+        p.replan(x0s[i], shift=1, replan_idx=0)
+        torch.cuda.synchronize()
+        b, bb = p.buffers(), bt.buffers(i)
+        assert np.array_equal(bb["cost"].cpu().numpy(), b["cost"].cpu().numpy()), c.name
+        assert np.array_equal(bb["mu"].cpu().numpy(), b["mu"].cpu().numpy()), c.name
+        assert np.array_equal(bb["sigma"].cpu().numpy(), b["sigma"].cpu().numpy()), c.name
+        assert np.array_equal(acts[i], p.action()), c.name
+        p.close()
+    bt.close()
