@@ -1576,6 +1576,47 @@ __device__ __forceinline__ float order_cost(uint32_t o) {
   return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
 }
 
+// Wave-wide minimum, maximum and inclusive sum with DPP row shifts and row
+// broadcasts (no LDS round trips): in-row steps of 1, 2, 4 and 8 lanes, then
+// row 0's last lane into row 1 and row 2's into row 3, then lane 31 into rows
+// 2 and 3.  Lanes without a source keep their own value (min, max) or add 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(static_cast<int>(old), static_cast<int>(v), CTRL, ROWS, 0xF, false));
+}
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, dpp_u32<kDppRowShr1, 0xF>(v, v));
+  v = min(v, dpp_u32<kDppRowShr2, 0xF>(v, v));
+  v = min(v, dpp_u32<kDppRowShr4, 0xF>(v, v));
+  v = min(v, dpp_u32<kDppRowShr8, 0xF>(v, v));
+  v = min(v, dpp_u32<kDppRowBcast15, 0xA>(v, v));
+  v = min(v, dpp_u32<kDppRowBcast31, 0xC>(v, v));
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, dpp_u32<kDppRowShr1, 0xF>(v, v));
+  v = max(v, dpp_u32<kDppRowShr2, 0xF>(v, v));
+  v = max(v, dpp_u32<kDppRowShr4, 0xF>(v, v));
+  v = max(v, dpp_u32<kDppRowShr8, 0xF>(v, v));
+  v = max(v, dpp_u32<kDppRowBcast15, 0xA>(v, v));
+  v = max(v, dpp_u32<kDppRowBcast31, 0xC>(v, v));
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_sum_u32(uint32_t v) {
+  v += dpp_u32<kDppRowShr1, 0xF>(0u, v);
+  v += dpp_u32<kDppRowShr2, 0xF>(0u, v);
+  v += dpp_u32<kDppRowShr4, 0xF>(0u, v);
+  v += dpp_u32<kDppRowShr8, 0xF>(0u, v);
+  v += dpp_u32<kDppRowBcast15, 0xA>(0u, v);
+  v += dpp_u32<kDppRowBcast31, 0xC>(0u, v);
+  return v;
+}
+
 constexpr int kTopkBins = 2048;      // radix digits of up to 11 bits
 constexpr int kTopkCache = 16384;    // batches up to this size keep their cost images in LDS
 constexpr int kTopkRankSort = 1024;  // elite sets up to this size are ordered by counting ranks
@@ -1608,12 +1649,7 @@ __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t 
   uint32_t tot = 0;
   for (int i = 0; i < per; ++i)
     if (first + i < nbins) tot += sm.hist[first + i];
-  uint32_t inc = tot;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t v = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += v;
-  }
+  uint32_t inc = wave_inclusive_sum_u32(tot);
   if (lane == 63) sm.wlo[wave] = inc;
   __syncthreads();
 #pragma unroll
@@ -1744,13 +1780,12 @@ __device__ __forceinline__ const unsigned long long* topk_select(const PlanDesc&
       }
     }
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = min(lo, static_cast<uint32_t>(__shfl_xor(static_cast<int>(lo), o, 64)));
-    hi = max(hi, static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), o, 64)));
-  }
+  lo = wave_min_u32(lo);
+  hi = wave_max_u32(hi);
   if ((tid & 63) == 0) { sm.wlo[tid >> 6] = lo; sm.whi[tid >> 6] = hi; }
   if (tid == 0) { sm.count = 0u; sm.count2 = 0u; }
+  // the first radix pass's histogram is cleared before the same barrier
+  for (int i = tid; i < kTopkBins; i += BS) sm.hist[i] = 0u;
   __syncthreads();
 #pragma unroll
   for (int w = 0; w < BS / 64; ++w) { lo = min(lo, sm.wlo[w]); hi = max(hi, sm.whi[w]); }
@@ -1762,12 +1797,16 @@ __device__ __forceinline__ const unsigned long long* topk_select(const PlanDesc&
   unsigned long long prefix = 0ull, mask = 0ull;
   uint32_t rank = static_cast<uint32_t>(E), sel = static_cast<uint32_t>(B);
   int shift = bits;
+  bool cleared = true;
   while (shift > 0 && sel > static_cast<uint32_t>(kTopkBoundary)) {
     const int width = shift < 11 ? shift : 11;
     shift -= width;
     const int nb = 1 << width;
-    for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
-    __syncthreads();
+    if (!cleared) {
+      for (int i = tid; i < nb; i += BS) sm.hist[i] = 0u;
+      __syncthreads();
+    }
+    cleared = false;
 #pragma unroll 4
     for (int b = tid; b < B; b += BS) {
       const uint32_t v = image(b) - lo;
