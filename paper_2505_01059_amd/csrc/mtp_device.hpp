@@ -1551,10 +1551,25 @@ __device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl
 }
 
 // ------------------------------------------------------------------ reductions
+// One DPP step of a wave reduction: lanes without a source (and rows outside
+// ROWS) contribute +0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, false));
+}
+
+// Sum over the wave in a fixed order with DPP row shifts and row broadcasts
+// (no LDS round trips): in-row steps of 1, 2, 4 and 8 lanes, row 0's total into
+// row 1 and row 2's into row 3, then lane 31 into rows 2 and 3; lane 63 holds
+// the sum, which every lane reads.
 __device__ __forceinline__ float wave_sum64(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f32<0x111, 0xF>(v);
+  v += dpp_f32<0x112, 0xF>(v);
+  v += dpp_f32<0x114, 0xF>(v);
+  v += dpp_f32<0x118, 0xF>(v);
+  v += dpp_f32<0x142, 0xA>(v);
+  v += dpp_f32<0x143, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // ------------------------------------------------------------------ top-E
