@@ -1956,7 +1956,7 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
     wbuf[e] = uniform ? 1.0f : expf(-(ce - s0) / P.lam);
   }
   // normalisation sum in an order fixed by E alone (independent of the block
-  // size): lane l of wave 0 adds e = l, l+64, ... in turn, then a butterfly.
+  // size): lane l of wave 0 adds e = l, l+64, ... in turn, then wave_sum64.
   __syncthreads();
   if (tid < 64) {
     float acc = 0.0f;
@@ -2066,8 +2066,8 @@ __device__ __forceinline__ void entropy_block(const PlanDesc& P, int k, EntropyS
 }
 
 // ------------------------------------------------------------------ refit
-// One wave per output (t, j): lanes stride over the elites, fixed-order
-// butterfly reduction, then the sigma floor and exponential smoothing.
+// One wave per output (t, j): lanes stride over the elites, a fixed-order
+// wave sum, then the sigma floor and exponential smoothing.
 
 // The elite values of a row are gathered once: up to kUpdKeep per lane stay in
 // registers for the variance pass (each gather touches its own cache line, so
