@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mtp {
 
 constexpr int kMaxLayers = 16;
@@ -1686,7 +1688,8 @@ __device__ __forceinline__ void topk_find_bin(TopkSmem& sm, int nbins, uint32_t 
 
 // Counting ranks of n distinct keys src[0..n) among themselves: tpk threads
 // share each key's comparisons (as many as the block allows, at most a wave),
-// then combine their counts with a butterfly.  sink(key, rank) runs once per key.
+// then the first of them sums their counts (DPP suffix sums within a row of 16
+// lanes, LDS permutes across rows).  sink(key, rank) runs once per key.
 template <int BS, class Sink>
 __device__ __forceinline__ void topk_rank(const unsigned long long* src, int n, Sink sink) {
   int tpk = 1;
@@ -1707,7 +1710,14 @@ __device__ __forceinline__ void topk_rank(const unsigned long long* src, int n, 
       }
       for (; q < n; q += tpk) r += src[q] < k ? 1 : 0;
     }
-    for (int o = 1; o < tpk; o <<= 1) r += __shfl_xor(r, o, 64);
+    auto shl = [](int x, auto c) {
+      return __builtin_amdgcn_update_dpp(0, x, decltype(c)::value, 0xF, 0xF, false);
+    };
+    if (tpk > 1) r += shl(r, std::integral_constant<int, 0x101>{});
+    if (tpk > 2) r += shl(r, std::integral_constant<int, 0x102>{});
+    if (tpk > 4) r += shl(r, std::integral_constant<int, 0x104>{});
+    if (tpk > 8) r += shl(r, std::integral_constant<int, 0x108>{});
+    for (int o = 16; o < tpk; o <<= 1) r += __shfl_xor(r, o, 64);
     if (i < n && sub == 0) sink(k, r);
   }
 }
@@ -1722,7 +1732,7 @@ __device__ __forceinline__ void wave_append(bool t, unsigned long long key, uint
   const int leader = __ffsll(static_cast<long long>(m)) - 1;
   uint32_t slot0 = 0u;
   if (lane == leader) slot0 = atomicAdd(counter, static_cast<uint32_t>(__popcll(m)));
-  slot0 = static_cast<uint32_t>(__shfl(static_cast<int>(slot0), leader, 64));
+  slot0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(slot0), leader));
   const uint32_t slot = slot0 + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
   if (t && slot < cap) dst[slot] = key;
 }
