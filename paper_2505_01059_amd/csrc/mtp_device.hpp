@@ -1756,16 +1756,67 @@ __device__ __forceinline__ void topk_gather_split(int B, uint32_t lo, Image imag
                                                   unsigned long long pd, uint32_t* c_lo, unsigned long long* d_lo,
                                                   uint32_t cap_lo, uint32_t* c_b, unsigned long long* d_b,
                                                   uint32_t cap_b) {
-  for (int base = 0; base < B; base += BS) {
-    const int b = base + static_cast<int>(threadIdx.x);
-    unsigned long long key = 0ull, hv = 0ull;
-    if (b < B) {
-      const uint32_t im = image(b);
-      key = (static_cast<unsigned long long>(im) << 32) | static_cast<uint32_t>(b);
-      hv = static_cast<unsigned long long>(im - lo) >> shift;
+  if constexpr (BS >= 1024) {
+    // one row at a time, one counter bump per wave and list (measured faster
+    // than the grouped form below in the 1024-thread single-plan kernel)
+    for (int base = 0; base < B; base += BS) {
+      const int b = base + static_cast<int>(threadIdx.x);
+      unsigned long long key = 0ull, hv = 0ull;
+      if (b < B) {
+        const uint32_t im = image(b);
+        key = (static_cast<unsigned long long>(im) << 32) | static_cast<uint32_t>(b);
+        hv = static_cast<unsigned long long>(im - lo) >> shift;
+      }
+      wave_append(b < B && hv < pd, key, c_lo, d_lo, cap_lo);
+      wave_append(b < B && hv == pd, key, c_b, d_b, cap_b);
     }
-    wave_append(b < B && hv < pd, key, c_lo, d_lo, cap_lo);
-    wave_append(b < B && hv == pd, key, c_b, d_b, cap_b);
+    return;
+  }
+  // groups of kGroup rows per wave: the wave ballots every row of the group,
+  // reserves the group's slots of each list with one counter bump, then writes
+  // (kGroup times fewer round trips to the counters than one bump per row;
+  // measured faster in the 256-thread blocks of the batched kernel)
+  constexpr int kGroup = 8;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int base = 0; base < B; base += kGroup * BS) {
+    unsigned long long key[kGroup], ml[kGroup], mb[kGroup];
+    uint32_t nl = 0u, nbd = 0u;
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int b = base + u * BS + static_cast<int>(threadIdx.x);
+      unsigned long long hv = 0ull;
+      key[u] = 0ull;
+      if (b < B) {
+        const uint32_t im = image(b);
+        key[u] = (static_cast<unsigned long long>(im) << 32) | static_cast<uint32_t>(b);
+        hv = static_cast<unsigned long long>(im - lo) >> shift;
+      }
+      ml[u] = __ballot(b < B && hv < pd);
+      mb[u] = __ballot(b < B && hv == pd);
+      nl += static_cast<uint32_t>(__popcll(ml[u]));
+      nbd += static_cast<uint32_t>(__popcll(mb[u]));
+    }
+    uint32_t sl = 0u, sb = 0u;
+    if (lane == 0) {
+      if (nl) sl = atomicAdd(c_lo, nl);
+      if (nbd) sb = atomicAdd(c_b, nbd);
+    }
+    sl = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sl), 0));
+    sb = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sb), 0));
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      if ((ml[u] >> lane) & 1ull) {
+        const uint32_t slot = sl + static_cast<uint32_t>(__popcll(ml[u] & below));
+        if (slot < cap_lo) d_lo[slot] = key[u];
+      }
+      if ((mb[u] >> lane) & 1ull) {
+        const uint32_t slot = sb + static_cast<uint32_t>(__popcll(mb[u] & below));
+        if (slot < cap_b) d_b[slot] = key[u];
+      }
+      sl += static_cast<uint32_t>(__popcll(ml[u]));
+      sb += static_cast<uint32_t>(__popcll(mb[u]));
+    }
   }
 }
 
