@@ -113,7 +113,8 @@ typedef struct {
   const float* task_params;  /* host */
   int32_t n_task_params;
   const float* sample_params;  /* host, CHAIN_CONTACT only, R*B*(n+1) floats */
-  int32_t n_debug_states;    /* record x_{t+1} of candidates 0..n_debug_states-1 (0 = off) */
+  int32_t n_debug_states;    /* record x_{t+1} of candidates 0..n_debug_states-1 under every
+                                randomised model (0 = off) */
   int32_t n_replicas;        /* R >= 1 randomised models per candidate (R > 1: CHAIN_CONTACT only);
                                 0 is read as 1 */
   int32_t sample_wor;        /* 0: tensor path indices drawn with replacement (Alg. 1);
@@ -134,7 +135,8 @@ typedef struct {
  *   mu, sigma  float [T][n]
  *   x0         float [d]              start state of the current replan
  *   action     float [n]
- *   X_dbg      float [T][d][n_debug_states] or NULL (model 0 when R > 1)
+ *   X_dbg      float [R][T][d][n_debug_states] or NULL: x_{t+1} of candidates 0..n_debug_states-1
+ *                                     under each of the R randomised models (R = 1 unless n_replicas > 1)
  *   entropy    float [K]              cost entropy H = -sum_b P_b log P_b, P = softmax(cost) over the
  *                                     finite costs, of every iteration of the last replan
  *                                     (written only when cfg.diagnostics bit 0 is set)

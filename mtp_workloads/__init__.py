@@ -128,9 +128,9 @@ def chain_task(seed: int, n_links: int) -> ChainTask:
                      goal_weight=f32(1.0), ctrl_weight=f32(1e-3))
 
 
-def chain_contact_task(seed: int, n_links: int) -> ChainTask:
+def chain_contact_task(seed: int, n_links: int, ground_y: float = -4.0) -> ChainTask:
     rng = np.random.default_rng(np.random.PCG64([seed, 4]))
-    ground = -4.0
+    ground = float(ground_y)
     target = np.array([rng.uniform(-0.5, 0.5) * n_links,
                        rng.uniform(ground + 1.0, ground + 5.0)], f32)
     return ChainTask(gravity=f32(9.81), masses=np.ones(n_links, f32),
@@ -209,10 +209,12 @@ def chain_contact_config(name="chain24_contact_c4", *, n_links=24, horizon=256,
                          n_layers=12, n_width=64, n_tensor=65536, n_gauss=4096,
                          n_elites=512, n_iters=6, interp=BSPLINE, bspline_degree=3,
                          seed=0, temperature=0.1, smoothing=0.0, dt=0.005,
-                         u_max=5.0, n_replicas=1) -> Config:
+                         u_max=5.0, n_replicas=1, ground_y=-4.0) -> Config:
     """Contact chain; with n_replicas = R every candidate is rolled out under R
-    randomised models (rows r*B + b of sample_params) and its cost averaged."""
-    task = chain_contact_task(seed, n_links)
+    randomised models (rows r*B + b of sample_params) and its cost averaged.
+    ground_y is the ground height below the pinned base (the workload's -4 m;
+    a raised ground lets short horizons reach it)."""
+    task = chain_contact_task(seed, n_links, ground_y)
     B = n_tensor + n_gauss
     return Config(name=name, dynamics=CHAIN_CONTACT, interp=interp, n_links=n_links,
                   state_dim=2 * n_links, ctrl_dim=n_links, horizon=horizon,

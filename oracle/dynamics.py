@@ -120,12 +120,15 @@ def contact_forces(phi, dphi, lengths, mu_f, task):
     return np.stack([ft, fn], axis=-1)
 
 
-def chain_accel(x, tau, task, masses, mu_f=None, contact=False):
-    x = np.asarray(x, dtype=np.float64)
+def chain_accel(x, tau, task, masses, mu_f=None, contact=False, dtype=np.float64):
+    """State derivative (dphi, ddphi).  `dtype` is float64 for the oracle; the
+    float32 setting exists only to measure how fast float32 rounding drifts
+    from the float64 trajectory (same formulas, other precision)."""
+    x = np.asarray(x, dtype=dtype)
     n = x.shape[-1] // 2
     phi, dphi = x[..., :n], x[..., n:]
-    lengths = np.asarray(task.lengths, dtype=np.float64)
-    tau = np.asarray(tau, dtype=np.float64)
+    lengths = np.asarray(task.lengths, dtype=dtype)
+    tau = np.asarray(tau, dtype=dtype)
     Q = tau - np.concatenate([tau[..., 1:], np.zeros_like(tau[..., :1])], axis=-1)
     if contact:
         F = contact_forces(phi, dphi, lengths, mu_f, task)      # (..., n, 2)
@@ -179,8 +182,9 @@ class Model:
     `sample_index` selects rows of the per-sample domain-randomisation table
     (link masses, friction) for the contact chain."""
 
-    def __init__(self, cfg, sample_index=None):
+    def __init__(self, cfg, sample_index=None, dtype=np.float64):
         self.cfg = cfg
+        self.dtype = dtype
         self.dt = float(cfg.dt)
         self.task = cfg.task
         if cfg.dynamics == W.POINT_MASS:
@@ -188,20 +192,20 @@ class Model:
         self.contact = cfg.dynamics == W.CHAIN_CONTACT
         n = cfg.n_links
         if self.contact:
-            sp = np.asarray(cfg.sample_params, dtype=np.float64)
+            sp = np.asarray(cfg.sample_params, dtype=dtype)
             if sample_index is not None:
                 sp = sp[np.asarray(sample_index)]
             self.masses = sp[:, :n]
             self.mu_f = sp[:, n]
         else:
-            self.masses = np.asarray(cfg.task.masses, dtype=np.float64)
+            self.masses = np.asarray(cfg.task.masses, dtype=dtype)
             self.mu_f = None
 
     def step(self, x, u):
         if self.cfg.dynamics == W.POINT_MASS:
             return point_mass_step(x, u, self.dt)
-        f = lambda xx, uu: chain_accel(xx, uu, self.task, self.masses, self.mu_f, self.contact)
-        return rk4_step(f, x, u, self.dt)
+        f = lambda xx, uu: chain_accel(xx, uu, self.task, self.masses, self.mu_f, self.contact, self.dtype)
+        return rk4_step(f, x, u, self.dtype(self.cfg.dt))
 
     def cost(self, x_next, u):
         if self.cfg.dynamics == W.POINT_MASS:

@@ -62,6 +62,10 @@ def load():
     path = lib_path()
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2505_01059_amd.build`")
+    # torch first: its HIP runtime then satisfies the library's libamdhip64.so.7.
+    # Loaded the other way round, torch (which asks for libamdhip64.so by file
+    # name) maps a second runtime, and its streams are foreign to the library's.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = c_void_p
     sig = {
@@ -364,7 +368,9 @@ def _buffer_views(b, cfg, workspace, n_debug):
         action=view(b.action, torch.float32, (n,)),
         entropy=view(b.entropy, torch.float32, (cfg.n_iters,)),
     )
-    out["X"] = view(b.X_dbg, torch.float32, (T, d, n_debug)) if n_debug > 0 else None
+    R = max(1, int(getattr(cfg, "n_replicas", 1)))
+    out["X_all"] = view(b.X_dbg, torch.float32, (R, T, d, n_debug)) if n_debug > 0 else None
+    out["X"] = out["X_all"][0] if n_debug > 0 else None
     out["ld_U"] = ld
     return out
 

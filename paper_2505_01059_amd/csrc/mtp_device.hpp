@@ -58,7 +58,7 @@ struct PlanDesc {
   int32_t* eidx;         // [E]
   float* ecost;          // [E]
   float* w;              // [E]
-  float* X;              // [T][d][n_dbg] or null
+  float* X;              // [R][T][d][n_dbg] or null (states of every randomised model)
   float* entropy;        // [K] cost entropy of each iteration of the last replan
   // time-sliced pair-lane rollout (long chains, launches of more waves than SIMDs); null when unused
   struct SegCtl* seg_ctl;
@@ -140,9 +140,22 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fm
 // sin and cos of an angle given in revolutions, with no reduction: for the
 // rollouts that keep their angles reduced, whose arguments stay within a few
 // revolutions of [0, 1), well inside the instructions' input domain.
+//
+// The pair from v_sin / v_cos is a little short on average: over 2^22
+// arguments in [0, 1), s^2 + c^2 - 1 has mean -6.5e-8 and standard deviation
+// 5.7e-8, and the error varies slowly with the argument.  The chain rollouts
+// build every link direction from such a pair, so a slow-moving link keeps
+// the same small length deficit step after step and the trajectory drifts
+// linearly from the exact one (24-link chain, 128 RK4 steps: 7.9e-5 of the
+// state scale against 1.4e-5 with correctly rounded sin / cos).  One Newton
+// step towards unit length, (s, c) *= 1 + (1 - s^2 - c^2) / 2, removes the
+// bias: 1.9e-5 after 128 steps, for five more instructions per pair.
 __device__ __forceinline__ void rev_sincos(float rev, float* s, float* c) {
-  *s = __builtin_amdgcn_sinf(rev);
-  *c = __builtin_amdgcn_cosf(rev);
+  const float sv = __builtin_amdgcn_sinf(rev);
+  const float cv = __builtin_amdgcn_cosf(rev);
+  const float h = fmaf(-sv, sv, fmaf(-cv, cv, 1.0f)) * 0.5f;
+  *s = fmaf(sv, h, sv);
+  *c = fmaf(cv, h, cv);
 }
 
 constexpr float kTwoPi = 6.283185307179586f;
@@ -868,8 +881,8 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
     }
     const float dx = ex - K.tx, dy = ey - K.ty;
     cost += fmaf(K.wg, fmaf(dx, dx, dy * dy), K.wu * uu);
-    if (rep == 0 && b < P.n_dbg) {
-      float* X = P.X + b;
+    if (b < P.n_dbg) {
+      float* X = P.X + static_cast<size_t>(rep) * P.T * P.d * P.n_dbg + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
@@ -1312,7 +1325,7 @@ __device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts
 template <int N, bool CONTACT>
 __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N>& K, int b, float (&ph)[N / 2],
                                            float (&om)[N / 2], float (&turn)[N / 2], float& cost, int t0, int t1,
-                                           bool record) {
+                                           bool record, int rep = 0) {
   constexpr int M = N / 2;
   const bool B = K.B;
   const float* tk = P.task;
@@ -1393,7 +1406,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
     const float dx = ex - tgx, dy = ey - tgy;
     cost += fmaf(wg, fmaf(dx, dx, dy * dy), wu * uu);
     if (record && b < P.n_dbg) {
-      float* X = P.X + b;
+      float* X = P.X + static_cast<size_t>(rep) * P.T * P.d * P.n_dbg + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
 #pragma unroll
       for (int i = 0; i < M; ++i) {
@@ -1444,7 +1457,7 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
     float ph[M], om[M], turn[M];
     pair_start<N>(P, K, ph, om, turn);
     float cost = 0.0f;
-    pair_steps<N, CONTACT>(P, K, b, ph, om, turn, cost, 0, P.T, rep == 0);
+    pair_steps<N, CONTACT>(P, K, b, ph, om, turn, cost, 0, P.T, true, rep);
     total += cost;
   }
   if (!B) P.cost[b] = finite_or_inf(R == 1 ? total : total / static_cast<float>(R));

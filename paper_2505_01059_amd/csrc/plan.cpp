@@ -152,7 +152,7 @@ Layout compute_layout(const mtp_config& c, bool plan) {
   L.eidx = take(static_cast<size_t>(c.n_elites) * 4);
   L.ecost = take(static_cast<size_t>(c.n_elites) * 4);
   L.w = take(static_cast<size_t>(c.n_elites) * 4);
-  L.X = c.n_debug_states > 0 ? take(T * d * static_cast<size_t>(c.n_debug_states) * 4) : 0;
+  L.X = c.n_debug_states > 0 ? take(static_cast<size_t>(R) * T * d * static_cast<size_t>(c.n_debug_states) * 4) : 0;
   L.seg_state = L.segmented ? take((n + n / 2 + 1) * groups * 64 * 4) : 0;
   L.overlap = plan && uses_gen_overlap(c);
   L.U2 = L.overlap ? take(T * n * L.ldU * 4) : 0;

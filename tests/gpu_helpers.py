@@ -6,8 +6,12 @@ Parity rules (float32 GPU vs float64 oracle on identical inputs):
     the oracle's selection is applied to the GPU's own costs);
   * controls U: |a - b| <= 1e-4 * max(|b|, u_max);
   * costs s: |a - b| <= 1e-4 * |b| except candidates the oracle flags as sitting
-    on a switching surface (obstacle boundary, contact onset, ill-conditioned
-    Akima weights), which are counted and reported;
+    on a switching surface (obstacle boundary, ill-conditioned Akima weights,
+    at most 1% of the tensor paths), which are counted and reported; contact
+    chains that reach the ground follow chain_contact_parity (tests/contact_parity.py);
+  * elite sets against the float64 costs: equal once the flagged candidates
+    and those within twice the largest observed cost error of either elite
+    boundary are left out;
   * mean / std refit from identical candidates and costs: 1e-4 relative to
     max(|b|, 1e-3 * (u_max - u_min)).
 """
@@ -15,6 +19,7 @@ import numpy as np
 import torch
 
 from oracle import planner as OP, interp as OI, dynamics as OD
+from tests import contact_parity as CP
 
 U_TOL = 1e-4
 S_TOL = 1e-4
@@ -51,26 +56,20 @@ def akima_ill_conditioned(cfg, I, Z):
 
 
 def switching_flags(cfg, x0, U, margin=1e-5):
-    """Candidates whose oracle rollout passes within `margin` of a discontinuity."""
+    """Candidates whose float64 rollout sits on a switching surface the cost
+    tolerance cannot cover: a point-mass trajectory within `margin` of an
+    obstacle boundary (the penalty indicator), or a contact-chain trajectory
+    that comes near the ground at all within the horizon (contact is checked
+    by chain_contact_parity instead)."""
     B = U.shape[0]
-    R = int(getattr(cfg, "n_replicas", 1))
-    if R > 1:                    # any of the randomised models may sit on the surface
-        sp = np.asarray(cfg.sample_params).reshape(R, -1, cfg.sample_params.shape[1])
-        out = np.zeros(B, bool)
-        for r in range(R):
-            out |= switching_flags(cfg.replace(n_replicas=1, sample_params=np.ascontiguousarray(sp[r])),
-                                   x0, U, margin)
-        return out
     if cfg.dynamics == 0:
         s, X = OP.rollout(cfg, x0, U, keep_states=True)
         m = OD.point_mass_obstacle_margin(cfg.task, X)                    # (B, T)
         return np.min(m, axis=1) < margin
     if cfg.dynamics == 2:
-        s, X = OP.rollout(cfg, x0, U, keep_states=True)
-        n = cfg.n_links
-        p = OD.chain_positions(X[..., :n], np.asarray(cfg.task.lengths, np.float64))
-        gap = np.abs(p[..., 1] - float(cfg.task.ground_y))                 # (B, T, n)
-        return np.min(gap.reshape(B, -1), axis=1) < margin
+        idx = np.arange(B)
+        _, X = CP.reference_trajectories(cfg, x0, U, idx)
+        return CP.first_contact(cfg, x0, U, idx, X) < cfg.horizon
     return np.zeros(B, bool)
 
 
@@ -84,26 +83,105 @@ def cost_check(s_gpu, s_ref, flagged):
 
 
 def assert_costs(cfg, s_gpu, s_ref, flagged):
-    """Cost parity.  Smooth models: every unflagged candidate within S_TOL.
-    Contact chain: the penalty contact switches on and off, and a float32 state
-    that crosses the ground one step earlier or later than the float64 one sends
-    the chaotic chain on another trajectory; the rule there is at least 90% of
-    unflagged candidates within S_TOL and all within 1e-2 relative."""
+    """Cost parity: every unflagged candidate within S_TOL, whatever the model."""
     bad = cost_check(s_gpu, s_ref, flagged)
-    if cfg.dynamics != 2:
-        assert not bad.any(), f"{bad.sum()} costs out of tolerance at {np.flatnonzero(bad)[:10]}"
-        return
-    rel = np.abs(np.asarray(s_gpu, np.float64) - s_ref) / np.maximum(np.abs(s_ref), 1e-12)
-    n = max(1, int((~flagged).sum()))
-    assert bad.sum() <= 0.1 * n, f"{bad.sum()} of {n} contact-chain costs out of tolerance"
-    assert np.all(rel[~flagged] < 1e-2), f"max contact-chain cost error {rel[~flagged].max():.2e}"
+    assert not bad.any(), f"{bad.sum()} costs out of tolerance at {np.flatnonzero(bad)[:10]}"
 
 
-def elite_margin_safe(s_ref, E):
-    srt = np.sort(s_ref)
-    if E >= len(srt):
-        return True
-    return (srt[E] - srt[E - 1]) > 2 * S_TOL * max(abs(srt[E]), 1e-6)
+def akima_excluded(cfg, ill):
+    """Akima paths left out of the control check; at most 1% of the tensor paths (and 2)."""
+    cap = max(2, cfg.n_tensor // 100)
+    assert ill.sum() <= cap, f"{ill.sum()} ill-conditioned Akima paths excluded (cap {cap})"
+    return ill
+
+
+def chain_contact_parity(cfg, x0, U, s_gpu, X_gpu, label, rows=None, one_step_rows=None, seed=0, workers=1):
+    """The contact-chain rules (tests/contact_parity.py) on the candidates `rows`
+    (default 0..nb-1).
+
+    U (nb, T, n) float64 of the GPU's float32 controls of those candidates,
+    s_gpu (nb,) their GPU costs, X_gpu (R, nb, T, d) their recorded states;
+    one_step_rows picks positions (into rows) for the one-step rule.  Returns
+    the mask of candidates whose whole cost is not compared free-running
+    (contact within the horizon, or a horizon beyond the free-running cut)."""
+    nb, T = U.shape[0], U.shape[1]
+    idx = np.arange(nb) if rows is None else np.asarray(rows)
+    s_gpu = np.asarray(s_gpu, np.float64)
+    s_ref, X_ref, t_c = CP.reference_and_contact(cfg, x0, U, idx, workers)
+    cut = np.minimum(t_c, min(T, CP.FREE_RUN_CUT))
+    # rule 1: the GPU's cost is the sum of its own states' step costs
+    S_g = CP.cost_from_states(cfg, X_gpu, U)
+    e1 = np.abs(S_g.sum(axis=1) - s_gpu) / np.maximum(np.abs(s_gpu), 1e-6)
+    assert np.all(e1 <= CP.COST_SUM_TOL), f"[{label}] GPU cost != sum over its states ({e1.max():.2e})"
+    # rule 2: free-running states and cost prefix before contact and the horizon cut
+    S_r = CP.cost_from_states(cfg, X_ref, U)
+    err_t = np.zeros((nb, T))
+    for r in range(X_gpu.shape[0]):
+        e = np.max(np.abs(X_gpu[r] - X_ref[r]), axis=-1) / CP.scale_of(X_ref[r])
+        err_t = np.maximum(err_t, e)
+    before = np.arange(T)[None, :] < cut[:, None]
+    worst = np.max(np.where(before, err_t, 0.0))
+    assert worst <= CP.S_TOL, f"[{label}] state error {worst:.2e} before contact / horizon cut"
+    Pg = np.where(before, S_g, 0.0).sum(axis=1)
+    Pr = np.where(before, S_r, 0.0).sum(axis=1)
+    ep = np.abs(Pg - Pr) / np.maximum(np.abs(Pr), 1e-6)
+    assert np.all(ep <= CP.S_TOL), f"[{label}] cost before contact off by {ep.max():.2e}"
+    # rule 3: candidates that stay clear of the ground within a horizon below the cut
+    free = cut >= T
+    cost_rel = np.abs(s_gpu - s_ref) / np.maximum(np.abs(s_ref), 1e-12)
+    assert np.all(cost_rel[free] <= CP.S_TOL), f"[{label}] contact-free cost off by {cost_rel[free].max():.2e}"
+    # rule 4: one step from the GPU's own state once free running stops
+    pos = np.arange(nb) if one_step_rows is None else np.asarray(one_step_rows)
+    pos = pos[cut[pos] < T]
+    n_onset = n_steps = 0
+    ratio = 0.0
+    if len(pos):
+        err, tol, onset, checked = CP.one_step_check(cfg, x0, U[pos], X_gpu[:, pos], idx[pos], cut[pos],
+                                                     np.random.default_rng(seed))
+        bad = checked & ~onset & (err > tol)
+        n_onset, n_steps = int(onset.sum()), int(checked.sum())
+        ratio = float(np.max(np.where(checked & ~onset, err / tol, 0.0)))
+        assert not bad.any(), (f"[{label}] {bad.sum()} steps from the GPU's own states break the one-step "
+                               f"rule (worst error / tolerance {ratio:.1f})")
+        assert n_onset <= max(2, 0.02 * n_steps), f"[{label}] {n_onset} of {n_steps} steps on the onset switch"
+    # report: free-running error against t (it is not asserted past the cut)
+    marks = sorted(set(np.linspace(0, T - 1, 9).astype(int)))
+    print(f"[{label}] contact chain: {int((t_c < T).sum())}/{nb} candidates reach the ground "
+          f"(first at step {int(t_c.min())}); state error before the cut {worst:.2e}; "
+          f"cost from own states {e1.max():.2e}; one-step rule {n_steps} steps, {n_onset} onset, "
+          f"worst error/tolerance {ratio:.2f}", flush=True)
+    print(f"[{label}]   free-running state error vs t: " +
+          " ".join(f"t{t}:{err_t[:, t].max():.1e}" for t in marks) +
+          f"; whole-cost error max {cost_rel.max():.1e}, >1e-4: {int((cost_rel > CP.S_TOL).sum())}", flush=True)
+    return ~free
+
+
+def elite_sets_agree(iE_gpu, s_gpu, s_ref, flagged, E):
+    """Alg. 2 top-E against the oracle's float64 costs.  With delta the largest
+    cost difference over the unflagged candidates (each already within 1e-4),
+    an unflagged candidate whose oracle cost lies more than 2 delta below (or
+    above) both elite boundaries, the GPU's and the oracle's, is an elite (or
+    not) on both sides.  So: leave out the flagged candidates and those inside
+    that band, and the two elite sets must be equal.  Returns the number of
+    distinct oracle costs among the unflagged candidates left out by the band."""
+    s_gpu = np.asarray(s_gpu, np.float64)
+    s_ref = np.where(np.isnan(s_ref), np.inf, s_ref)
+    flagged = np.asarray(flagged, bool)
+    iE_ref = OP.top_elites(s_ref, E)
+    if E >= len(s_ref):
+        assert set(iE_gpu) == set(iE_ref)
+        return 0
+    unf = ~flagged & np.isfinite(s_ref) & np.isfinite(s_gpu)
+    delta = float(np.max(np.abs(s_gpu - s_ref)[unf])) if unf.any() else 0.0
+    thr = [float(s_ref[iE_ref[-1]]), float(s_gpu[iE_gpu[-1]])]
+    lo, hi = min(thr), max(thr)
+    band = (s_ref >= lo - 2 * delta) & (s_ref <= hi + 2 * delta)
+    drop = flagged | band
+    a = {int(b) for b in iE_gpu if not drop[b]}
+    b_ = {int(b) for b in iE_ref if not drop[b]}
+    assert a == b_, f"elite sets differ outside the boundary band: {sorted(a ^ b_)[:10]}"
+    # exact ties (identical candidates, e.g. duplicated paths) count once
+    return int(np.unique(s_ref[band & ~flagged]).size)
 
 
 def refit_close(a, b, cfg):

@@ -235,3 +235,20 @@ def test_single_plan_overlap_buffer():
     big = c1.replace(n_tensor=16384, n_gauss=1024)          # 4 lanes x 17408 candidates = 272 workgroups
     for off in (c1.replace(n_iters=1), c1.replace(n_tensor=0, n_gauss=9216), big, W.c4()):
         assert N.workspace_bytes(off) == N.workspace_bytes(off.replace(sample_wor=1)), off.name
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before anything imported torch must not map a second
+    HIP runtime (torch's streams would be foreign to it): load() brings torch's
+    runtime in first."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2505_01059_amd as m\n"
+            "m.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "print(len({l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

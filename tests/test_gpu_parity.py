@@ -47,6 +47,17 @@ def configs():
                                               n_replicas=3),
         "contact24_r2": W.chain_contact_config(name="contact24_r2", n_tensor=100, n_gauss=28, horizon=32,
                                                n_elites=12, n_iters=2, n_replicas=2),
+        # the workload's ground is 4 m below the base, out of reach in the short horizons above;
+        # these raise it so that every candidate falls onto it mid-horizon (one-lane 4 and 7 links,
+        # the latter with two randomised models, and the 24-link pair lanes)
+        "contact4_ground": W.chain_contact_config(name="contact4_ground", n_links=4, n_tensor=150, n_gauss=42,
+                                                  horizon=80, n_layers=6, n_width=12, n_elites=12, n_iters=2,
+                                                  ground_y=-0.5),
+        "contact7_ground_r2": W.chain_contact_config(name="contact7_ground_r2", n_links=7, n_tensor=120,
+                                                     n_gauss=40, horizon=100, n_layers=6, n_width=16,
+                                                     n_elites=12, n_iters=2, n_replicas=2, ground_y=-0.5),
+        "contact24_ground": W.chain_contact_config(name="contact24_ground", n_tensor=100, n_gauss=28, horizon=100,
+                                                   n_elites=12, n_iters=2, ground_y=-2.0),
         # degenerate and extreme shapes: one step, ragged horizons, one waypoint per
         # layer, a straight Akima line, only the nominal, E = B, the largest graph,
         # a candidate tile plus one, one-lane chains with linear paths and with contact
@@ -141,7 +152,7 @@ def test_candidates_stage(name, torch_mod):
     _, _, U_ref = OP.candidates(cfg, mu.astype(np.float64), sg.astype(np.float64), r, k)
     U = H.to_oracle_U(b["U"])
     ok = H.u_close(U, U_ref, cfg.u_max)
-    ill = H.akima_ill_conditioned(cfg, I_ref, Z_ref)
+    ill = H.akima_excluded(cfg, H.akima_ill_conditioned(cfg, I_ref, Z_ref))
     rows_bad = ~np.all(ok, axis=(1, 2))
     G1 = cfg.n_gauss - 1
     rows_bad[G1:G1 + cfg.n_tensor] &= ~ill
@@ -150,11 +161,17 @@ def test_candidates_stage(name, torch_mod):
     plan.close()
 
 
+def recorded_states(b):
+    """(R, nd, T, d) float64 from the plan's debug-state buffer."""
+    return b["X_all"].cpu().numpy().transpose(0, 3, 1, 2).astype(np.float64)
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_rollout_stage(name, torch_mod):
     cfg = CONFIGS[name]
     _log(f"[rollout] {name}")
-    nd = min(8, cfg.n_samples)
+    contact = cfg.dynamics == W.CHAIN_CONTACT
+    nd = cfg.n_samples if contact else min(8, cfg.n_samples)
     plan = make_plan(cfg, n_debug_states=nd)
     mu, sg = random_state(cfg, 2)
     _, _, U_ref = OP.candidates(cfg, mu.astype(np.float64), sg.astype(np.float64), 1, 0)
@@ -166,14 +183,16 @@ def test_rollout_stage(name, torch_mod):
     plan.run_stage(1, 1, 0)
     torch_mod.cuda.synchronize()
     s = b["cost"].cpu().numpy()
+    if contact:
+        # every candidate recorded: the contact-chain rules cover costs and states
+        H.chain_contact_parity(cfg, x0, U32, s, recorded_states(b), f"rollout {name}")
+        plan.close()
+        return
     s_ref, X_ref = OP.rollout(cfg, x0, U32, keep_states=True)
     flagged = H.switching_flags(cfg, x0, U32)
-    bad = H.cost_check(s, s_ref, flagged)
     rel = np.abs(s - s_ref) / np.maximum(np.abs(s_ref), 1e-12)
     _log(f"  cost rel err max {rel[~flagged].max():.3e} median {np.median(rel):.3e}; flagged {flagged.sum()}")
     H.assert_costs(cfg, s, s_ref, flagged)
-    if cfg.dynamics == 2:
-        flagged = flagged | bad                        # divergent contact trajectories are not compared
     X = b["X"].cpu().numpy().transpose(2, 0, 1).astype(np.float64)        # (nd, T, d)
     Xr = X_ref[:nd]
     okx = np.abs(X - Xr) <= 1e-4 * np.maximum(1.0, np.abs(Xr))
@@ -395,11 +414,12 @@ def test_teacher_forced_replan(name, torch_mod):
     iteration from the GPU's own input mean/std and every stage is compared."""
     cfg = CONFIGS[name]
     _log(f"[replan] {name}")
-    plan = make_plan(cfg)
+    contact = cfg.dynamics == W.CHAIN_CONTACT
+    plan = make_plan(cfg, n_debug_states=cfg.n_samples if contact else 0)
     x0 = W.initial_state(cfg, seed=7)
     mu, sg = random_state(cfg, 8)
     r = 11
-    margin_events = 0
+    band_total = 0
     for k in range(cfg.n_iters):
         plan.set_state(mu, sg, r)
         plan.set_x0(x0)
@@ -408,29 +428,32 @@ def test_teacher_forced_replan(name, torch_mod):
         b = plan.buffers()
         ref = OP.iterate(cfg, x0, mu.astype(np.float64), sg.astype(np.float64), r, k)
         assert np.array_equal(b["I"].cpu().numpy().T.astype(np.int64), ref["I"])
-        U = H.to_oracle_U(b["U"])
         s = b["cost"].cpu().numpy()
         iE = b["elite_idx"].cpu().numpy()
-        flagged = H.switching_flags(cfg, x0, ref["U"])
-        ill = H.akima_ill_conditioned(cfg, ref["I"], ref["Z"])
+        if contact:
+            U = H.to_oracle_U(b["U"])
+            assert H.u_close(U, ref["U"], cfg.u_max).all()
+            flagged = H.chain_contact_parity(cfg, x0, U, s, recorded_states(b), f"replan {name} k={k}")
+        else:
+            flagged = H.switching_flags(cfg, x0, ref["U"])
+        ill = H.akima_excluded(cfg, H.akima_ill_conditioned(cfg, ref["I"], ref["Z"]))
         G1 = cfg.n_gauss - 1
         flagged[G1:G1 + cfg.n_tensor] |= ill
         H.assert_costs(cfg, s, ref["s"], flagged)
-        if cfg.dynamics == 2:
-            flagged = flagged | H.cost_check(s, ref["s"], flagged)
         # the oracle's selection on the GPU's own costs is bit-exact
         assert np.array_equal(iE, OP.top_elites(s.astype(np.float64), cfg.n_elites))
-        if H.elite_margin_safe(ref["s"], cfg.n_elites) and not flagged.any():
-            assert set(iE) == set(ref["iE"])
-        else:
-            margin_events += 1
+        # against the oracle's own costs: equal sets outside the flagged candidates and the boundary band
+        band = H.elite_sets_agree(iE, s, ref["s"], flagged, cfg.n_elites)
+        band_total += band
+        _log(f"  k={k}: flagged {int(flagged.sum())}, left out at the elite boundary {band}")
+        assert band <= max(4, cfg.n_elites // 4), f"{band} candidates within the elite boundary band"
         mu2, sg2, _ = OP.refit(ref["U"], s.astype(np.float64), iE, mu.astype(np.float64),
                                sg.astype(np.float64), cfg)
         assert H.refit_close(b["mu"].cpu().numpy(), mu2, cfg).all()
         assert H.refit_close(b["sigma"].cpu().numpy(), sg2, cfg).all()
         mu = b["mu"].cpu().numpy().copy()
         sg = b["sigma"].cpu().numpy().copy()
-    _log(f"  margin events {margin_events}")
+    _log(f"  elite boundary band total {band_total}")
     plan.close()
 
 
