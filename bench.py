@@ -4,9 +4,12 @@
 A step is one replan: n_iters CEM iterations of candidate generation (Philox
 graph + paths + spline, Gaussian samples), fused rollout + cost, top-E and
 softmax refit, replayed from a captured hipGraph with every input already in
-HBM.  The default workload is the 7-link pendulum chain with Akima
-interpolation (9216 candidates = 8192 tensor + 1024 Gaussian, horizon 128,
-8x32 graph, 128 elites, 8 iterations).
+HBM.  The default workload is the largest single-GPU configuration: the
+24-link chain with ground contact and per-candidate domain randomisation
+(69632 candidates = 65536 tensor + 4096 Gaussian, horizon 256, 12x64 graph,
+512 elites, 6 iterations, cubic B-spline).  The 7-link chain (9216
+candidates, horizon 128, Akima) is timed after it and reported under
+"secondary".
 
 Prints one JSON line:
   value        rollout steps/s = candidates x horizon x iterations per replan,
@@ -14,7 +17,10 @@ Prints one JSON line:
   roofline     the rollout kernel's algorithmic FP32 flops per launch over its
                mean launch time (HIP events around every rollout launch on the
                plan's stream, in a second timed pass launching kernels one by one);
-  cpu_baseline the FP64 oracle timed on one CEM iteration of the same workload.
+  cpu_baseline the FP64 oracle on one CEM iteration of the workload (batches
+               above 20000 candidates: a 1024-candidate subset), one thread;
+               cpu_baseline_all_cores the same sample with its rollouts split
+               over every host core.
 """
 import argparse
 import json
@@ -55,35 +61,58 @@ def cpu_model():
     return platform.processor()
 
 
+def kernel_sources_digest():
+    """SHA-256 over the HIP sources of the library: a counter summary taken from
+    other sources no longer describes the kernels that run."""
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2505_01059_amd", "csrc", "*"))):
+        if path.endswith((".hip", ".hpp", ".cpp")):
+            with open(path, "rb") as f:
+                h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profiles(workload):
-    """HBM bytes per rollout launch from the committed PMC summary, if it is current."""
+    """HBM bytes per rollout launch from the committed PMC summary, if it was
+    taken from the kernel sources that are built now (else None)."""
     path = os.path.join(ROOT, "profiles", f"rollout_{workload}_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             rec = json.load(f)
-        return rec.get("bytes_per_launch")
     except (OSError, ValueError):
         return None
+    if rec.get("kernel_sources_sha") != kernel_sources_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def baseline_sample(cfg):
+    """The oracle's bounded sample: the whole batch, or for batches above 20000
+    candidates the first 512 local samples, 511 tensor paths and the nominal
+    (1024 candidates) at the same horizon and model."""
+    import numpy as np
+    if cfg.n_samples <= 20000:
+        return cfg
+    G = min(cfg.n_gauss, 513)
+    sub = cfg.replace(n_tensor=1024 - G, n_gauss=G, n_elites=min(cfg.n_elites, 64))
+    if cfg.sample_params is not None:
+        B, R = cfg.n_samples, max(1, int(cfg.n_replicas))
+        rows = [cfg.sample_params[r * B:r * B + sub.n_samples] for r in range(R)]
+        sub = sub.replace(sample_params=np.concatenate(rows, axis=0))
+    return sub
 
 
 def cpu_baseline(cfg, x0, min_seconds=10.0, max_iters=100000):
     """Oracle (FP64 NumPy, as written) on CEM iterations of the same workload, one
     thread: whole iterations until at least min_seconds have passed."""
-    import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import planner as OP
     mu, sg = OP.initial_distribution(cfg)
-    sub = cfg
-    if cfg.n_samples > 20000:
-        # bounded sample: the first 256 candidates of the batch, same horizon and model
-        G = min(cfg.n_gauss, 32)
-        sub = cfg.replace(n_tensor=256 - G, n_gauss=G, n_elites=min(cfg.n_elites, 16))
-        if cfg.sample_params is not None:
-            B, R = cfg.n_samples, max(1, int(cfg.n_replicas))
-            rows = [cfg.sample_params[r * B:r * B + sub.n_samples] for r in range(R)]
-            sub = sub.replace(sample_params=np.concatenate(rows, axis=0))
+    sub = baseline_sample(cfg)
     iters = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
@@ -99,6 +128,43 @@ def cpu_baseline(cfg, x0, min_seconds=10.0, max_iters=100000):
         "value": steps / dt, "unit": "rollout steps/s", "cores": 1, "kind": "oracle",
         "sample": f"{iters} CEM iteration(s), {sub.n_samples} candidates x {sub.horizon} steps each "
                   f"(FP64 NumPy oracle, 1 thread, {dt:.1f} s; host {cpu_model()}, nproc {os.cpu_count()})",
+    }
+
+
+def _oracle_rollout_chunk(args):
+    cfg, x0, U, idx = args
+    from threadpoolctl import threadpool_limits
+    from oracle import planner as OP
+    with threadpool_limits(limits=1):
+        return OP.rollout(cfg, x0, U, sample_index=idx)
+
+
+def cpu_baseline_all_cores(cfg, x0):
+    """The oracle's rollouts of one CEM iteration of the same sample, split over
+    every host core (spawned worker processes, one thread each); candidates,
+    top-E and refit stay in this process."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import planner as OP
+    sub = baseline_sample(cfg)
+    cores = os.cpu_count() or 1
+    mu, sg = OP.initial_distribution(sub)
+    parts = np.array_split(np.arange(sub.n_samples), cores)
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_oracle_rollout_chunk, [(sub, x0, np.zeros((1, 1, sub.ctrl_dim)), np.array([0]))] * cores))
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            _, _, U = OP.candidates(sub, mu, sg, 0, 0)
+            s = np.concatenate(list(ex.map(_oracle_rollout_chunk, [(sub, x0, U[p], p) for p in parts])))
+            iE = OP.top_elites(s, sub.n_elites)
+            OP.refit(U, s, iE, mu, sg, sub)
+            dt = time.perf_counter() - t0
+    return {
+        "value": sub.n_samples * sub.horizon / dt, "unit": "rollout steps/s", "cores": cores, "kind": "oracle",
+        "sample": f"1 CEM iteration, {sub.n_samples} candidates x {sub.horizon} steps, rollouts split over "
+                  f"{cores} processes ({dt:.1f} s; host {cpu_model()})",
     }
 
 
@@ -124,7 +190,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="chain7_akima", choices=sorted(workloads()))
+    ap.add_argument("--workload", default="chain24_contact_bspline", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, nargs="+", default=[2000.0],
                     help="serving: Poisson request rates (req/s) to run, one after another")
@@ -141,41 +207,69 @@ def main():
               "(instances shard across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
     import mtp_workloads as W
-    import paper_2505_01059_amd as mtp
-    from paper_2505_01059_amd import roofline as RF
 
     cfg = workloads()[args.workload]()
     if isinstance(cfg, tuple):
         return bench_serve(args, cfg[1])
     if isinstance(cfg, list):
         return bench_mix(args, cfg)
+    rec, plan_info = time_plan(cfg, args.workload, args.steps, args.warmup)
+    out = {
+        "metric": METRIC, "value": rec["rollout_steps_per_s"], "unit": "rollout steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_replan"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": plan_info,
+        "replans_per_s": rec["replans_per_s"],
+        "latency_ms_p50": rec["latency_ms_p50"], "latency_ms_p99": rec["latency_ms_p99"],
+        "stage_ms_per_launch": rec["stage_ms_per_launch"],
+        "roofline": rec["roofline"],
+    }
+    if args.workload == "chain24_contact_bspline":
+        # the 7-link chain of the other single-instance configuration, as extra keys
+        sec, sec_info = time_plan(W.c1(), "chain7_akima", max(args.steps, 20), args.warmup)
+        sec["config"] = sec_info
+        out["secondary"] = {"chain7_akima": sec}
+    if not args.no_cpu_baseline:
+        x0 = W.initial_state(cfg)
+        print("[bench] timing the oracle on the host (1 thread)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, x0)
+        print("[bench] timing the oracle on the host (all cores)", file=sys.stderr, flush=True)
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(cfg, x0)
+    print(json.dumps(out), flush=True)
+
+
+def time_plan(cfg, name, steps, warmup):
+    """Replans of one plan from its captured graph: wall-clock throughput, per-replan
+    latency (replan + action read-back) and per-stage kernel times from HIP events."""
+    import torch
+    import mtp_workloads as W
+    import paper_2505_01059_amd as mtp
+    from paper_2505_01059_amd import roofline as RF
     x0 = W.initial_state(cfg)
     dev = torch.device("cuda:0")
     plan = mtp.Plan(cfg, device=dev)
     x0_dev = torch.tensor(x0, device=dev)
     B, T, K = cfg.n_samples, cfg.horizon, cfg.n_iters
-    print(f"[bench] workload {args.workload}: B={B} T={T} n={cfg.ctrl_dim} K={K}", file=sys.stderr, flush=True)
+    print(f"[bench] workload {name}: B={B} T={T} n={cfg.ctrl_dim} K={K}", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.replan(x0_dev, shift=1)
     torch.cuda.synchronize()
 
     # timed region: back-to-back replans from the captured graph
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.replan(x0_dev, shift=1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = wall / args.steps * 1e3
-    value = B * T * K * args.steps / wall
+    ms_per_step = wall / steps * 1e3
     print(f"[bench] {ms_per_step:.3f} ms/replan", file=sys.stderr, flush=True)
 
     # latency: submit a replan and wait for its action, per replan
     lat = []
-    for _ in range(max(args.steps, 30)):
+    for _ in range(max(steps, 30 if B * T < 10 ** 7 else 10)):
         t = time.perf_counter()
         plan.replan(x0_dev, shift=1)
         plan.action()
@@ -186,7 +280,7 @@ def main():
 
     # kernel timing pass: HIP events around every stage launch on the plan's stream
     plan.set_stage_timing(True)
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.replan(x0_dev, shift=1)
     torch.cuda.synchronize()
     st = plan.stage_times()
@@ -196,7 +290,7 @@ def main():
     n_obs = len(cfg.task.obstacles) if cfg.dynamics == 0 else 0
     flops_step = RF.flops_per_sample_step(cfg.dynamics, cfg.n_links, n_obs)
     achieved = B * T * flops_step / (roll_avg_ms * 1e-3) / 1e12
-    traffic = traffic_from_profiles(args.workload)
+    traffic = traffic_from_profiles(name)
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": RF.PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / RF.PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
@@ -204,28 +298,17 @@ def main():
         "flops_per_sample_step": flops_step, "launch_ms": round(roll_avg_ms, 4),
         "frac_of_unpacked_fp32": round(achieved / RF.PEAK_FP32_UNPACKED_TFLOPS, 4),
     }
-    stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items()}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "rollout steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "candidates": B, "tensor": cfg.n_tensor,
-                   "gaussian": cfg.n_gauss, "horizon": T, "ctrl_dim": cfg.ctrl_dim,
-                   "layers": cfg.n_layers, "width": cfg.n_width, "elites": cfg.n_elites,
-                   "iters": K, "interp": W.INTERP_NAMES[int(cfg.interp)],
-                   "overlap_tensor_paths": plan.draws_ahead()},
-        "replans_per_s": args.steps / wall,
-        "latency_ms_p50": round(p50, 4), "latency_ms_p99": round(p99, 4),
-        "stage_ms_per_launch": stage_ms,
-        "roofline": roofline,
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, x0)
-    print(json.dumps(out), flush=True)
+    info = {"workload": name, "candidates": B, "tensor": cfg.n_tensor,
+            "gaussian": cfg.n_gauss, "horizon": T, "ctrl_dim": cfg.ctrl_dim,
+            "layers": cfg.n_layers, "width": cfg.n_width, "elites": cfg.n_elites,
+            "iters": K, "interp": W.INTERP_NAMES[int(cfg.interp)],
+            "overlap_tensor_paths": plan.draws_ahead()}
+    rec = {"rollout_steps_per_s": B * T * K * steps / wall, "ms_per_replan": ms_per_step,
+           "replans_per_s": steps / wall, "latency_ms_p50": round(p50, 4), "latency_ms_p99": round(p99, 4),
+           "stage_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items()},
+           "roofline": roofline}
     plan.close()
+    return rec, info
 
 
 def mix_flops(cfgs):
@@ -327,23 +410,36 @@ def bench_mix(args, cfgs):
 
 
 def bench_serve(args, robots):
-    """Poisson replan requests from many robots through the continuous-batching server."""
+    """Poisson replan requests from many robots through the continuous-batching
+    server, in closed loop: every returned control moves its robot one step of
+    its model (float64, on the host), and the robot's next request plans from
+    the state it reached (the receding horizon of Alg. 2)."""
     import numpy as np
     import torch
     import mtp_workloads as W
     import paper_2505_01059_amd as mtp
     dev = torch.device("cuda:0")
-    x0s = [W.initial_state(c, seed=i) for i, c in enumerate(robots)]
-    pool = int(args.budget_gb * (1 << 30))
-    srv = mtp.Server(robots, pool_bytes=pool, iters_per_launch=1, max_inflight=2, device=dev)
+    state = {i: W.initial_state(c, seed=i).astype(np.float64) for i, c in enumerate(robots)}
+    budget = int(args.budget_gb * (1 << 30))
+    srv = mtp.Server(budget, len(robots), iters_per_launch=1, max_inflight=2, device=dev, robots=robots)
     work = {i: c.n_samples * c.horizon * c.n_iters for i, c in enumerate(robots)}
+    steps_taken = {i: 0 for i in range(len(robots))}
+
+    def deliver(done):
+        for d in done:
+            r = d["robot"]
+            state[r] = mtp.plant_step(robots[r], state[r], d["u"])
+            steps_taken[r] += 1
+
     # warm up: one request per robot
     for i in range(len(robots)):
-        srv.submit(i, x0s[i], shift=0)
+        srv.submit(i, state[i].astype(np.float32), shift=0)
     n = 0
     while n < len(robots):
         srv.pump(wait_us=1000)
-        n += len(srv.poll())
+        got = srv.poll()
+        deliver(got)
+        n += len(got)
     results = []
     for rate in args.rate:
         rng = np.random.Generator(np.random.PCG64(0))
@@ -364,10 +460,13 @@ def bench_serve(args, robots):
         while True:
             now = srv.now_ns()
             while i_next < len(arrivals) and arrivals[i_next] <= now:
-                srv.submit(int(who[i_next]), x0s[int(who[i_next])], shift=1, t_arrival_ns=int(arrivals[i_next]))
+                r = int(who[i_next])
+                srv.submit(r, state[r].astype(np.float32), shift=1, t_arrival_ns=int(arrivals[i_next]))
                 i_next += 1
             srv.pump(wait_us=200)
-            done += srv.poll()
+            got = srv.poll()
+            deliver(got)
+            done += got
             if now - last_print > 2_000_000_000:
                 st = srv.stats()
                 print(f"[bench]   t={(now - t0) / 1e9:5.1f}s done={len(done)} queued={st['queued']} "
@@ -389,17 +488,19 @@ def bench_serve(args, robots):
         # drain what is left before the next rate
         while srv.stats()["queued"] + srv.stats()["in_flight"] > 0:
             srv.pump(wait_us=1000)
-            srv.poll()
+            deliver(srv.poll())
     main_r = results[0]
     out = {
         "metric": METRIC, "value": main_r["rollout_steps_per_s"], "unit": "rollout steps/s", "n_gpus": 1,
         "steps": len(args.rate), "warmup": 1, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve512", "robots": len(robots), "budget_gb": args.budget_gb,
-                   "iters_per_launch": 1, "max_inflight": 2, "duration_s": args.duration},
+                   "iters_per_launch": 1, "max_inflight": 2, "duration_s": args.duration,
+                   "closed_loop": True},
         "replans_per_s": main_r["replans_per_s"], "latency_ms_p50": main_r["latency_ms_p50"],
         "latency_ms_p99": main_r["latency_ms_p99"], "load_sweep": results,
         "resident_mb": srv.stats()["resident_bytes"] / (1 << 20),
+        "plant_steps_taken": int(sum(steps_taken.values())),
     }
     srv.close()
     print(json.dumps(out), flush=True)

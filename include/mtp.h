@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define MTP_ABI_VERSION 2
+#define MTP_ABI_VERSION 3
 
 typedef enum {
   MTP_OK = 0,
@@ -159,6 +159,11 @@ mtp_status mtp_validate_config(const mtp_config* cfg, char* why, size_t why_len)
  * candidates, costs, elites.  A server lends this much from its pool to every
  * replan in flight; 0 if cfg is invalid. */
 size_t mtp_transient_bytes(const mtp_config* cfg);
+
+/* Bytes of the resident buffers of one instance (control block, start state,
+ * warm-start mean / std, tables, per-sample parameters): what a server takes
+ * from its pool for as long as the robot is registered; 0 if cfg is invalid. */
+size_t mtp_resident_bytes(const mtp_config* cfg);
 
 /* Validate cfg, lay the plan out in the caller's workspace, upload its tables
  * (spline basis, task and sample parameters) on `hip_stream` (NULL = default
@@ -284,20 +289,31 @@ mtp_status mtp_batch_destroy(mtp_batch* b);
 const char* mtp_batch_last_error(const mtp_batch* b);
 
 /* ---------------------------------------------------------------- serving
- * A request loop for many robots.  Each robot has a fixed config and keeps its
- * warm-start mean/std, start state, tables and replan counter resident on the
- * device.  A request (robot, x0, shift) waits in an arrival-ordered queue; it is
- * admitted when its robot has no request in flight and a transient slab (graph,
- * paths, candidates, costs, elites) fits in the device-memory pool, whose size is
- * the HBM budget.  Admitted requests run as continuous batches: every launch is
- * one persistent batched launch that advances each admitted request by up to
+ * A request loop for many robots: the receding-horizon outer loop of Alg. 2
+ * (replan from the current state, send the first control, shift the warm
+ * start one step) run for a fleet, with continuous batching.
+ *
+ * Memory.  The server owns one caller-supplied device arena
+ * (mtp_server_workspace_bytes): launch tables for max_robots slots and a pool
+ * of hbm_budget_bytes.  A robot's resident buffers (warm-start mean / std,
+ * start state, tables, replan counter) are taken from the pool when it is
+ * added and given back when it is removed; every admitted request borrows a
+ * transient slab (graph, paths, candidates, costs, elites) from the same pool
+ * until its result is delivered.  The server never calls hipMalloc.
+ *
+ * Requests.  A request (robot, x0, shift) waits in an arrival-ordered queue; it
+ * is admitted when its robot has no request in flight and its slab fits in the
+ * pool.  Admitted requests run as continuous batches: every launch is one
+ * persistent batched launch that advances each admitted request by up to
  * iters_per_launch CEM iterations from wherever it stands, so requests that
  * arrive while others are on the GPU join at the next iteration boundary.  Up
  * to max_inflight launches are queued on the stream ahead of the GPU.  A
  * request's result is bit-identical to the same replan run alone.
  *
- * Threading: submit, poll and stats may be called from any thread; pump from
- * one thread at a time.  Clock: mtp_server_now_ns (steady, nanoseconds). */
+ * Threading: submit, poll and stats may be called from any thread; pump, add,
+ * remove and get_robot_state from one thread at a time (add and
+ * get_robot_state synchronise the server's stream).  Clock: mtp_server_now_ns
+ * (steady, nanoseconds). */
 typedef struct mtp_server mtp_server;
 
 typedef struct {
@@ -309,27 +325,50 @@ typedef struct {
   uint64_t t_done_ns;        /* when pump saw the result on the host */
   uint32_t replan_idx;       /* the robot's replan counter used */
   int32_t n;                 /* valid entries of u (ctrl_dim <= 32) */
-  float u[32];
+  float u[32];               /* u*: first control of the best candidate of the last iteration */
 } mtp_completion;
 
 typedef struct {
   uint64_t submitted, admitted, completed, launches, deferred_for_budget;
+  uint64_t dropped;          /* requests of removed robots, never delivered */
   uint64_t pool_bytes, pool_in_use, pool_peak, resident_bytes;
-  int32_t queued, in_flight;
+  int32_t queued, in_flight, robots, pad;
 } mtp_server_stats;
 
-size_t mtp_server_workspace_bytes(const mtp_config* robots, int32_t n_robots, size_t pool_bytes,
-                                  int32_t iters_per_launch);
-mtp_status mtp_server_create(const mtp_config* robots, int32_t n_robots, void* d_workspace, size_t ws_bytes,
-                             size_t pool_bytes, int32_t iters_per_launch, int32_t max_inflight, void* hip_stream,
-                             mtp_server** out);
+/* Device arena for a server: launch tables for max_robots robots and a queue of
+ * queue_items items (0: 4096 per robot), x0 staging, and the pool of
+ * hbm_budget_bytes.  0 if an argument is invalid. */
+size_t mtp_server_workspace_bytes(size_t hbm_budget_bytes, int32_t max_robots, uint32_t queue_items);
+/* Create an empty server on the caller's arena d_workspace (256-byte aligned,
+ * at least mtp_server_workspace_bytes) and stream; iters_per_launch >= 1,
+ * 1 <= max_inflight <= 8. */
+mtp_status mtp_server_create(size_t hbm_budget_bytes, int32_t max_robots, uint32_t queue_items,
+                             int32_t iters_per_launch, int32_t max_inflight, void* d_workspace, size_t ws_bytes,
+                             void* hip_stream, mtp_server** out);
 /* Same scheduler driving a host-only stand-in for the device (no GPU needed): a
  * launch takes 20 us plus ns_per_sample_step per candidate-step it advances and
  * returns zero actions.  For testing admission, budget and batching logic. */
-mtp_status mtp_server_create_simulated(const mtp_config* robots, int32_t n_robots, size_t pool_bytes,
+mtp_status mtp_server_create_simulated(size_t hbm_budget_bytes, int32_t max_robots, uint32_t queue_items,
                                        int32_t iters_per_launch, int32_t max_inflight, double ns_per_sample_step,
                                        mtp_server** out);
-/* Queue a replan of `robot` from host state h_x0 (state_dim floats, copied). */
+/* Register a robot (its planner config, Alg. 2 inputs; copied): takes its
+ * resident buffers from the pool, uploads its tables and initialises mean =
+ * box centre, std = sigma_init, replan counter 0.  Writes its id.  MTP_ERR_BUSY
+ * if every slot is taken, the pool cannot hold its resident buffers or the
+ * launch queue cannot hold its items; MTP_ERR_UNSUPPORTED above ctrl_dim 32
+ * or state_dim 64. */
+mtp_status mtp_server_add_robot(mtp_server* s, const mtp_config* cfg, int32_t* robot_id);
+/* Unregister a robot: its queued requests are dropped, a request already on the
+ * GPU finishes but its completion is dropped, and its memory returns to the
+ * pool when that launch has been retired.  The id may then be reused. */
+mtp_status mtp_server_remove_robot(mtp_server* s, int32_t robot);
+/* A robot's warm-start mean and std (device arrays of T*n floats, either may be
+ * NULL) and its next replan index, for checkpoints and checks; MTP_ERR_BUSY
+ * while it has a request admitted. */
+mtp_status mtp_server_get_robot_state(mtp_server* s, int32_t robot, float* d_mu, float* d_sigma,
+                                      uint32_t* replan_idx);
+/* Queue a replan of `robot` from host state h_x0 (state_dim floats, copied),
+ * shifting its warm start by `shift` steps first (Alg. 2's receding horizon). */
 mtp_status mtp_server_submit(mtp_server* s, int32_t robot, const float* h_x0, int32_t shift,
                              uint64_t t_arrival_ns, uint64_t* ticket);
 /* One scheduling round: retire finished launches (their completed requests become
@@ -337,11 +376,21 @@ mtp_status mtp_server_submit(mtp_server* s, int32_t robot, const float* h_x0, in
  * there is work and room.  If wait_us > 0 and nothing could be retired, block up to
  * wait_us for the oldest launch first. */
 mtp_status mtp_server_pump(mtp_server* s, int32_t wait_us, int32_t* n_completed);
+/* Completed requests (at most max), oldest first. */
 mtp_status mtp_server_poll(mtp_server* s, mtp_completion* out, int32_t max, int32_t* n_out);
 mtp_status mtp_server_get_stats(const mtp_server* s, mtp_server_stats* out);
 uint64_t mtp_server_now_ns(void);
 mtp_status mtp_server_destroy(mtp_server* s);
 const char* mtp_server_last_error(const mtp_server* s);
+
+/* Host-side plant of a robot, for closing the receding-horizon loop of Alg. 2
+ * around a server or plan (execute u*, replan from the state it leads to): one
+ * step x_{t+1} = f(x_t, u_t) of cfg's model in float64 on the host (no device
+ * work), h_x and h_x_next state_dim doubles, h_u ctrl_dim floats.  The point
+ * mass takes a semi-implicit Euler step, the chains a classical RK4 step with
+ * the control held; the contact chain uses the first row of sample_params as
+ * its masses and friction. */
+mtp_status mtp_plant_step(const mtp_config* cfg, const double* h_x, const float* h_u, double* h_x_next);
 
 /* Chain lengths the rollout kernel is instantiated for (writes up to `cap`, returns the count). */
 int32_t mtp_supported_chain_links(int32_t* out, int32_t cap);

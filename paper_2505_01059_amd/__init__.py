@@ -6,6 +6,7 @@ stream; every step of a replan runs in the library's kernels.  There is no
 CPU fallback: if the library is missing, `load()` raises.
 """
 from ._native import (  # noqa: F401
-    MtpError, load, Plan, Batch, Server, config_struct, task_params_of, lib_path,
+    MtpError, load, Plan, Batch, Server, config_struct, task_params_of, lib_path, resident_bytes,
+    transient_bytes, plant_step,
     STAGE_CANDIDATES, STAGE_ROLLOUT, STAGE_TOPK, STAGE_UPDATE, STAGE_ALL,
 )

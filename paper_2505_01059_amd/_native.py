@@ -27,7 +27,7 @@ class MtpError(RuntimeError):
 
 
 STAGE_CANDIDATES, STAGE_ROLLOUT, STAGE_TOPK, STAGE_UPDATE, STAGE_ALL = range(5)
-MTP_ABI_VERSION = 2
+MTP_ABI_VERSION = 3
 
 
 class mtp_config(ctypes.Structure):
@@ -71,6 +71,7 @@ def load():
     sig = {
         "mtp_workspace_bytes": (c_size_t, [P]),
         "mtp_transient_bytes": (c_size_t, [P]),
+        "mtp_resident_bytes": (c_size_t, [P]),
         "mtp_validate_config": (c_int32, [P, c_char_p, c_size_t]),
         "mtp_plan_create": (c_int32, [P, P, c_size_t, P, POINTER(P)]),
         "mtp_replan": (c_int32, [P, P, c_int32]),
@@ -102,10 +103,14 @@ def load():
         "mtp_batch_set_graph_mode": (c_int32, [P, c_int32]),
         "mtp_batch_destroy": (c_int32, [P]),
         "mtp_batch_last_error": (c_char_p, [P]),
-        "mtp_server_workspace_bytes": (c_size_t, [P, c_int32, c_size_t, c_int32]),
-        "mtp_server_create": (c_int32, [P, c_int32, P, c_size_t, c_size_t, c_int32, c_int32, P, POINTER(P)]),
-        "mtp_server_create_simulated": (c_int32, [P, c_int32, c_size_t, c_int32, c_int32, ctypes.c_double,
+        "mtp_server_workspace_bytes": (c_size_t, [c_size_t, c_int32, c_uint32]),
+        "mtp_server_create": (c_int32, [c_size_t, c_int32, c_uint32, c_int32, c_int32, P, c_size_t, P,
+                                        POINTER(P)]),
+        "mtp_server_create_simulated": (c_int32, [c_size_t, c_int32, c_uint32, c_int32, c_int32, ctypes.c_double,
                                                   POINTER(P)]),
+        "mtp_server_add_robot": (c_int32, [P, P, POINTER(c_int32)]),
+        "mtp_server_remove_robot": (c_int32, [P, c_int32]),
+        "mtp_server_get_robot_state": (c_int32, [P, c_int32, P, P, POINTER(c_uint32)]),
         "mtp_server_submit": (c_int32, [P, c_int32, P, c_int32, c_uint64, POINTER(c_uint64)]),
         "mtp_server_pump": (c_int32, [P, c_int32, POINTER(c_int32)]),
         "mtp_server_poll": (c_int32, [P, P, c_int32, POINTER(c_int32)]),
@@ -114,6 +119,7 @@ def load():
         "mtp_server_destroy": (c_int32, [P]),
         "mtp_server_last_error": (c_char_p, [P]),
         "mtp_get_stage_times": (c_int32, [P, P, P]),
+        "mtp_plant_step": (c_int32, [P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -217,6 +223,24 @@ def transient_bytes(cfg) -> int:
     """Bytes one replan of cfg borrows from a server's pool (0 if invalid)."""
     c, keep = config_struct(cfg)
     return int(load().mtp_transient_bytes(byref(c)))
+
+
+def resident_bytes(cfg) -> int:
+    """Bytes a server keeps in its pool while the robot of cfg is registered (0 if invalid)."""
+    c, keep = config_struct(cfg)
+    return int(load().mtp_resident_bytes(byref(c)))
+
+
+def plant_step(cfg, x, u):
+    """One float64 host step of cfg's model from state x under control u (the
+    robot that executes the planner's action)."""
+    c, keep = config_struct(cfg)
+    xx = np.ascontiguousarray(np.asarray(x, np.float64))
+    uu = np.ascontiguousarray(np.asarray(u, np.float32))
+    out = np.empty_like(xx)
+    _check(load(), load().mtp_plant_step(byref(c), xx.ctypes.data_as(c_void_p), uu.ctypes.data_as(c_void_p),
+                                         out.ctypes.data_as(c_void_p)))
+    return out
 
 
 def _torch():
@@ -382,13 +406,14 @@ def _i32(a):
 class Batch:
     """Many instances replanned by one persistent launch (mtp_batch)."""
 
-    def __init__(self, cfgs, device="cuda", use_graph=True):
+    def __init__(self, cfgs, device="cuda", use_graph=True, n_debug_states=None):
         torch = _torch()
         self.lib = load()
         self.cfgs = list(cfgs)
         self.n = len(self.cfgs)
         self.device = torch.device(device)
-        structs = [config_struct(c) for c in self.cfgs]
+        self.n_debug = [0] * self.n if n_debug_states is None else [int(v) for v in n_debug_states]
+        structs = [config_struct(c, nd) for c, nd in zip(self.cfgs, self.n_debug)]
         self._keep = [k for _, k in structs]
         arr = (mtp_config * self.n)(*[c for c, _ in structs])
         self._arr = arr
@@ -459,7 +484,7 @@ class Batch:
     def buffers(self, i):
         b = mtp_buffers()
         self._err(self.lib.mtp_batch_get_buffers(self.handle, int(i), byref(b)))
-        return _buffer_views(b, self.cfgs[i], self.workspace, 0)
+        return _buffer_views(b, self.cfgs[i], self.workspace, self.n_debug[i])
 
     def set_state(self, i, mu, sigma):
         torch = _torch()
@@ -487,44 +512,71 @@ class mtp_completion(ctypes.Structure):
 
 class mtp_server_stats(ctypes.Structure):
     _fields_ = [(name, c_uint64) for name in
-                ("submitted", "admitted", "completed", "launches", "deferred_for_budget", "pool_bytes",
-                 "pool_in_use", "pool_peak", "resident_bytes")] + [("queued", c_int32), ("in_flight", c_int32)]
+                ("submitted", "admitted", "completed", "launches", "deferred_for_budget", "dropped", "pool_bytes",
+                 "pool_in_use", "pool_peak", "resident_bytes")] + [("queued", c_int32), ("in_flight", c_int32),
+                                                                   ("robots", c_int32), ("pad", c_int32)]
 
 
 class Server:
-    """Continuous-batching request loop over many robots (mtp_server).
+    """Continuous-batching request loop over a fleet of robots (mtp_server).
 
-    simulated=True drives the same scheduler with a host-only stand-in for the
-    device (no GPU, zero actions, synthetic launch times)."""
+    The server's device arena (launch tables and a pool of budget_bytes that
+    holds the robots' resident buffers and the requests' transient slabs) is
+    one torch allocation.  simulated=True drives the same scheduler with a
+    host-only stand-in for the device (no GPU, zero actions, synthetic launch
+    times).  Robots given as `robots` are added in order (ids 0, 1, ...)."""
 
-    def __init__(self, robots, pool_bytes, iters_per_launch=1, max_inflight=2, device="cuda",
-                 simulated=False, ns_per_sample_step=0.0):
+    def __init__(self, budget_bytes, max_robots, iters_per_launch=1, max_inflight=2, device="cuda",
+                 simulated=False, ns_per_sample_step=0.0, queue_items=0, robots=()):
         self.lib = load()
-        self.cfgs = list(robots)
-        self.n = len(self.cfgs)
-        structs = [config_struct(c) for c in self.cfgs]
-        self._keep = [k for _, k in structs]
-        self._arr = (mtp_config * self.n)(*[c for c, _ in structs])
+        self.cfgs = {}
+        self._keep = {}
         h = c_void_p()
         self.workspace = None
+        self.simulated = simulated
         if simulated:
-            st = self.lib.mtp_server_create_simulated(self._arr, self.n, int(pool_bytes), int(iters_per_launch),
-                                                      int(max_inflight), float(ns_per_sample_step), byref(h))
+            st = self.lib.mtp_server_create_simulated(int(budget_bytes), int(max_robots), int(queue_items),
+                                                      int(iters_per_launch), int(max_inflight),
+                                                      float(ns_per_sample_step), byref(h))
         else:
             torch = _torch()
-            nbytes = int(self.lib.mtp_server_workspace_bytes(self._arr, self.n, int(pool_bytes),
-                                                             int(iters_per_launch)))
+            nbytes = int(self.lib.mtp_server_workspace_bytes(int(budget_bytes), int(max_robots), int(queue_items)))
             if nbytes == 0:
-                raise MtpError(1, "server workspace size: invalid robots or pool")
+                raise MtpError(1, "server workspace size: invalid budget or robot count")
             self.device = torch.device(device)
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
-            st = self.lib.mtp_server_create(self._arr, self.n, c_void_p(self.workspace.data_ptr()), nbytes,
-                                            int(pool_bytes), int(iters_per_launch), int(max_inflight),
+            st = self.lib.mtp_server_create(int(budget_bytes), int(max_robots), int(queue_items),
+                                            int(iters_per_launch), int(max_inflight),
+                                            c_void_p(self.workspace.data_ptr()), nbytes,
                                             c_void_p(self.stream.cuda_stream), byref(h))
         _check(self.lib, st)
         self.handle = h
         self._buf = (mtp_completion * 1024)()
+        for c in robots:
+            self.add_robot(c)
+
+    def add_robot(self, cfg):
+        c, keep = config_struct(cfg)
+        rid = c_int32()
+        self._err(self.lib.mtp_server_add_robot(self.handle, byref(c), byref(rid)))
+        self.cfgs[int(rid.value)] = cfg
+        return int(rid.value)
+
+    def remove_robot(self, robot):
+        self._err(self.lib.mtp_server_remove_robot(self.handle, int(robot)))
+        self.cfgs.pop(int(robot), None)
+
+    def robot_state(self, robot):
+        """(mu, sigma) as (T, n) float32 device tensors and the next replan index."""
+        torch = _torch()
+        cfg = self.cfgs[int(robot)]
+        mu = torch.empty((cfg.horizon, cfg.ctrl_dim), dtype=torch.float32, device=self.device)
+        sg = torch.empty_like(mu)
+        r = c_uint32()
+        self._err(self.lib.mtp_server_get_robot_state(self.handle, int(robot), c_void_p(mu.data_ptr()),
+                                                      c_void_p(sg.data_ptr()), byref(r)))
+        return mu, sg, int(r.value)
 
     def _err(self, st):
         if st != 0:

@@ -48,12 +48,10 @@ struct BatchLayout {
   std::vector<Layout> lays;
   uint32_t capacity;
   int32_t x0_total, act_total;
-  size_t pool, pool_bytes;   // pooled mode: transient slabs are lent from [pool, pool + pool_bytes)
   size_t total;
 };
 
-bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string* why, mtp_status* code,
-                  size_t pool_bytes = 0, int max_iters_per_launch = 0) {
+bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string* why, mtp_status* code) {
   if (cfgs == nullptr || n < 1 || n > 65536) {
     if (why) *why = "need 1..65536 configs";
     if (code) *code = MTP_ERR_INVALID_ARG;
@@ -70,8 +68,7 @@ bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string
       return false;
     }
     L->lays.push_back(compute_layout(cfgs[i]));
-    const int k_cap = max_iters_per_launch > 0 ? std::min(max_iters_per_launch, cfgs[i].n_iters) : cfgs[i].n_iters;
-    L->capacity += items_for(cfgs[i], 0, k_cap, true);   // sized for split candidate items
+    L->capacity += items_for(cfgs[i], 0, cfgs[i].n_iters, true);   // sized for split candidate items
     L->x0_total += cfgs[i].state_dim;
     L->act_total += cfgs[i].ctrl_dim;
   }
@@ -89,10 +86,34 @@ bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string
   L->tr.resize(n);
   for (int i = 0; i < n; ++i) {
     L->res[i] = take(L->lays[i].resident);
-    L->tr[i] = pool_bytes > 0 ? 0 : take(L->lays[i].transient);
+    L->tr[i] = take(L->lays[i].transient);
   }
-  L->pool = pool_bytes > 0 ? take(pool_bytes) : 0;
-  L->pool_bytes = pool_bytes;
+  L->total = off;
+  return true;
+}
+
+// Tables of a batch whose instances are attached one by one (the server):
+// max_inst slots, each with a fixed place in the packed start-state and
+// action vectors, and a queue of `capacity` items.  Resident and transient
+// memory of the instances comes from the caller (the server's pool).
+bool batch_layout_dynamic(int32_t max_inst, uint32_t capacity, BatchLayout* L) {
+  if (max_inst < 1 || max_inst > 65536 || capacity < 1) return false;
+  L->lays.assign(max_inst, Layout{});
+  L->capacity = capacity;
+  L->x0_total = max_inst * kSlotX0;
+  L->act_total = max_inst * kSlotAct;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+  L->ctl = take(sizeof(BatchCtl));
+  L->descs = take(sizeof(PlanDesc) * max_inst);
+  L->ictl = take(sizeof(InstCtl) * max_inst);
+  L->order = take(sizeof(int32_t) * max_inst);
+  L->out = take(sizeof(float) * (L->act_total + 4));
+  L->queue = take(sizeof(BatchItem) * capacity);
+  L->ready = take(sizeof(uint32_t) * capacity);
+  L->inst0 = off;
+  L->res.assign(max_inst, 0);
+  L->tr.assign(max_inst, 0);
   L->total = off;
   return true;
 }
@@ -127,13 +148,20 @@ struct mtp_batch {
   uint64_t wait_ticks = 0;
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // one captured launch per persistent grid size, kept until the batch is
+  // destroyed (a schedule change selects another, it never destroys one that
+  // may still be executing)
+  struct GraphEntry {
+    int grid;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  bool dynamic = false;   // instances attached and detached one by one (the server)
   int last_active = 0;
   uint32_t next_r = 0;
-  bool pooled = false;
   bool descs_dirty = false;
-  PlanDesc* h_descs = nullptr;   // pinned staging of the descriptor table (pooled mode)
+  PlanDesc* h_descs = nullptr;   // pinned staging of the descriptor table (dynamic batches)
   bool sticky = false;
   std::string err;
 };
@@ -150,11 +178,13 @@ static mtp_status bdev(mtp_batch* b, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return bdev(b, e_, where); \
   } while (0)
 
-static void drop_graph(mtp_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+// Only at destroy, after the stream has drained.
+static void drop_graphs(mtp_batch* b) {
+  for (auto& g : b->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  b->graphs.clear();
 }
 
 static BatchLaunch launch_of(mtp_batch* b, int32_t n_active, uint32_t total, const float* x0) {
@@ -177,8 +207,12 @@ static void apply_schedule(mtp_batch* b) {
   b->grid = std::max(1, per_cu * b->cu_count);
 }
 
-static mtp_status ensure_graph(mtp_batch* b) {
-  if (b->exec) return MTP_OK;
+static mtp_status ensure_graph(mtp_batch* b, hipGraphExec_t* exec) {
+  for (const auto& g : b->graphs)
+    if (g.grid == b->grid) {
+      *exec = g.exec;
+      return MTP_OK;
+    }
   if (!b->cap_stream) BCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "stream create");
   BCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   const BatchLaunch L = launch_of(b, 0, 0, nullptr);
@@ -188,8 +222,14 @@ static mtp_status ensure_graph(mtp_batch* b) {
   const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
   if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return bdev(b, e, "capture"); }
   if (e2 != hipSuccess) return bdev(b, e2, "end capture");
-  b->graph = g;
-  BCHK(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  hipGraphExec_t x = nullptr;
+  const hipError_t e3 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e3 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return bdev(b, e3, "graph instantiate");
+  }
+  b->graphs.push_back({b->grid, g, x});
+  *exec = x;
   return MTP_OK;
 }
 
@@ -213,9 +253,10 @@ static mtp_status run_launch(mtp_batch* b, int32_t n_active, uint32_t total, con
   const BatchLaunch L = launch_of(b, n_active, total, d_x0);
   BCHK(b, launch_batch_prepare(L, b->stream), "prepare");
   if (b->use_graph) {
-    const mtp_status s = ensure_graph(b);
+    hipGraphExec_t exec = nullptr;
+    const mtp_status s = ensure_graph(b, &exec);
     if (s != MTP_OK) return s;
-    BCHK(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
+    BCHK(b, hipGraphLaunch(exec, b->stream), "graph launch");
   } else {
     BCHK(b, launch_batch_persistent(L, b->grid, b->stream), "persistent");
     BCHK(b, launch_batch_pack(L, b->d_out, b->n, b->lay.act_total, b->stream), "pack");
@@ -226,6 +267,7 @@ static mtp_status run_launch(mtp_batch* b, int32_t n_active, uint32_t total, con
 
 static mtp_status reset_instances(mtp_batch* b) {
   for (int i = 0; i < b->n; ++i) {
+    if (b->cfgs[i].horizon == 0) continue;   // an empty slot of a dynamic batch
     const mtp_status s = upload_plan_tables(b->cfgs[i], b->descs[i], b->task[i].data(),
                                             b->sparams[i].empty() ? nullptr : b->sparams[i].data(), b->stream,
                                             &b->err);
@@ -238,6 +280,48 @@ static mtp_status reset_instances(mtp_batch* b) {
   return MTP_OK;
 }
 
+static void set_views(mtp_batch* b) {
+  const BatchLayout& lay = b->lay;
+  b->d_ctl = reinterpret_cast<BatchCtl*>(b->base + lay.ctl);
+  b->d_descs = reinterpret_cast<PlanDesc*>(b->base + lay.descs);
+  b->d_ictl = reinterpret_cast<InstCtl*>(b->base + lay.ictl);
+  b->d_order = reinterpret_cast<int32_t*>(b->base + lay.order);
+  b->d_out = reinterpret_cast<float*>(b->base + lay.out);
+  b->d_queue = reinterpret_cast<BatchItem*>(b->base + lay.queue);
+  b->d_ready = reinterpret_cast<uint32_t*>(b->base + lay.ready);
+}
+
+// Pinned staging, device query, schedule and the zeroed control block and
+// ready flags; shared by both ways of creating a batch.
+static mtp_status init_common(mtp_batch* b) {
+  const int n = b->n;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_ictl), sizeof(InstCtl) * n, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_order), sizeof(int32_t) * n, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(float) * (b->lay.act_total + 4), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e != hipSuccess) return MTP_ERR_DEVICE;
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  int cus = 0, clk_khz = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return MTP_ERR_DEVICE;
+  b->cu_count = std::max(1, cus);
+  b->max_occ = std::max(1, batch_max_blocks_per_cu());
+  // every wait of the persistent kernel gives up after 10 s of wall clock
+  if (clk_khz <= 0) clk_khz = 100000;   // the constant-rate counter runs at 100 MHz on this family
+  b->wait_ticks = static_cast<uint64_t>(clk_khz) * 1000ull * 10ull;
+  apply_schedule(b);
+  BatchCtl ctl{};
+  ctl.capacity = b->lay.capacity;
+  e = hipMemcpyAsync(b->d_descs, b->descs.data(), sizeof(PlanDesc) * n, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_ready, 0, sizeof(uint32_t) * b->lay.capacity, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  return e == hipSuccess ? MTP_OK : MTP_ERR_DEVICE;
+}
+
 extern "C" {
 
 size_t mtp_batch_workspace_bytes(const mtp_config* cfgs, int32_t n) {
@@ -248,24 +332,14 @@ size_t mtp_batch_workspace_bytes(const mtp_config* cfgs, int32_t n) {
 
 }  // extern "C"
 
-size_t mtp::batch_workspace_bytes_pooled(const mtp_config* cfgs, int32_t n, size_t pool_bytes, int max_iters) {
-  BatchLayout L;
-  if (!batch_layout(cfgs, n, &L, nullptr, nullptr, pool_bytes, max_iters)) return 0;
-  return L.total;
-}
-
-mtp_status mtp::batch_create_internal(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes,
-                                      void* hip_stream, size_t pool_bytes, int max_iters, mtp_batch** out,
-                                      std::string* why_out) {
+static mtp_status batch_create_static(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes,
+                                      void* hip_stream, mtp_batch** out) {
   if (out == nullptr) return MTP_ERR_INVALID_ARG;
   *out = nullptr;
   BatchLayout lay;
   std::string why;
   mtp_status code = MTP_OK;
-  if (!batch_layout(cfgs, n, &lay, &why, &code, pool_bytes, max_iters)) {
-    if (why_out) *why_out = why;
-    return code;
-  }
+  if (!batch_layout(cfgs, n, &lay, &why, &code)) return code;
   if (d_workspace == nullptr || ws_bytes < lay.total || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
     return MTP_ERR_WORKSPACE;
   mtp_batch* b = new (std::nothrow) mtp_batch();
@@ -289,58 +363,19 @@ mtp_status mtp::batch_create_internal(const mtp_config* cfgs, int32_t n, void* d
     } else {
       c.sample_params = nullptr;
     }
-    b->descs[i] = make_desc(c, lay.lays[i], b->base + lay.res[i], pool_bytes > 0 ? nullptr : b->base + lay.tr[i]);
+    b->descs[i] = make_desc(c, lay.lays[i], b->base + lay.res[i], b->base + lay.tr[i]);
   }
-  b->pooled = pool_bytes > 0;
-  b->d_ctl = reinterpret_cast<BatchCtl*>(b->base + lay.ctl);
-  b->d_descs = reinterpret_cast<PlanDesc*>(b->base + lay.descs);
-  b->d_ictl = reinterpret_cast<InstCtl*>(b->base + lay.ictl);
-  b->d_order = reinterpret_cast<int32_t*>(b->base + lay.order);
-  b->d_out = reinterpret_cast<float*>(b->base + lay.out);
-  b->d_queue = reinterpret_cast<BatchItem*>(b->base + lay.queue);
-  b->d_ready = reinterpret_cast<uint32_t*>(b->base + lay.ready);
-
-  auto fail = [&](hipError_t e, const char* where) {
+  set_views(b);
+  if (init_common(b) != MTP_OK) {
     mtp_batch_destroy(b);
-    (void)e;
-    (void)where;
     return MTP_ERR_DEVICE;
-  };
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_ictl), sizeof(InstCtl) * n, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_order), sizeof(int32_t) * n, hipHostMallocDefault);
-  if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(float) * (lay.act_total + 4), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
-  if (e != hipSuccess) return fail(e, "host alloc");
-
-  int dev = 0;
-  e = hipGetDevice(&dev);
-  int cus = 0, clk_khz = 0;
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev);
-  if (e != hipSuccess) return fail(e, "device query");
-  b->cu_count = std::max(1, cus);
-  b->max_occ = std::max(1, batch_max_blocks_per_cu());
-  // every wait of the persistent kernel gives up after 10 s of wall clock
-  if (clk_khz <= 0) clk_khz = 100000;   // the constant-rate counter runs at 100 MHz on this family
-  b->wait_ticks = static_cast<uint64_t>(clk_khz) * 1000ull * 10ull;
-  apply_schedule(b);
-
+  }
   b->order_natural.resize(n);
   std::iota(b->order_natural.begin(), b->order_natural.end(), 0);
   b->order_longest = b->order_natural;
   std::stable_sort(b->order_longest.begin(), b->order_longest.end(), [&](int a, int c) {
     return work_estimate(b->cfgs[a]) > work_estimate(b->cfgs[c]);
   });
-
-  // device tables and control block
-  BatchCtl ctl{};
-  ctl.capacity = lay.capacity;
-  e = hipMemcpyAsync(b->d_descs, b->descs.data(), sizeof(PlanDesc) * n, hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(b->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(b->d_ready, 0, sizeof(uint32_t) * lay.capacity, b->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return fail(e, "tables");
   if (reset_instances(b) != MTP_OK) {
     mtp_batch_destroy(b);
     return MTP_ERR_DEVICE;
@@ -349,12 +384,89 @@ mtp_status mtp::batch_create_internal(const mtp_config* cfgs, int32_t n, void* d
   return MTP_OK;
 }
 
-uint8_t* mtp::batch_pool_base(mtp_batch* b) { return b->base + b->lay.pool; }
-size_t mtp::batch_transient_bytes(const mtp_batch* b, int i) { return b->lay.lays[i].transient; }
-size_t mtp::batch_resident_bytes(const mtp_batch* b) {
-  size_t s = 0;
-  for (const auto& L : b->lay.lays) s += L.resident;
+size_t mtp::batch_dynamic_bytes(int32_t max_inst, uint32_t capacity) {
+  BatchLayout L;
+  return batch_layout_dynamic(max_inst, capacity, &L) ? L.total : 0;
+}
+
+mtp_status mtp::batch_create_dynamic(int32_t max_inst, uint32_t capacity, void* d_workspace, size_t ws_bytes,
+                                     void* hip_stream, mtp_batch** out) {
+  if (out == nullptr) return MTP_ERR_INVALID_ARG;
+  *out = nullptr;
+  BatchLayout lay;
+  if (!batch_layout_dynamic(max_inst, capacity, &lay)) return MTP_ERR_INVALID_ARG;
+  if (d_workspace == nullptr || ws_bytes < lay.total || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
+    return MTP_ERR_WORKSPACE;
+  mtp_batch* b = new (std::nothrow) mtp_batch();
+  if (b == nullptr) return MTP_ERR_INVALID_ARG;
+  b->n = max_inst;
+  b->lay = lay;
+  b->base = static_cast<uint8_t*>(d_workspace);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->cfgs.assign(max_inst, mtp_config{});
+  b->task.resize(max_inst);
+  b->sparams.resize(max_inst);
+  b->descs.assign(max_inst, PlanDesc{});
+  b->dynamic = true;
+  set_views(b);
+  if (init_common(b) != MTP_OK) {
+    mtp_batch_destroy(b);
+    return MTP_ERR_DEVICE;
+  }
+  *out = b;
+  return MTP_OK;
+}
+
+mtp_status mtp::batch_attach(mtp_batch* b, int32_t i, const mtp_config& cfg, uint8_t* resident) {
+  if (b == nullptr || !b->dynamic || i < 0 || i >= b->n || resident == nullptr) return MTP_ERR_INVALID_ARG;
+  if (b->sticky) return MTP_ERR_DEVICE;
+  if (cfg.state_dim > kSlotX0 || cfg.ctrl_dim > kSlotAct) {
+    b->err = "an attached instance needs state_dim <= 64 and ctrl_dim <= 32";
+    return MTP_ERR_UNSUPPORTED;
+  }
+  mtp_config c = cfg;
+  b->task[i].assign(c.task_params, c.task_params + c.n_task_params);
+  c.task_params = b->task[i].data();
+  if (c.dynamics == MTP_DYN_CHAIN_CONTACT) {
+    const size_t B = static_cast<size_t>(c.n_tensor) + c.n_gauss;
+    b->sparams[i].assign(c.sample_params, c.sample_params + B * (c.ctrl_dim + 1) *
+                                                             static_cast<size_t>(c.n_replicas > 1 ? c.n_replicas : 1));
+    c.sample_params = b->sparams[i].data();
+  } else {
+    b->sparams[i].clear();
+    c.sample_params = nullptr;
+  }
+  b->cfgs[i] = c;
+  b->lay.lays[i] = compute_layout(c);
+  b->descs[i] = make_desc(c, b->lay.lays[i], resident, nullptr);
+  b->descs_dirty = true;
+  const mtp_status s = upload_plan_tables(c, b->descs[i], b->task[i].data(),
+                                          b->sparams[i].empty() ? nullptr : b->sparams[i].data(), b->stream, &b->err);
+  if (s != MTP_OK) b->sticky = true;
   return s;
+}
+
+void mtp::batch_detach(mtp_batch* b, int32_t i) {
+  if (b == nullptr || !b->dynamic || i < 0 || i >= b->n) return;
+  b->cfgs[i] = mtp_config{};
+  b->descs[i] = PlanDesc{};
+  b->lay.lays[i] = Layout{};
+  b->task[i].clear();
+  b->sparams[i].clear();
+  b->descs_dirty = true;
+}
+
+size_t mtp::batch_resident_bytes_of(const mtp_config& c) { return compute_layout(c).resident; }
+
+mtp_status mtp::batch_copy_state(mtp_batch* b, int32_t i, float* d_mu, float* d_sigma) {
+  if (b == nullptr || i < 0 || i >= b->n || b->cfgs[i].horizon == 0) return MTP_ERR_INVALID_ARG;
+  if (b->sticky) return MTP_ERR_DEVICE;
+  const size_t bytes = sizeof(float) * b->cfgs[i].horizon * b->cfgs[i].ctrl_dim;
+  if (d_mu) BCHK(b, hipMemcpyAsync(d_mu, b->descs[i].mu, bytes, hipMemcpyDeviceToDevice, b->stream), "mu copy");
+  if (d_sigma)
+    BCHK(b, hipMemcpyAsync(d_sigma, b->descs[i].sigma, bytes, hipMemcpyDeviceToDevice, b->stream), "sigma copy");
+  BCHK(b, hipStreamSynchronize(b->stream), "sync");
+  return MTP_OK;
 }
 
 void mtp::batch_set_transient(mtp_batch* b, int i, uint8_t* base) {
@@ -377,7 +489,7 @@ extern "C" {
 
 mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes, void* hip_stream,
                             mtp_batch** out) {
-  return batch_create_internal(cfgs, n, d_workspace, ws_bytes, hip_stream, 0, 0, out, nullptr);
+  return batch_create_static(cfgs, n, d_workspace, ws_bytes, hip_stream, out);
 }
 
 mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_active, const int32_t* h_k_begin,
@@ -400,8 +512,8 @@ mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_activ
   std::vector<int32_t> act_offsets(b->n);
   int act_off = 0;
   for (int i = 0; i < b->n; ++i) {
-    x0_offsets[i] = x0_off;
-    act_offsets[i] = act_off;
+    x0_offsets[i] = b->dynamic ? i * kSlotX0 : x0_off;
+    act_offsets[i] = b->dynamic ? i * kSlotAct : act_off;
     x0_off += b->cfgs[i].state_dim;
     act_off += b->cfgs[i].ctrl_dim;
   }
@@ -526,9 +638,7 @@ mtp_status mtp_batch_set_schedule(mtp_batch* b, int32_t wg_per_cu, int32_t order
   if (b == nullptr || wg_per_cu < 0 || order < 0 || order > 1) return MTP_ERR_INVALID_ARG;
   b->wg_per_cu = wg_per_cu;
   b->order_mode = order;
-  const int old = b->grid;
   apply_schedule(b);
-  if (b->grid != old) drop_graph(b);
   return MTP_OK;
 }
 
@@ -590,7 +700,7 @@ mtp_status mtp_batch_autotune(mtp_batch* b, int32_t reps, int32_t* h_choice, flo
 mtp_status mtp_batch_destroy(mtp_batch* b) {
   if (b == nullptr) return MTP_ERR_INVALID_ARG;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  drop_graph(b);
+  drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->staged) (void)hipEventDestroy(b->staged);
   if (b->h_ictl) (void)hipHostFree(b->h_ictl);

@@ -65,14 +65,22 @@ struct mtp_batch;
 
 namespace mtp {
 
-// Internal batch API used by the server (pooled transient workspaces).
-size_t batch_workspace_bytes_pooled(const mtp_config* cfgs, int32_t n, size_t pool_bytes, int max_iters);
-mtp_status batch_create_internal(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes,
-                                 void* hip_stream, size_t pool_bytes, int max_iters, mtp_batch** out,
-                                 std::string* why);
-uint8_t* batch_pool_base(mtp_batch* b);
-size_t batch_transient_bytes(const mtp_batch* b, int i);
-size_t batch_resident_bytes(const mtp_batch* b);
+// Internal batch API used by the server.
+// Batches whose instances come and go (the server): fixed slots, each with a
+// place of kSlotX0 floats in the packed start states and kSlotAct in the packed
+// actions; resident and transient memory is the caller's.
+constexpr int kSlotX0 = 64, kSlotAct = 32;
+size_t batch_dynamic_bytes(int32_t max_inst, uint32_t capacity);
+mtp_status batch_create_dynamic(int32_t max_inst, uint32_t capacity, void* d_workspace, size_t ws_bytes,
+                                void* hip_stream, mtp_batch** out);
+// Place instance `cfg` in slot i with its resident buffers at `resident`
+// (compute_layout(cfg).resident bytes, 256-aligned) and upload its tables;
+// synchronises the batch's stream.
+mtp_status batch_attach(mtp_batch* b, int32_t i, const mtp_config& cfg, uint8_t* resident);
+void batch_detach(mtp_batch* b, int32_t i);
+size_t batch_resident_bytes_of(const mtp_config& c);
+// Copy slot i's warm-start mean and std (device to device) and synchronise.
+mtp_status batch_copy_state(mtp_batch* b, int32_t i, float* d_mu, float* d_sigma);
 void batch_set_transient(mtp_batch* b, int i, uint8_t* base);
 mtp_status batch_enqueue_readback(mtp_batch* b, float* h_dst, hipEvent_t done);
 int batch_act_total(const mtp_batch* b);

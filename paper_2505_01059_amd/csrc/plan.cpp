@@ -474,6 +474,11 @@ size_t mtp_transient_bytes(const mtp_config* cfg) {
   return compute_layout(*cfg).transient;
 }
 
+size_t mtp_resident_bytes(const mtp_config* cfg) {
+  if (!validate_config(cfg, nullptr, nullptr)) return 0;
+  return compute_layout(*cfg).resident;
+}
+
 mtp_status mtp_validate_config(const mtp_config* cfg, char* why, size_t why_len) {
   std::string msg;
   mtp_status code = MTP_OK;

@@ -187,3 +187,46 @@ def elite_sets_agree(iE_gpu, s_gpu, s_ref, flagged, E):
 def refit_close(a, b, cfg):
     scale = np.maximum(np.abs(b), 1e-3 * float(cfg.u_max - cfg.u_min))
     return np.abs(a - b) <= 1e-4 * scale
+
+
+def check_iteration(cfg, b, x0, mu, sg, r, k, label, X_all=None):
+    """One CEM iteration (Alg. 2 loop body) that ran on the GPU, against the
+    oracle's same iteration from the same mean and std (teacher forcing):
+    graph and path indices bit-exact, candidates within U_TOL, costs by the
+    rules above (contact chains from the recorded states X_all, (R, B, T, d)),
+    the oracle's top-E on the GPU's costs bit-exact and elite sets against the
+    oracle's costs, the refit from the GPU's elites and the action.  `b` holds
+    the iteration's buffers as numpy arrays or torch views.  Returns the number
+    of distinct costs left out at the elite boundary."""
+    def np_(v):
+        return v.cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)
+    mu = np.asarray(mu, np.float64)
+    sg = np.asarray(sg, np.float64)
+    ref = OP.iterate(cfg, x0, mu, sg, r, k)
+    if cfg.n_tensor > 0:
+        assert np.array_equal(np_(b["Z"]), ref["Z"]), f"[{label}] graph waypoints"
+        assert np.array_equal(np_(b["I"]).T.astype(np.int64), ref["I"]), f"[{label}] path indices"
+    U = to_oracle_U(b["U"]) if hasattr(b["U"], "cpu") else np.asarray(b["U"], np.float64)
+    ill = akima_excluded(cfg, akima_ill_conditioned(cfg, ref["I"], ref["Z"]))
+    G1 = cfg.n_gauss - 1
+    rows_bad = ~np.all(u_close(U, ref["U"], cfg.u_max), axis=(1, 2))
+    rows_bad[G1:G1 + cfg.n_tensor] &= ~ill
+    assert not rows_bad.any(), f"[{label}] {rows_bad.sum()} candidates differ"
+    s = np_(b["cost"]).astype(np.float64)
+    iE = np_(b["elite_idx"])
+    if cfg.dynamics == 2:
+        assert X_all is not None, "contact chains are checked from their recorded states"
+        flagged = chain_contact_parity(cfg, x0, U, s, X_all, label)
+    else:
+        flagged = switching_flags(cfg, x0, ref["U"])
+    flagged[G1:G1 + cfg.n_tensor] |= ill
+    assert_costs(cfg, s, ref["s"], flagged)
+    assert np.array_equal(iE, OP.top_elites(s, cfg.n_elites)), f"[{label}] elites on the GPU's costs"
+    band = elite_sets_agree(iE, s, ref["s"], flagged, cfg.n_elites)
+    assert band <= max(4, cfg.n_elites // 4), f"[{label}] {band} costs within the elite boundary band"
+    mu2, sg2, _ = OP.refit(ref["U"], s, iE, mu, sg, cfg)
+    assert refit_close(np_(b["mu"]), mu2, cfg).all(), f"[{label}] refit mean"
+    assert refit_close(np_(b["sigma"]), sg2, cfg).all(), f"[{label}] refit std"
+    np.testing.assert_array_equal(np_(b["action"]), U[iE[0], 0].astype(np.float32), err_msg=f"[{label}] action")
+    print(f"[{label}] flagged {int(flagged.sum())}, elite boundary band {band}", flush=True)
+    return band

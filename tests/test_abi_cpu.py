@@ -252,3 +252,27 @@ def test_one_hip_runtime_whatever_the_import_order():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+@pytest.mark.parametrize("kind", ["point_mass", "chain2", "chain7", "chain24", "contact7", "contact24"])
+def test_plant_step_equals_the_oracle(kind):
+    """The serving loop's host plant (float64, tension formulation) against the
+    oracle's dense Lagrangian step on random states, contact ones included."""
+    from oracle import dynamics as OD
+    rng = np.random.default_rng(len(kind))
+    if kind == "point_mass":
+        cfg = W.point_mass_config()
+    elif kind.startswith("chain"):
+        cfg = W.chain_config(n_links=int(kind[5:]), n_tensor=8, n_gauss=8, n_elites=4)
+    else:
+        cfg = W.chain_contact_config(n_links=int(kind[7:]), n_tensor=8, n_gauss=8, n_elites=4, ground_y=-1.0)
+    model = OD.Model(cfg, np.array([0]))
+    for trial in range(20):
+        x = rng.normal(size=cfg.state_dim) * (0.3 if cfg.dynamics else 1.0)
+        if cfg.dynamics:
+            x[:cfg.n_links] += np.pi / 2 * (trial % 3)
+        u = rng.uniform(float(cfg.u_min), float(cfg.u_max), size=cfg.ctrl_dim).astype(np.float32)
+        got = mtp.plant_step(cfg, x, u)
+        want = model.step(x[None], u[None].astype(np.float64))[0]
+        # two float64 formulations of one ODE: rounding apart, amplified by the 24-link conditioning
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-9 * max(1.0, np.max(np.abs(want))))

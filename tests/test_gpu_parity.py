@@ -426,31 +426,8 @@ def test_teacher_forced_replan(name, torch_mod):
         plan.run_stage(4, r, k)
         torch_mod.cuda.synchronize()
         b = plan.buffers()
-        ref = OP.iterate(cfg, x0, mu.astype(np.float64), sg.astype(np.float64), r, k)
-        assert np.array_equal(b["I"].cpu().numpy().T.astype(np.int64), ref["I"])
-        s = b["cost"].cpu().numpy()
-        iE = b["elite_idx"].cpu().numpy()
-        if contact:
-            U = H.to_oracle_U(b["U"])
-            assert H.u_close(U, ref["U"], cfg.u_max).all()
-            flagged = H.chain_contact_parity(cfg, x0, U, s, recorded_states(b), f"replan {name} k={k}")
-        else:
-            flagged = H.switching_flags(cfg, x0, ref["U"])
-        ill = H.akima_excluded(cfg, H.akima_ill_conditioned(cfg, ref["I"], ref["Z"]))
-        G1 = cfg.n_gauss - 1
-        flagged[G1:G1 + cfg.n_tensor] |= ill
-        H.assert_costs(cfg, s, ref["s"], flagged)
-        # the oracle's selection on the GPU's own costs is bit-exact
-        assert np.array_equal(iE, OP.top_elites(s.astype(np.float64), cfg.n_elites))
-        # against the oracle's own costs: equal sets outside the flagged candidates and the boundary band
-        band = H.elite_sets_agree(iE, s, ref["s"], flagged, cfg.n_elites)
-        band_total += band
-        _log(f"  k={k}: flagged {int(flagged.sum())}, left out at the elite boundary {band}")
-        assert band <= max(4, cfg.n_elites // 4), f"{band} candidates within the elite boundary band"
-        mu2, sg2, _ = OP.refit(ref["U"], s.astype(np.float64), iE, mu.astype(np.float64),
-                               sg.astype(np.float64), cfg)
-        assert H.refit_close(b["mu"].cpu().numpy(), mu2, cfg).all()
-        assert H.refit_close(b["sigma"].cpu().numpy(), sg2, cfg).all()
+        X_all = recorded_states(b) if contact else None
+        band_total += H.check_iteration(cfg, b, x0, mu, sg, r, k, f"replan {name} k={k}", X_all)
         mu = b["mu"].cpu().numpy().copy()
         sg = b["sigma"].cpu().numpy().copy()
     _log(f"  elite boundary band total {band_total}")
