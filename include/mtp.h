@@ -383,6 +383,26 @@ uint64_t mtp_server_now_ns(void);
 mtp_status mtp_server_destroy(mtp_server* s);
 const char* mtp_server_last_error(const mtp_server* s);
 
+/* ------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid it): one replan, as mtp_replan_at
+ * on a fresh plan whose warm start is (d_mu, d_sigma), with every buffer
+ * besides its inputs and outputs in a static device array of
+ * mtp_noalloc_scratch_bytes() (64 MiB) that each device holds for the life of
+ * the process.  No hipMalloc, no workspace, no graph.
+ *   d_x0     [state_dim] start state (read)
+ *   d_mu, d_sigma [T][n] warm-start mean and std: read, shifted by shift_steps,
+ *            refitted over n_iters CEM iterations and written back
+ *   d_action [n] written: first control of the best candidate of the last iteration
+ * Enqueued on hip_stream (NULL = default); the host tables are uploaded with a
+ * synchronisation of that stream first.  Every call on one device uses the same
+ * array and leaves its contents behind: calls that overlap on a device race.
+ * MTP_ERR_WORKSPACE if the config's buffers (mtp_workspace_bytes without the
+ * second candidate buffer) exceed the array. */
+size_t mtp_noalloc_scratch_bytes(void);
+mtp_status mtp_replan_noalloc(const mtp_config* cfg, const float* d_x0, float* d_mu, float* d_sigma,
+                              int32_t shift_steps, uint32_t replan_idx, float* d_action, void* hip_stream);
+
 /* Host-side plant of a robot, for closing the receding-horizon loop of Alg. 2
  * around a server or plan (execute u*, replan from the state it leads to): one
  * step x_{t+1} = f(x_t, u_t) of cfg's model in float64 on the host (no device

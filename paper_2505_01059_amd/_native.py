@@ -120,6 +120,8 @@ def load():
         "mtp_server_last_error": (c_char_p, [P]),
         "mtp_get_stage_times": (c_int32, [P, P, P]),
         "mtp_plant_step": (c_int32, [P, P, P, P]),
+        "mtp_noalloc_scratch_bytes": (c_size_t, []),
+        "mtp_replan_noalloc": (c_int32, [P, P, P, P, c_int32, c_uint32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -276,3 +276,16 @@ def test_plant_step_equals_the_oracle(kind):
         want = model.step(x[None], u[None].astype(np.float64))[0]
         # two float64 formulations of one ODE: rounding apart, amplified by the 24-link conditioning
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-9 * max(1.0, np.max(np.abs(want))))
+
+
+def test_noalloc_rejects_configs_beyond_its_scratch():
+    """A config whose buffers exceed the static scratch array is refused with
+    MTP_ERR_WORKSPACE before anything touches the device."""
+    lib = mtp.load()
+    cfg = W.c1()                                  # ~36 MB of buffers: fits
+    big = W.c4()                                  # 1.7 GB of candidates: does not
+    c, keep = N.config_struct(big)
+    fake = ctypes.c_void_p(256)                   # never dereferenced: the size check comes first
+    st = lib.mtp_replan_noalloc(ctypes.byref(c), fake, fake, fake, 0, 0, fake, None)
+    assert st == 3
+    assert N.workspace_bytes(cfg) > 0 and lib.mtp_noalloc_scratch_bytes() == 64 << 20
