@@ -148,11 +148,14 @@ typedef struct {
 
 typedef struct mtp_plan mtp_plan;
 
-/* Bytes of device workspace a plan needs (256-byte aligned base required); 0 if cfg is invalid. */
+/* Bytes of device workspace a plan needs (256-byte aligned base required); 0 if cfg is invalid.
+ * Sizes the buffers of Alg. 2's loop body: graph Z (Def. 1), paths I (Alg. 1),
+ * candidates U, costs S (Eq. 1), elites, mean / std. */
 size_t mtp_workspace_bytes(const mtp_config* cfg);
 
-/* Check a config without creating anything; on failure writes a reason into `why`
- * (NUL-terminated, at most why_len bytes; may be NULL). */
+/* Check a config (Alg. 2's inputs: graph L x W of Def. 1, B, beta as counts,
+ * T, alpha, lambda, sigma floor, E) without creating anything; on failure
+ * writes a reason into `why` (NUL-terminated, at most why_len bytes; may be NULL). */
 mtp_status mtp_validate_config(const mtp_config* cfg, char* why, size_t why_len);
 
 /* Bytes of the per-replan (transient) buffers of one instance: graph, paths,
@@ -165,13 +168,15 @@ size_t mtp_transient_bytes(const mtp_config* cfg);
  * from its pool for as long as the robot is registered; 0 if cfg is invalid. */
 size_t mtp_resident_bytes(const mtp_config* cfg);
 
-/* Validate cfg, lay the plan out in the caller's workspace, upload its tables
- * (spline basis, task and sample parameters) on `hip_stream` (NULL = default
- * stream) and initialise mu = (u_min+u_max)/2, sigma = sigma_init, replan index 0. */
+/* Alg. 2's initialisation: validate cfg, lay the plan out in the caller's
+ * workspace, upload its tables (spline basis of Def. 2 / Def. 3, task and
+ * sample parameters) on `hip_stream` (NULL = default stream) and initialise
+ * mu = (u_min+u_max)/2, sigma = sigma_init, replan index 0. */
 mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_bytes,
                            void* hip_stream, mtp_plan** out);
 
-/* One replan (Alg. 2 loop body, n_iters iterations) from start state d_x0 (d floats,
+/* Alg. 2's planning step: the loop body (graph, paths, interpolation, local
+ * samples, rollout and cost, top-E, softmax refit) n_iters times from start state d_x0 (d floats,
  * read by the replan's first kernel, so it must stay valid until that point in
  * stream order), after shifting the
  * warm-start mean/std forward by shift_steps (0 = no shift; the mean's last row is
@@ -179,18 +184,21 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
  * Philox replan index and increments it.  Asynchronous. */
 mtp_status mtp_replan(mtp_plan* p, const float* d_x0, int32_t shift_steps);
 
-/* As mtp_replan with an explicit replan index; the counter continues from replan_idx+1. */
+/* Alg. 2's planning step as mtp_replan with an explicit replan index; the counter continues from replan_idx+1. */
 mtp_status mtp_replan_at(mtp_plan* p, const float* d_x0, int32_t shift_steps, uint32_t replan_idx);
 
-/* Copy the action of the last replan (n floats) to the host; synchronises the stream. */
+/* Alg. 2's output: the first control of the cheapest candidate of the last
+ * iteration, the control the robot executes (n floats) copied to the host;
+ * synchronises the stream. */
 mtp_status mtp_get_action(mtp_plan* p, float* h_u);
 
-/* Export / import the warm-start state (device arrays of T*n floats) and the replan
- * counter, for checkpoint and resume.  get_state synchronises the stream. */
+/* Alg. 2's warm start between replans (mean and std carried over, shifted by
+ * the next call): export / import it (device arrays of T*n floats) with the
+ * replan counter, for checkpoint and resume.  get_state synchronises the stream. */
 mtp_status mtp_get_state(const mtp_plan* p, float* d_mu, float* d_sigma, uint32_t* replan_idx);
 mtp_status mtp_set_state(mtp_plan* p, const float* d_mu, const float* d_sigma, uint32_t replan_idx);
 
-/* Staged execution for checks: run one stage of CEM iteration k of replan r on the
+/* One stage of Alg. 2's loop body, for checks: run one stage of CEM iteration k of replan r on the
  * buffers as they stand (MTP_STAGE_ALL runs one whole iteration).  A test may write
  * a stage's inputs through mtp_get_buffers first.  x0 must have been set by a replan
  * or mtp_set_x0. */
@@ -202,12 +210,15 @@ typedef enum {
   MTP_STAGE_ALL = 4
 } mtp_stage;
 mtp_status mtp_run_stage(mtp_plan* p, int32_t stage, uint32_t replan_idx, int32_t k);
+/* The rollouts' start state x0 (Eq. 1) for mtp_run_stage, copied from device memory. */
 mtp_status mtp_set_x0(mtp_plan* p, const float* d_x0);
 
-/* Replay replans through a captured hipGraph (1, default) or launch kernels one by one (0). */
+/* How Alg. 2's planning step is launched (the arithmetic is the same): replay
+ * a captured hipGraph (1, default) or launch kernels one by one (0). */
 mtp_status mtp_set_graph_mode(mtp_plan* p, int32_t use_graph);
 
-/* Per-stage kernel timing with hipEvents recorded on the plan's stream around every
+/* Measurement of Alg. 2's stages (no arithmetic of its own): per-stage kernel
+ * timing with hipEvents recorded on the plan's stream around every
  * stage launch.  While enabled, replans launch their kernels one by one (no graph).
  * mtp_get_stage_times waits for the recorded events and returns, per stage
  * (candidates, rollout, top-E, refit), the summed kernel milliseconds and the
@@ -215,6 +226,7 @@ mtp_status mtp_set_graph_mode(mtp_plan* p, int32_t use_graph);
 mtp_status mtp_set_stage_timing(mtp_plan* p, int32_t enable);
 mtp_status mtp_get_stage_times(mtp_plan* p, double* h_ms4, uint64_t* h_count4);
 
+/* Device views of the intermediates of Alg. 2's last loop body (layouts above). */
 mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
 
 /* 1 if the plan draws each next CEM iteration's tensor-path controls during the
@@ -227,16 +239,20 @@ mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
  * results are the same bits either way (Alg. 2: the tensor paths do not depend
  * on the sampling distribution being refitted). */
 int32_t mtp_plan_draws_ahead(const mtp_plan* p);
-/* Status flags of the last replan: bit 0 = every elite cost was +inf (weights fell back to uniform);
+/* Status of Alg. 2's last planning step: bit 0 = every elite cost was +inf (weights fell back to uniform);
  * bit 1 = an elite index out of range (never expected); bit 2 = a wait of the time-sliced rollout
  * timed out (results of that replan are not valid). */
 mtp_status mtp_get_flags(mtp_plan* p, uint32_t* h_flags);
+/* Release the plan object (the workspace stays the caller's). */
 mtp_status mtp_plan_destroy(mtp_plan* p);
 
+/* Error reporting of the conventions above (no passage of the paper). */
 const char* mtp_status_str(mtp_status s);
 const char* mtp_last_error(const mtp_plan* p);
 
-/* The host-built interpolation table of a config (no device needed): basis gets
+/* The interpolation operator of Def. 2 (B-spline, Eq. 3-4), Def. 3 (Akima,
+ * Eq. 5-7) or the linear paths of Thm. 1, as the host builds it (no device
+ * needed): basis gets
  * horizon*8 floats, span gets horizon ints.  B-spline row t holds the degree+1
  * weights of control points span[t] .. span[t]+degree; Akima row t holds the
  * cubic Hermite weights (value i, slope i, value i+1, slope i+1) of interval
@@ -257,34 +273,40 @@ mtp_status mtp_interp_table(const mtp_config* cfg, float* h_basis, int32_t* h_sp
  * state_dim floats) and actions (sum of ctrl_dim floats). */
 typedef struct mtp_batch mtp_batch;
 
+/* Workspace of n instances of Alg. 2 (each as mtp_workspace_bytes) plus the launch queue. */
 size_t mtp_batch_workspace_bytes(const mtp_config* cfgs, int32_t n);
+/* Alg. 2's initialisation for every instance (as mtp_plan_create). */
 mtp_status mtp_batch_create(const mtp_config* cfgs, int32_t n, void* d_workspace, size_t ws_bytes,
                             void* hip_stream, mtp_batch** out);
-/* Replan every instance from the packed start states (device, read by the launch's
+/* Alg. 2's planning step for every instance at once: replan from the packed start states (device, read by the launch's
  * first kernel) with per-instance warm-start shifts (host array of n ints; NULL = 0).
  * All instances use the batch's replan counter, which then increments. */
 mtp_status mtp_batch_replan(mtp_batch* b, const float* d_x0_packed, const int32_t* h_shift);
-/* General step: run CEM iterations [h_k_begin[i], h_k_end[i]) of replan h_r[i] for the
+/* Part of Alg. 2's planning step for a subset: run CEM iterations [h_k_begin[i], h_k_end[i]) of replan h_r[i] for the
  * n_active instances listed in h_active (host arrays indexed like h_active).  The shift
  * applies to instances whose k_begin is 0; x0 is staged for those too (d_x0_packed may
  * be NULL to keep each instance's x0). */
 mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_active, const int32_t* h_k_begin,
                           const int32_t* h_k_end, const int32_t* h_shift, const uint32_t* h_r,
                           const float* d_x0_packed);
-/* Actions of the last launch (packed, host); synchronises; MTP_ERR_DEVICE if the
+/* Alg. 2's output per instance: the actions of the last launch (packed, host); synchronises; MTP_ERR_DEVICE if the
  * launch reported a queue timeout or overflow. */
 mtp_status mtp_batch_get_actions(mtp_batch* b, float* h_u_packed);
+/* Device views of instance i's Alg. 2 intermediates (as mtp_get_buffers). */
 mtp_status mtp_batch_get_buffers(const mtp_batch* b, int32_t i, mtp_buffers* out);
+/* Instance i's warm-start mean and std (as mtp_set_state, the replan index aside). */
 mtp_status mtp_batch_set_state(mtp_batch* b, int32_t i, const float* d_mu, const float* d_sigma);
-/* Schedule knobs of the persistent launch: workgroups per compute unit (0 = the
+/* Scheduling of the batched launch (no arithmetic of Alg. 2 changes): workgroups per compute unit (0 = the
  * occupancy limit) and the order of the initial queue (0 = config order,
  * 1 = longest estimated work first). */
 mtp_status mtp_batch_set_schedule(mtp_batch* b, int32_t wg_per_cu, int32_t order);
-/* Time every schedule (reps replans each, HIP events) and keep the fastest; writes
+/* Scheduling of the batched launch: time every schedule (reps replans each, HIP events) and keep the fastest; writes
  * {wg_per_cu, order} to h_choice and the best milliseconds per replan to h_ms.
  * Every instance is reset to its initial state and replan index 0 afterwards. */
 mtp_status mtp_batch_autotune(mtp_batch* b, int32_t reps, int32_t* h_choice, float* h_ms);
+/* As mtp_set_graph_mode, for the persistent launch. */
 mtp_status mtp_batch_set_graph_mode(mtp_batch* b, int32_t use_graph);
+/* Release the batch object (the workspace stays the caller's). */
 mtp_status mtp_batch_destroy(mtp_batch* b);
 const char* mtp_batch_last_error(const mtp_batch* b);
 
@@ -378,8 +400,11 @@ mtp_status mtp_server_submit(mtp_server* s, int32_t robot, const float* h_x0, in
 mtp_status mtp_server_pump(mtp_server* s, int32_t wait_us, int32_t* n_completed);
 /* Completed requests (at most max), oldest first. */
 mtp_status mtp_server_poll(mtp_server* s, mtp_completion* out, int32_t max, int32_t* n_out);
+/* Counters of the request loop (admission, budget, launches). */
 mtp_status mtp_server_get_stats(const mtp_server* s, mtp_server_stats* out);
+/* The server's clock for arrival and completion times. */
 uint64_t mtp_server_now_ns(void);
+/* Release the server; its arena stays the caller's.  Synchronises its stream. */
 mtp_status mtp_server_destroy(mtp_server* s);
 const char* mtp_server_last_error(const mtp_server* s);
 
@@ -412,7 +437,8 @@ mtp_status mtp_replan_noalloc(const mtp_config* cfg, const float* d_x0, float* d
  * its masses and friction. */
 mtp_status mtp_plant_step(const mtp_config* cfg, const double* h_x, const float* h_u, double* h_x_next);
 
-/* Chain lengths the rollout kernel is instantiated for (writes up to `cap`, returns the count). */
+/* The rollout of Alg. 2 (Eq. 1) is compiled per chain length: the lengths it is
+ * instantiated for (writes up to `cap`, returns the count). */
 int32_t mtp_supported_chain_links(int32_t* out, int32_t cap);
 
 #ifdef __cplusplus
