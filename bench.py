@@ -192,6 +192,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="chain24_contact_bspline", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 7-link chain's extra keys")
     ap.add_argument("--rate", type=float, nargs="+", default=[2000.0],
                     help="serving: Poisson request rates (req/s) to run, one after another")
     ap.add_argument("--duration", type=float, default=20.0, help="serving: measured seconds per rate")
@@ -226,7 +227,7 @@ def main():
         "stage_ms_per_launch": rec["stage_ms_per_launch"],
         "roofline": rec["roofline"],
     }
-    if args.workload == "chain24_contact_bspline":
+    if args.workload == "chain24_contact_bspline" and not args.no_secondary:
         # the 7-link chain of the other single-instance configuration, as extra keys
         sec, sec_info = time_plan(W.c1(), "chain7_akima", max(args.steps, 20), args.warmup)
         sec["config"] = sec_info

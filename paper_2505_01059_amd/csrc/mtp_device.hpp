@@ -140,17 +140,25 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fm
 // sin and cos of an angle given in revolutions, with no reduction: for the
 // rollouts that keep their angles reduced, whose arguments stay within a few
 // revolutions of [0, 1), well inside the instructions' input domain.
-//
-// The pair from v_sin / v_cos is a little short on average: over 2^22
-// arguments in [0, 1), s^2 + c^2 - 1 has mean -6.5e-8 and standard deviation
-// 5.7e-8, and the error varies slowly with the argument.  The chain rollouts
-// build every link direction from such a pair, so a slow-moving link keeps
-// the same small length deficit step after step and the trajectory drifts
-// linearly from the exact one (24-link chain, 128 RK4 steps: 7.9e-5 of the
-// state scale against 1.4e-5 with correctly rounded sin / cos).  One Newton
-// step towards unit length, (s, c) *= 1 + (1 - s^2 - c^2) / 2, removes the
-// bias: 1.9e-5 after 128 steps, for five more instructions per pair.
 __device__ __forceinline__ void rev_sincos(float rev, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(rev);
+  *c = __builtin_amdgcn_cosf(rev);
+}
+
+// The same with the pair brought back to unit length.  The pair from v_sin /
+// v_cos is a little short on average: over 2^22 arguments in [0, 1),
+// s^2 + c^2 - 1 has mean -6.5e-8 and standard deviation 5.7e-8, and the error
+// varies slowly with the argument.  Every link direction is built from such a
+// pair, so in a long chain whose links turn slowly each link keeps the same
+// small length deficit step after step and the trajectory drifts linearly from
+// the exact one (24 links, 128 RK4 steps: 7.9e-5 of the state scale against
+// 1.4e-5 with correctly rounded sin / cos).  One Newton step towards unit
+// length, (s, c) *= 1 + (1 - s^2 - c^2) / 2, removes the bias (1.9e-5 after
+// 128 steps) for five more instructions per pair.  The long-chain (pair-lane)
+// rollouts use it; in the 7-link chain the bias is swamped by the rest of the
+// rounding (2.6e-5 against 2.1e-5 after 128 steps) and the shorter chains keep
+// the plain pair.
+__device__ __forceinline__ void rev_sincos_unit(float rev, float* s, float* c) {
   const float sv = __builtin_amdgcn_sinf(rev);
   const float cv = __builtin_amdgcn_cosf(rev);
   const float h = fmaf(-sv, sv, fmaf(-cv, cv, 1.0f)) * 0.5f;
@@ -1334,7 +1342,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
   const float dtr = kInvTwoPi * dt, hdtr = kInvTwoPi * hdt, dt6r = kInvTwoPi * dt6;
   float s[M], c[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) rev_sincos(ph[i], &s[i], &c[i]);
+  for (int i = 0; i < M; ++i) rev_sincos_unit(ph[i], &s[i], &c[i]);
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* ub = P.U + b;
   float u[M];
@@ -1374,7 +1382,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
       float s2[M], c2[M];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        rev_sincos(fmaf(hr, oms[i], ph[i]), &s2[i], &c2[i]);
+        rev_sincos_unit(fmaf(hr, oms[i], ph[i]), &s2[i], &c2[i]);
         oms[i] = fmaf(h, kk[i], om[i]);
       }
       pair_accel<N, CONTACT>(s2, c2, oms, q, q_o, K, kk);
@@ -1392,7 +1400,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
       pu[i] = fmaf(dt6r, aph[i], ph[i]);
       ph[i] = __builtin_amdgcn_fractf(pu[i]);
       om[i] = fmaf(dt6, aom[i], om[i]);
-      rev_sincos(ph[i], &s[i], &c[i]);
+      rev_sincos_unit(ph[i], &s[i], &c[i]);
       ex = fmaf(K.l[i], s[i], ex);
       ey = fmaf(-K.l[i], c[i], ey);
       uu = fmaf(u[i], u[i], uu);
