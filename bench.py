@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--workload", default="chain24_contact_bspline", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 7-link chain's extra keys")
+    ap.add_argument("--tune-cache", default=None,
+                    help="mix256: JSON schedule cache to read (and write after a search)")
     ap.add_argument("--rate", type=float, nargs="+", default=[2000.0],
                     help="serving: Poisson request rates (req/s) to run, one after another")
     ap.add_argument("--duration", type=float, default=20.0, help="serving: measured seconds per rate")
@@ -332,8 +334,11 @@ def bench_mix(args, cfgs):
     x0s = [W.initial_state(c, seed=i) for i, c in enumerate(cfgs)]
     steps_per_replan = sum(c.n_samples * c.horizon * c.n_iters for c in cfgs)
     bt = mtp.Batch(cfgs, device=dev)
-    wg, order, tune_ms = bt.autotune(reps=1)
-    print(f"[bench] autotune: {wg} workgroups/CU, order {order}, {tune_ms:.2f} ms", file=sys.stderr, flush=True)
+    t_tune = time.perf_counter()
+    sched, tune_ms, cached = bt.tune(reps=1, cache_path=args.tune_cache)
+    t_tune = time.perf_counter() - t_tune
+    print(f"[bench] schedule {sched} ({tune_ms:.2f} ms per replan, "
+          f"{'from the cache' if cached else f'searched in {t_tune:.1f} s'})", file=sys.stderr, flush=True)
     xp = bt.pack_x0(x0s)
     for _ in range(args.warmup):
         bt.replan(xp, shift=1)
@@ -395,7 +400,7 @@ def bench_mix(args, cfgs):
         "data": "synthetic",
         "config": {"workload": "mix256", "instances": len(cfgs),
                    "candidates_total": sum(c.n_samples for c in cfgs),
-                   "schedule": {"workgroups_per_cu": wg, "longest_first": bool(order)}},
+                   "schedule": dict(sched, from_cache=cached)},
         "replans_per_s": len(cfgs) * args.steps / wall,
         "latency_ms_p50": round(statistics.median(lat), 3), "latency_ms_p99": round(lat[-1], 3),
         "plain_stage_ms_sum": {k_: round(v, 3) for k_, v in stage_tot.items()},

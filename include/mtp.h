@@ -296,14 +296,76 @@ mtp_status mtp_batch_get_actions(mtp_batch* b, float* h_u_packed);
 mtp_status mtp_batch_get_buffers(const mtp_batch* b, int32_t i, mtp_buffers* out);
 /* Instance i's warm-start mean and std (as mtp_set_state, the replan index aside). */
 mtp_status mtp_batch_set_state(mtp_batch* b, int32_t i, const float* d_mu, const float* d_sigma);
-/* Scheduling of the batched launch (no arithmetic of Alg. 2 changes): workgroups per compute unit (0 = the
- * occupancy limit) and the order of the initial queue (0 = config order,
- * 1 = longest estimated work first). */
+/*
+ * Schedule of the batched launch.  None of it changes the arithmetic of Alg. 2:
+ * every candidate, rollout, selection and refit output is computed by the same
+ * code from the same inputs whichever workgroup takes it, so results are
+ * bit-identical under every schedule.
+ *   wg_per_cu      persistent workgroups per compute unit (0 = the occupancy limit)
+ *   order          initial queue order: 0 = config order, 1 = longest estimated work first
+ *   cand_tiles     candidate tiles (256 candidates, all joints) per queue item: 1, 2 or 4
+ *   roll_tiles     rollout tiles (one workgroup's candidates) per queue item: 1, 2 or 4
+ *   refit_outputs  refit outputs (t, j) per queue item: 4, 8, 16, 32 or 64
+ *   split_pct      a launch whose active instances have fewer candidate tiles than
+ *                  split_pct % of the persistent workgroups runs the finest items
+ *                  instead (one joint of one candidate tile, one rollout tile, four
+ *                  refit outputs), so that a light load still spreads over the chip;
+ *                  0 = never, 100 = fewer tiles than workgroups
+ * Defaults: {0, 1, 1, 1, 64, 100}.
+ */
+typedef struct {
+  int32_t wg_per_cu;
+  int32_t order;
+  int32_t cand_tiles;
+  int32_t roll_tiles;
+  int32_t refit_outputs;
+  int32_t split_pct;
+} mtp_batch_schedule;
+
+/* Scheduling of the batched launch: set the workgroups per compute unit and the queue order, keeping the rest. */
 mtp_status mtp_batch_set_schedule(mtp_batch* b, int32_t wg_per_cu, int32_t order);
-/* Scheduling of the batched launch: time every schedule (reps replans each, HIP events) and keep the fastest; writes
- * {wg_per_cu, order} to h_choice and the best milliseconds per replan to h_ms.
+/* Scheduling of the batched launch: set every knob; MTP_ERR_INVALID_ARG (nothing changed) for a value outside
+ * the ranges above. */
+mtp_status mtp_batch_set_schedule_full(mtp_batch* b, const mtp_batch_schedule* h_schedule);
+/* Scheduling of the batched launch: the schedule in force. */
+mtp_status mtp_batch_get_schedule(const mtp_batch* b, mtp_batch_schedule* h_schedule);
+/* Scheduling of the batched launch: time every workgroups-per-CU x order setting (reps replans each, HIP events) and
+ * keep the fastest; writes {wg_per_cu, order} to h_choice and the best milliseconds per replan to h_ms.
  * Every instance is reset to its initial state and replan index 0 afterwards. */
 mtp_status mtp_batch_autotune(mtp_batch* b, int32_t reps, int32_t* h_choice, float* h_ms);
+/*
+ * Scheduling of the batched launch (Alg. 2's planning step for many instances)
+ * with a cache.  If cache_path (may be NULL)
+ * names a schedule cache holding an entry for (this GPU's architecture name,
+ * its compute-unit count, mtp_batch_mix_signature of the batch's configs), that
+ * schedule is applied, nothing is launched and *h_from_cache = 1.  Otherwise
+ * every knob is searched by coordinate descent (each value of one knob timed
+ * with the others held, reps replans per setting after one warm-up, HIP
+ * events; a change is kept when it is at least 1 % faster; at most three
+ * sweeps over the knobs), the fastest schedule is applied and, with a
+ * cache_path, stored there; *h_from_cache = 0, and every instance is reset to
+ * its initial state and replan index 0.  h_out / h_ms (may be NULL) receive
+ * the schedule and its milliseconds per replan (the cached figure on a hit).
+ * Static batches only (the server's batch has no fixed mix).
+ */
+mtp_status mtp_batch_tune(mtp_batch* b, int32_t reps, const char* cache_path, mtp_batch_schedule* h_out,
+                          float* h_ms, int32_t* h_from_cache);
+/* Scheduling of the batched launch: signature of a mix for the schedule cache, a 64-bit FNV-1a hash of every
+ * config's shape in order (dynamics, interpolation, links, dimensions, horizon,
+ * graph, candidate counts, elites, iterations, degree, replicas, sampling,
+ * diagnostics, debug states, task-parameter count).  Seeds, weights and other
+ * float parameters do not enter.  Host only; 0 for invalid arguments. */
+uint64_t mtp_batch_mix_signature(const mtp_config* cfgs, int32_t n);
+/* Scheduling of the batched launch: the schedule cache (host only), a JSON file {"format": "mtp-schedules-1", "entries": [{"arch", "cus", "mix",
+ * "wg_per_cu", "order", "cand_tiles", "roll_tiles", "refit_outputs", "split_pct", "ms"}, ...]}.
+ * lookup: *h_found = 1 and the entry's schedule and ms if the file holds the key; 0 if it does not or the file is
+ * missing or unreadable.  store: replaces the key's entry or appends one, keeping every other entry, and writes
+ * the file through a temporary and a rename; MTP_ERR_INVALID_ARG for an invalid schedule or an existing file
+ * that is not such a cache (left untouched). */
+mtp_status mtp_schedule_cache_lookup(const char* path, const char* arch, int32_t cus, uint64_t mix,
+                                     mtp_batch_schedule* h_out, float* h_ms, int32_t* h_found);
+mtp_status mtp_schedule_cache_store(const char* path, const char* arch, int32_t cus, uint64_t mix,
+                                    const mtp_batch_schedule* h_schedule, float ms);
 /* As mtp_set_graph_mode, for the persistent launch. */
 mtp_status mtp_batch_set_graph_mode(mtp_batch* b, int32_t use_graph);
 /* Release the batch object (the workspace stays the caller's). */

@@ -7,6 +7,6 @@ CPU fallback: if the library is missing, `load()` raises.
 """
 from ._native import (  # noqa: F401
     MtpError, load, Plan, Batch, Server, config_struct, task_params_of, lib_path, resident_bytes,
-    transient_bytes, plant_step,
+    transient_bytes, plant_step, mix_signature, schedule_cache_lookup, schedule_cache_store, SCHEDULE_FIELDS,
     STAGE_CANDIDATES, STAGE_ROLLOUT, STAGE_TOPK, STAGE_UPDATE, STAGE_ALL,
 )

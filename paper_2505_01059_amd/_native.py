@@ -100,6 +100,13 @@ def load():
         "mtp_batch_set_state": (c_int32, [P, c_int32, P, P]),
         "mtp_batch_set_schedule": (c_int32, [P, c_int32, c_int32]),
         "mtp_batch_autotune": (c_int32, [P, c_int32, P, P]),
+        "mtp_batch_set_schedule_full": (c_int32, [P, P]),
+        "mtp_batch_get_schedule": (c_int32, [P, P]),
+        "mtp_batch_tune": (c_int32, [P, c_int32, c_char_p, P, POINTER(c_float), POINTER(c_int32)]),
+        "mtp_batch_mix_signature": (c_uint64, [P, c_int32]),
+        "mtp_schedule_cache_lookup": (c_int32, [c_char_p, c_char_p, c_int32, c_uint64, P, POINTER(c_float),
+                                                POINTER(c_int32)]),
+        "mtp_schedule_cache_store": (c_int32, [c_char_p, c_char_p, c_int32, c_uint64, P, c_float]),
         "mtp_batch_set_graph_mode": (c_int32, [P, c_int32]),
         "mtp_batch_destroy": (c_int32, [P]),
         "mtp_batch_last_error": (c_char_p, [P]),
@@ -405,6 +412,46 @@ def _i32(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
 
 
+class mtp_batch_schedule(ctypes.Structure):
+    _fields_ = [(name, c_int32) for name in
+                ("wg_per_cu", "order", "cand_tiles", "roll_tiles", "refit_outputs", "split_pct")]
+
+
+SCHEDULE_FIELDS = tuple(name for name, _ in mtp_batch_schedule._fields_)
+
+
+def _schedule_dict(s):
+    return {name: int(getattr(s, name)) for name in SCHEDULE_FIELDS}
+
+
+def _schedule_struct(d):
+    return mtp_batch_schedule(*[int(d[name]) for name in SCHEDULE_FIELDS])
+
+
+def mix_signature(cfgs):
+    """mtp_batch_mix_signature of a list of workload configs (host only)."""
+    lib = load()
+    structs = [config_struct(c) for c in cfgs]
+    arr = (mtp_config * len(structs))(*[c for c, _ in structs])
+    return int(lib.mtp_batch_mix_signature(arr, len(structs)))
+
+
+def schedule_cache_lookup(path, arch, cus, mix):
+    """(schedule dict, ms) stored under (arch, cus, mix) in the cache file, or None."""
+    lib = load()
+    out, ms, found = mtp_batch_schedule(), c_float(), c_int32()
+    _check(lib, lib.mtp_schedule_cache_lookup(os.fsencode(path), arch.encode(), int(cus), int(mix), byref(out),
+                                              byref(ms), byref(found)))
+    return (_schedule_dict(out), float(ms.value)) if found.value else None
+
+
+def schedule_cache_store(path, arch, cus, mix, schedule, ms):
+    lib = load()
+    s = _schedule_struct(schedule)
+    _check(lib, lib.mtp_schedule_cache_store(os.fsencode(path), arch.encode(), int(cus), int(mix), byref(s),
+                                             float(ms)))
+
+
 class Batch:
     """Many instances replanned by one persistent launch (mtp_batch)."""
 
@@ -496,8 +543,29 @@ class Batch:
         self._err(self.lib.mtp_batch_set_state(self.handle, int(i), c_void_p(mu.data_ptr()),
                                                c_void_p(sg.data_ptr())))
 
-    def set_schedule(self, wg_per_cu, order):
-        self._err(self.lib.mtp_batch_set_schedule(self.handle, int(wg_per_cu), int(order)))
+    def schedule(self):
+        s = mtp_batch_schedule()
+        self._err(self.lib.mtp_batch_get_schedule(self.handle, byref(s)))
+        return _schedule_dict(s)
+
+    def set_schedule(self, wg_per_cu=None, order=None, **knobs):
+        """Set any of the schedule knobs of mtp.h (the others keep their values)."""
+        d = self.schedule()
+        knobs.update({k: v for k, v in (("wg_per_cu", wg_per_cu), ("order", order)) if v is not None})
+        unknown = set(knobs) - set(SCHEDULE_FIELDS)
+        if unknown:
+            raise ValueError(f"unknown schedule knobs {sorted(unknown)}")
+        d.update(knobs)
+        s = _schedule_struct(d)
+        self._err(self.lib.mtp_batch_set_schedule_full(self.handle, byref(s)))
+
+    def tune(self, reps=2, cache_path=None):
+        """Search the schedule (or take it from the cache file); returns (schedule, ms, from_cache)."""
+        out, ms, hit = mtp_batch_schedule(), c_float(), c_int32()
+        self._err(self.lib.mtp_batch_tune(self.handle, int(reps),
+                                          None if cache_path is None else os.fsencode(cache_path), byref(out),
+                                          byref(ms), byref(hit)))
+        return _schedule_dict(out), float(ms.value), bool(hit.value)
 
     def autotune(self, reps=2):
         choice = np.zeros(2, np.int32)

@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmtp.so")
 
-SOURCES = ["kernels.hip", "rollout_quad.hip", "plan.cpp", "batch.hip", "batch.cpp", "server.cpp", "plant.cpp", "noalloc.hip"]
+SOURCES = ["kernels.hip", "rollout_quad.hip", "plan.cpp", "batch.hip", "batch.cpp", "server.cpp", "plant.cpp", "noalloc.hip",
+           "schedule_cache.cpp"]
 # The batched persistent kernel and the quad-lane rollout run one wave per SIMD,
 # and LLVM's iterative ILP scheduler orders their long dependent chains better
 # than the default (measured: 256-instance batched replan 86.1 -> 82.2 ms).

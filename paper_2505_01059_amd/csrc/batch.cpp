@@ -30,16 +30,26 @@ double work_estimate(const mtp_config& c) {
   return B * c.horizon * per_step * c.n_iters;
 }
 
-uint32_t items_for(const mtp_config& c, int k_begin, int k_end, bool cand_split) {
+uint32_t items_for(const mtp_config& c, int k_begin, int k_end, uint32_t shape) {
   const int B = c.n_tensor + c.n_gauss;
   const bool quad = is_quad_chain(c.dynamics, c.n_links);
   const bool pair = is_pair_chain(c.dynamics, c.n_links);
-  const int Pn = c.n_tensor;
-  const uint32_t per_iter = host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhPaths, quad, pair, c.sample_wor != 0) +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhCand, quad, pair, false, cand_split) +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhRoll, quad, pair, false) + 1u +
-                            host_phase_tiles(B, Pn, c.horizon, c.ctrl_dim, kPhUpd, quad, pair, false, cand_split);
+  const bool wor = c.sample_wor != 0;
+  uint32_t per_iter = 0;
+  for (uint32_t ph = kPhPaths; ph <= kPhUpd; ++ph)
+    per_iter += phase_items(B, c.n_tensor, c.horizon, c.ctrl_dim, ph, quad, pair, wor, shape);
   return 1u + per_iter * static_cast<uint32_t>(k_end - k_begin);
+}
+
+uint32_t log2_of(int v) {
+  uint32_t l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
+// Item shape of a loaded launch under schedule s.
+uint32_t coarse_shape(const mtp_batch_schedule& s) {
+  return make_shape(log2_of(s.cand_tiles), 0u, log2_of(s.roll_tiles), log2_of(s.refit_outputs));
 }
 
 struct BatchLayout {
@@ -68,7 +78,7 @@ bool batch_layout(const mtp_config* cfgs, int32_t n, BatchLayout* L, std::string
       return false;
     }
     L->lays.push_back(compute_layout(cfgs[i]));
-    L->capacity += items_for(cfgs[i], 0, cfgs[i].n_iters, true);   // sized for split candidate items
+    L->capacity += items_for(cfgs[i], 0, cfgs[i].n_iters, kShapeFinest);   // sized for the most items
     L->x0_total += cfgs[i].state_dim;
     L->act_total += cfgs[i].ctrl_dim;
   }
@@ -143,7 +153,8 @@ struct mtp_batch {
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   // schedule
-  int cu_count = 1, max_occ = 1, wg_per_cu = 0, order_mode = 1, grid = 1;
+  int cu_count = 1, max_occ = 1, grid = 1;
+  mtp_batch_schedule sched{0, 1, 1, 1, 64, 100};
   std::vector<int32_t> order_natural, order_longest;
   uint64_t wait_ticks = 0;
   bool use_graph = true;
@@ -203,7 +214,7 @@ static BatchLaunch launch_of(mtp_batch* b, int32_t n_active, uint32_t total, con
 }
 
 static void apply_schedule(mtp_batch* b) {
-  const int per_cu = b->wg_per_cu > 0 ? std::min(b->wg_per_cu, b->max_occ) : b->max_occ;
+  const int per_cu = b->sched.wg_per_cu > 0 ? std::min(b->sched.wg_per_cu, b->max_occ) : b->max_occ;
   b->grid = std::max(1, per_cu * b->cu_count);
 }
 
@@ -554,19 +565,20 @@ mtp_status mtp_batch_step(mtp_batch* b, int32_t n_active, const int32_t* h_activ
   }
   // Few active instances leave most workgroups idle while their candidate
   // tiles run, each tile covering all joints one after another, and while
-  // their refit items run 64 outputs each: then every (tile, joint) and every
-  // four outputs become items of their own.  With many instances the items
-  // stay large (far fewer of them through the one queue counter).
-  uint32_t cand_tiles = 0;
+  // their refit items run many outputs each: then every (tile, joint) and
+  // every four outputs become items of their own.  With many instances the
+  // items stay large (far fewer of them through the one queue counter).
+  uint64_t cand_tiles = 0;
   for (int a = 0; a < n_active; ++a) {
     const mtp_config& c = b->cfgs[h_active[a]];
-    cand_tiles += static_cast<uint32_t>((c.n_tensor + c.n_gauss + kCandThreads - 1) / kCandThreads);
+    cand_tiles += static_cast<uint64_t>((c.n_tensor + c.n_gauss + kCandThreads - 1) / kCandThreads);
   }
-  const uint32_t split = cand_tiles < static_cast<uint32_t>(b->grid) ? 1u : 0u;
+  const bool light = cand_tiles * 100u < static_cast<uint64_t>(b->sched.split_pct) * static_cast<uint64_t>(b->grid);
+  const uint32_t shape = light ? kShapeFinest : coarse_shape(b->sched);
   for (int a = 0; a < n_active; ++a) {
     const int i = h_active[a];
-    b->h_ictl[i].cand_split = split;
-    total += items_for(b->cfgs[i], h_k_begin[a], h_k_end[a], split != 0);
+    b->h_ictl[i].shape = shape;
+    total += items_for(b->cfgs[i], h_k_begin[a], h_k_end[a], shape);
   }
   if (total > b->lay.capacity) {
     b->err = "step needs more queue items than the batch was sized for";
@@ -581,7 +593,7 @@ mtp_status mtp_batch_replan(mtp_batch* b, const float* d_x0_packed, const int32_
     b->err = "d_x0_packed is NULL";
     return MTP_ERR_INVALID_ARG;
   }
-  const std::vector<int32_t>& ord = b->order_mode == 1 ? b->order_longest : b->order_natural;
+  const std::vector<int32_t>& ord = b->sched.order == 1 ? b->order_longest : b->order_natural;
   std::vector<int32_t> kb(b->n, 0), ke(b->n), sh(b->n, 0);
   std::vector<uint32_t> rr(b->n, b->next_r);
   for (int a = 0; a < b->n; ++a) {
@@ -635,10 +647,23 @@ mtp_status mtp_batch_set_state(mtp_batch* b, int32_t i, const float* d_mu, const
 }
 
 mtp_status mtp_batch_set_schedule(mtp_batch* b, int32_t wg_per_cu, int32_t order) {
-  if (b == nullptr || wg_per_cu < 0 || order < 0 || order > 1) return MTP_ERR_INVALID_ARG;
-  b->wg_per_cu = wg_per_cu;
-  b->order_mode = order;
+  if (b == nullptr) return MTP_ERR_INVALID_ARG;
+  mtp_batch_schedule s = b->sched;
+  s.wg_per_cu = wg_per_cu;
+  s.order = order;
+  return mtp_batch_set_schedule_full(b, &s);
+}
+
+mtp_status mtp_batch_set_schedule_full(mtp_batch* b, const mtp_batch_schedule* h_schedule) {
+  if (b == nullptr || h_schedule == nullptr || !schedule_valid(*h_schedule)) return MTP_ERR_INVALID_ARG;
+  b->sched = *h_schedule;
   apply_schedule(b);
+  return MTP_OK;
+}
+
+mtp_status mtp_batch_get_schedule(const mtp_batch* b, mtp_batch_schedule* h_schedule) {
+  if (b == nullptr || h_schedule == nullptr) return MTP_ERR_INVALID_ARG;
+  *h_schedule = b->sched;
   return MTP_OK;
 }
 
@@ -648,52 +673,157 @@ mtp_status mtp_batch_set_graph_mode(mtp_batch* b, int32_t use_graph) {
   return MTP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Milliseconds per whole replan of every instance under schedule s: one
+// warm-up launch, then reps launches between two HIP events.  The instances'
+// iterations run from their current state with replan index 0 (the caller
+// resets them afterwards).
+mtp_status time_schedule(mtp_batch* b, const mtp_batch_schedule& s, int reps, hipEvent_t e0, hipEvent_t e1,
+                         float* ms) {
+  mtp_status st = mtp_batch_set_schedule_full(b, &s);
+  if (st != MTP_OK) return st;
+  const std::vector<int32_t>& ord = s.order == 1 ? b->order_longest : b->order_natural;
+  std::vector<int32_t> kb(b->n, 0), ke(b->n), sh(b->n, 0);
+  std::vector<uint32_t> rr(b->n, 0);
+  for (int a = 0; a < b->n; ++a) ke[a] = b->cfgs[ord[a]].n_iters;
+  st = mtp_batch_step(b, b->n, ord.data(), kb.data(), ke.data(), sh.data(), rr.data(), nullptr);
+  if (st != MTP_OK) return st;
+  BCHK(b, hipEventRecord(e0, b->stream), "event");
+  for (int r = 0; r < reps && st == MTP_OK; ++r)
+    st = mtp_batch_step(b, b->n, ord.data(), kb.data(), ke.data(), sh.data(), rr.data(), nullptr);
+  if (st != MTP_OK) return st;
+  BCHK(b, hipEventRecord(e1, b->stream), "event");
+  BCHK(b, hipEventSynchronize(e1), "event sync");
+  float t = 0.0f;
+  BCHK(b, hipEventElapsedTime(&t, e0, e1), "elapsed");
+  *ms = t / static_cast<float>(reps);
+  // the launches must have completed cleanly for their times to count
+  std::vector<float> acts(b->lay.act_total);
+  return mtp_batch_get_actions(b, acts.data());
+}
+
+struct Events {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~Events() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
 mtp_status mtp_batch_autotune(mtp_batch* b, int32_t reps, int32_t* h_choice, float* h_ms) {
   if (b == nullptr || reps < 1) return MTP_ERR_INVALID_ARG;
   if (b->sticky) return MTP_ERR_DEVICE;
-  // x0 of every instance as it stands: stage nothing (x0_packed NULL keeps it)
-  hipEvent_t e0, e1;
-  BCHK(b, hipEventCreate(&e0), "event");
-  BCHK(b, hipEventCreate(&e1), "event");
+  Events ev;
+  BCHK(b, hipEventCreate(&ev.e0), "event");
+  BCHK(b, hipEventCreate(&ev.e1), "event");
   float best = -1.0f;
-  int best_wg = b->wg_per_cu, best_order = b->order_mode;
+  mtp_batch_schedule best_s = b->sched;
   for (int order = 0; order <= 1; ++order) {
     for (int wg = 1; wg <= b->max_occ; ++wg) {
-      mtp_batch_set_schedule(b, wg, order);
-      const std::vector<int32_t>& ord = order == 1 ? b->order_longest : b->order_natural;
-      std::vector<int32_t> kb(b->n, 0), ke(b->n), sh(b->n, 0);
-      std::vector<uint32_t> rr(b->n, 0);
-      for (int a = 0; a < b->n; ++a) ke[a] = b->cfgs[ord[a]].n_iters;
-      mtp_status s = mtp_batch_step(b, b->n, ord.data(), kb.data(), ke.data(), sh.data(), rr.data(), nullptr);
-      if (s != MTP_OK) return s;
-      BCHK(b, hipEventRecord(e0, b->stream), "event");
-      for (int r = 0; r < reps && s == MTP_OK; ++r)
-        s = mtp_batch_step(b, b->n, ord.data(), kb.data(), ke.data(), sh.data(), rr.data(), nullptr);
-      if (s != MTP_OK) return s;
-      BCHK(b, hipEventRecord(e1, b->stream), "event");
-      BCHK(b, hipEventSynchronize(e1), "event sync");
+      mtp_batch_schedule s = b->sched;
+      s.wg_per_cu = wg;
+      s.order = order;
       float ms = 0.0f;
-      BCHK(b, hipEventElapsedTime(&ms, e0, e1), "elapsed");
-      ms /= static_cast<float>(reps);
+      const mtp_status st = time_schedule(b, s, reps, ev.e0, ev.e1, &ms);
+      if (st != MTP_OK) return st;
       if (best < 0.0f || ms < best) {
         best = ms;
-        best_wg = wg;
-        best_order = order;
+        best_s = s;
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  // verify the last launch completed cleanly
-  std::vector<float> acts(b->lay.act_total);
-  const mtp_status s = mtp_batch_get_actions(b, acts.data());
-  if (s != MTP_OK) return s;
-  mtp_batch_set_schedule(b, best_wg, best_order);
+  mtp_batch_set_schedule_full(b, &best_s);
   if (h_choice) {
-    h_choice[0] = best_wg;
-    h_choice[1] = best_order;
+    h_choice[0] = best_s.wg_per_cu;
+    h_choice[1] = best_s.order;
   }
   if (h_ms) *h_ms = best;
+  return reset_instances(b);
+}
+
+mtp_status mtp_batch_tune(mtp_batch* b, int32_t reps, const char* cache_path, mtp_batch_schedule* h_out,
+                          float* h_ms, int32_t* h_from_cache) {
+  if (b == nullptr || reps < 1) return MTP_ERR_INVALID_ARG;
+  if (b->dynamic) {
+    b->err = "a batch without a fixed mix (the server's) cannot be tuned";
+    return MTP_ERR_INVALID_ARG;
+  }
+  if (b->sticky) return MTP_ERR_DEVICE;
+  if (h_from_cache) *h_from_cache = 0;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  BCHK(b, hipGetDevice(&dev), "device");
+  BCHK(b, hipGetDeviceProperties(&prop, dev), "device properties");
+  const std::string arch = prop.gcnArchName;
+  const uint64_t mix = mtp_batch_mix_signature(b->cfgs.data(), b->n);
+  if (cache_path != nullptr) {
+    mtp_batch_schedule s;
+    float ms = 0.0f;
+    int32_t found = 0;
+    if (mtp_schedule_cache_lookup(cache_path, arch.c_str(), b->cu_count, mix, &s, &ms, &found) == MTP_OK && found &&
+        mtp_batch_set_schedule_full(b, &s) == MTP_OK) {
+      if (h_out) *h_out = s;
+      if (h_ms) *h_ms = ms;
+      if (h_from_cache) *h_from_cache = 1;
+      return MTP_OK;
+    }
+  }
+  Events ev;
+  BCHK(b, hipEventCreate(&ev.e0), "event");
+  BCHK(b, hipEventCreate(&ev.e1), "event");
+  // coordinate descent from the current schedule: one knob at a time, every
+  // value of it with the others held; a change must win by 1 %
+  mtp_batch_schedule best = b->sched;
+  float best_ms = 0.0f;
+  mtp_status st = time_schedule(b, best, reps, ev.e0, ev.e1, &best_ms);
+  if (st != MTP_OK) return st;
+  std::vector<int> wgs;
+  for (int w = 1; w <= b->max_occ; ++w) wgs.push_back(w);
+  const std::vector<int> orders{0, 1}, tiles{1, 2, 4}, outputs{4, 8, 16, 32, 64}, pcts{0, 25, 100, 400, 1 << 30};
+  struct Knob {
+    int32_t mtp_batch_schedule::*field;
+    const std::vector<int>* values;
+  };
+  const Knob knobs[] = {{&mtp_batch_schedule::wg_per_cu, &wgs},       {&mtp_batch_schedule::order, &orders},
+                        {&mtp_batch_schedule::split_pct, &pcts},      {&mtp_batch_schedule::cand_tiles, &tiles},
+                        {&mtp_batch_schedule::roll_tiles, &tiles},    {&mtp_batch_schedule::refit_outputs, &outputs}};
+  for (int sweep = 0; sweep < 3; ++sweep) {
+    bool changed = false;
+    for (const Knob& k : knobs) {
+      for (const int v : *k.values) {
+        if (best.*(k.field) == v) continue;
+        mtp_batch_schedule s = best;
+        s.*(k.field) = v;
+        float ms = 0.0f;
+        st = time_schedule(b, s, reps, ev.e0, ev.e1, &ms);
+        if (st != MTP_OK) return st;
+        if (ms < 0.99f * best_ms) {
+          best = s;
+          best_ms = ms;
+          changed = true;
+        }
+      }
+    }
+    if (!changed) break;
+  }
+  mtp_batch_set_schedule_full(b, &best);
+  if (cache_path != nullptr) {
+    st = mtp_schedule_cache_store(cache_path, arch.c_str(), b->cu_count, mix, &best, best_ms);
+    if (st != MTP_OK) {
+      b->err = std::string("schedule cache not written: ") + cache_path;
+      (void)reset_instances(b);
+      return st;
+    }
+  }
+  if (h_out) *h_out = best;
+  if (h_ms) *h_ms = best_ms;
   return reset_instances(b);
 }
 

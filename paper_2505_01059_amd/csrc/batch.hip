@@ -18,24 +18,9 @@
 
 namespace mtp {
 
-__device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phase, uint32_t cand_split) {
-  switch (phase) {
-    case kPhShift: return 1u;
-    case kPhPaths: return (P.P > 0 && P.wor) ? static_cast<uint32_t>((P.P + kCandThreads - 1) / kCandThreads) : 1u;
-    case kPhCand:
-      return static_cast<uint32_t>((P.B + kCandThreads - 1) / kCandThreads) * (cand_split ? static_cast<uint32_t>(P.n) : 1u);
-    case kPhRoll: {
-      const int per = is_quad_chain(P.dyn, P.n_links)   ? kBatchThreads / 4
-                      : is_pair_chain(P.dyn, P.n_links) ? kBatchThreads / 2
-                                                         : kBatchThreads;
-      return static_cast<uint32_t>((P.B + per - 1) / per);
-    }
-    case kPhTopk: return 1u;
-    default: {
-      const int per = cand_split ? kUpdOutputsPerTileSplit : kUpdOutputsPerTile;
-      return static_cast<uint32_t>((P.T * P.n + per - 1) / per);
-    }
-  }
+__device__ __forceinline__ uint32_t phase_tiles(const PlanDesc& P, uint32_t phase, uint32_t shape) {
+  return phase_items(P.B, P.P, P.T, P.n, phase, is_quad_chain(P.dyn, P.n_links), is_pair_chain(P.dyn, P.n_links),
+                     P.wor != 0, shape);
 }
 
 union BatchSmem {
@@ -122,36 +107,41 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
   const int tid = threadIdx.x;
   const uint32_t epoch = ctl->epoch;
   const uint32_t total = ctl->total;
+  // rollout items of several tiles run one tile per pass of this loop: `sub`
+  // is the tile of the current item to run next (0: take a new item)
+  uint32_t sub = 0;
   for (;;) {
-    if (tid == 0) {
-      sh.pos = atomicAdd(&ctl->head, 1u);
-      sh.abort = 0;
-    }
-    __syncthreads();
-    const uint32_t pos = sh.pos;
-    if (pos >= total) break;
-    if (tid == 0) {
-      const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&ready[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-            wall_clock64() - t0 > wait_ticks) {
-          atomicOr(&ctl->error, 1u);
-          sh.abort = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+    if (sub == 0u) {
+      if (tid == 0) {
+        sh.pos = atomicAdd(&ctl->head, 1u);
+        sh.abort = 0;
       }
-      if (!sh.abort) sh.item = queue[pos];
+      __syncthreads();
+      const uint32_t pos = sh.pos;
+      if (pos >= total) break;
+      if (tid == 0) {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(&ready[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+          if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+              wall_clock64() - t0 > wait_ticks) {
+            atomicOr(&ctl->error, 1u);
+            sh.abort = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if (!sh.abort) sh.item = queue[pos];
+      }
+      __syncthreads();
+      if (sh.abort) break;
+      // acquire: the item's inputs were released by the workgroups that made
+      // them (only an invalidation here, no write-back)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __syncthreads();
-    if (sh.abort) break;
-    // acquire: the item's inputs were released by the workgroups that made
-    // them (only an invalidation here, no write-back)
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t inst = __builtin_amdgcn_readfirstlane(sh.item.inst);
     const uint32_t phase_word = __builtin_amdgcn_readfirstlane(sh.item.phase);
     const uint32_t phase = phase_word & kItemPhaseMask;
-    const uint32_t split = phase_word >> kItemSplitShift;   // the instance's candidate split, carried by its items
+    const uint32_t shape = phase_word >> kItemShapeShift;   // the instance's item shape, carried by its items
     const uint32_t k = __builtin_amdgcn_readfirstlane(sh.item.k);
     const uint32_t tile = __builtin_amdgcn_readfirstlane(sh.item.tile);
     const PlanDesc P = descs[inst];
@@ -161,25 +151,31 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         shift_block<kBatchThreads>(P, static_cast<int>(P.ctrl[1]));
         break;
       case kPhPaths:
-        path_tile(P, P.ctrl[0], static_cast<int>(k), static_cast<int>(tile), static_cast<int>(phase_tiles(P, kPhPaths, split)),
+        path_tile(P, P.ctrl[0], static_cast<int>(k), static_cast<int>(tile), static_cast<int>(phase_tiles(P, kPhPaths, shape)),
                   sm.path);
         break;
       case kPhCand: {
-        // an item is a candidate tile with all its joints, or (split, when few
-        // instances are active) one joint of a tile
+        // an item is 2^cand_lg consecutive candidate tiles with all their
+        // joints, or one joint of them
         const uint32_t r = P.ctrl[0];
         const CandView v = cand_view(sm.cand);
-        const int ct = split ? static_cast<int>(tile) / P.n : static_cast<int>(tile);
-        const int j0 = split ? static_cast<int>(tile) - ct * P.n : 0;
-        const int j1 = split ? j0 + 1 : P.n;
-        for (int j = j0; j < j1; ++j) {
-          cand_tile(P, r, static_cast<int>(k), j, ct * kCandThreads, 0, P.T, v);
-          __syncthreads();
-        }
+        const bool one_joint = shape_cand_joint(shape) != 0u;
+        const int group = one_joint ? static_cast<int>(tile) / P.n : static_cast<int>(tile);
+        const int j0 = one_joint ? static_cast<int>(tile) - group * P.n : 0;
+        const int j1 = one_joint ? j0 + 1 : P.n;
+        const int per = 1 << shape_cand_lg(shape);
+        const int n_tiles = (P.B + kCandThreads - 1) / kCandThreads;
+        const int ct1 = min(group * per + per, n_tiles);
+        for (int ct = group * per; ct < ct1; ++ct)
+          for (int j = j0; j < j1; ++j) {
+            cand_tile(P, r, static_cast<int>(k), j, ct * kCandThreads, 0, P.T, v);
+            __syncthreads();
+          }
         break;
       }
       case kPhRoll:
-        run_rollout_tile(P, tile, sm);
+        // an item is 2^roll_lg consecutive rollout tiles, one per pass
+        run_rollout_tile(P, (tile << shape_roll_lg(shape)) + sub, sm);
         break;
       case kPhTopk:
         topk_block<kBatchThreads>(P, sm.topk);
@@ -190,7 +186,7 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         break;
       default: {
         const int wave = tid >> 6;
-        const int per = split ? kUpdOutputsPerTileSplit : kUpdOutputsPerTile;
+        const int per = 1 << shape_upd_lg(shape);
         const int base = static_cast<int>(tile) * per;
         for (int m = wave; m < per; m += kBatchThreads / 64) {
           const int o = base + m;
@@ -203,11 +199,20 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
     // reached the L2) one wave writes the L2 back for the other XCDs, instead
     // of every wave doing it
     __syncthreads();
+    if (phase == kPhRoll) {
+      const uint32_t lg = shape_roll_lg(shape);
+      const uint32_t next = (tile << lg) + sub + 1u;
+      if (sub + 1u < (1u << lg) && next < phase_tiles(P, kPhRoll, 0u)) {
+        ++sub;   // the same item's next tile (the barrier above ordered its LDS reuse)
+        continue;
+      }
+      sub = 0;
+    }
 
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       sh.publish = 0;
-      const uint32_t nt = phase_tiles(P, phase, split);
+      const uint32_t nt = phase_tiles(P, phase, shape);
       const uint32_t done = atomicAdd(&ictl[inst].done, 1u) + 1u;
       if (done == nt) {
         // acquire the other tiles' results (released before their counts)
@@ -224,7 +229,7 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
         if (phase == kPhUpd && nk >= ictl[inst].k_end) {
           atomicAdd(&ctl->finished, 1u);
         } else {
-          const uint32_t m = phase_tiles(P, nph, split);
+          const uint32_t m = phase_tiles(P, nph, shape);
           sh.pub_pos = atomicAdd(&ctl->tail, m);
           sh.pub_count = m;
           sh.pub_phase = nph;
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(kBatchThreads, MTP_BATCH_MIN_WG_PER_CU) void k_batc
       if (p0 + m <= ctl->capacity) {
         for (uint32_t t = tid; t < m; t += kBatchThreads) {
           BatchItem it;
-          it.inst = inst; it.phase = sh.pub_phase | (split << kItemSplitShift); it.k = sh.pub_k; it.tile = t;
+          it.inst = inst; it.phase = sh.pub_phase | (shape << kItemShapeShift); it.k = sh.pub_k; it.tile = t;
           queue[p0 + t] = it;
         }
         // one release (one L2 write-back) in wave 0, which then sets the ready
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(64) void k_batch_init(const PlanDesc* __restrict__ 
     const uint32_t epoch = ctl->epoch + 1u;   // ctl is rewritten by the host-side reset below
     BatchItem it;
     it.inst = static_cast<uint32_t>(i);
-    it.phase = kPhShift | (ic.cand_split << kItemSplitShift);
+    it.phase = kPhShift | (ic.shape << kItemShapeShift);
     it.k = ic.k_begin;
     it.tile = 0u;
     queue[slot] = it;

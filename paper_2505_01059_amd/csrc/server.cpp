@@ -311,14 +311,14 @@ struct Robot {
 };
 
 // Queue items one launch may need for a robot: iters_per_launch iterations in
-// the split form (the larger one).
+// the finest item shape (the most items).
 uint32_t launch_items(const mtp_config& c, int iters_per_launch) {
   const int B = c.n_tensor + c.n_gauss;
   const bool quad = is_quad_chain(c.dynamics, c.n_links);
   const bool pair = is_pair_chain(c.dynamics, c.n_links);
   uint32_t per = 1u;
   for (uint32_t ph = kPhPaths; ph <= kPhUpd; ++ph)
-    per += host_phase_tiles(B, c.n_tensor, c.horizon, c.ctrl_dim, ph, quad, pair, c.sample_wor != 0, true);
+    per += phase_items(B, c.n_tensor, c.horizon, c.ctrl_dim, ph, quad, pair, c.sample_wor != 0, kShapeFinest);
   return 1u + per * static_cast<uint32_t>(std::min(iters_per_launch, c.n_iters));
 }
 

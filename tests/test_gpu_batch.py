@@ -180,6 +180,98 @@ def test_batch_autotune_and_reset():
     bt.close()
 
 
+# Schedules far from the default: several candidate and rollout tiles per item,
+# few refit outputs per item, the finest items always, and never.
+SCHEDULES = [
+    dict(cand_tiles=4, roll_tiles=2, refit_outputs=8, split_pct=0),
+    dict(cand_tiles=2, roll_tiles=4, refit_outputs=16, split_pct=0, order=0),
+    dict(cand_tiles=4, roll_tiles=4, refit_outputs=32, split_pct=1 << 30),
+    dict(cand_tiles=1, roll_tiles=1, refit_outputs=4, split_pct=0, wg_per_cu=1),
+]
+
+
+def test_every_schedule_gives_the_standalone_bits():
+    """Item shapes, split threshold, queue order and grid change which
+    workgroup computes what, never a value: every instance under every
+    schedule equals its standalone plan bit for bit."""
+    import paper_2505_01059_amd as mtp
+    cfgs = small_mix()
+    x0s = [W.initial_state(c, seed=50 + i) for i, c in enumerate(cfgs)]
+    ref = [standalone(c, x0s[i], 2) for i, c in enumerate(cfgs)]
+    for sched in SCHEDULES:
+        _log(f"[schedule] {sched}")
+        bt = mtp.Batch(cfgs, device="cuda:0")
+        bt.set_schedule(**sched)
+        got = bt.schedule()
+        assert all(got[k] == v for k, v in sched.items()), got
+        xp = bt.pack_x0(x0s)
+        for r in range(2):
+            bt.replan(xp, shift=1)
+        acts = bt.actions()
+        for i, c in enumerate(cfgs):
+            mu, sg, a, ent = ref[i]
+            b = bt.buffers(i)
+            assert np.array_equal(b["mu"].cpu().numpy(), mu), (c.name, sched)
+            assert np.array_equal(b["sigma"].cpu().numpy(), sg), (c.name, sched)
+            assert np.array_equal(acts[i], a), (c.name, sched)
+            if c.diagnostics:
+                assert np.array_equal(b["entropy"].cpu().numpy(), ent), (c.name, sched)
+        bt.close()
+
+
+def test_unsupported_schedules_are_refused():
+    import paper_2505_01059_amd as mtp
+    bt = mtp.Batch(small_mix()[:2], device="cuda:0")
+    before = bt.schedule()
+    for bad in (dict(cand_tiles=3), dict(roll_tiles=8), dict(refit_outputs=2), dict(order=2)):
+        with pytest.raises(mtp.MtpError):
+            bt.set_schedule(**bad)
+        assert bt.schedule() == before
+    bt.close()
+
+
+def test_tuned_schedule_is_cached_and_reused(tmp_path):
+    """The first tune searches and writes the cache; a new batch of the same
+    mix on the same GPU takes the cached schedule without searching, and its
+    replans equal the standalone plans bit for bit."""
+    import json
+    import torch
+    import paper_2505_01059_amd as mtp
+    cfgs = small_mix()[:5]
+    x0s = [W.initial_state(c, seed=60 + i) for i, c in enumerate(cfgs)]
+    path = str(tmp_path / "schedules.json")
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    sched, ms, hit = bt.tune(reps=1, cache_path=path)
+    _log(f"[tune] {sched} {ms:.3f} ms from_cache={hit}")
+    assert not hit and ms > 0 and bt.schedule() == sched
+    bt.close()
+    (entry,) = json.load(open(path))["entries"]
+    props = torch.cuda.get_device_properties(0)
+    assert entry["cus"] == props.multi_processor_count
+    assert entry["arch"].split(":")[0] == props.gcnArchName.split(":")[0]
+    assert entry["mix"] == f"{mtp.mix_signature(cfgs):016x}"
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    sched2, ms2, hit2 = bt.tune(reps=1, cache_path=path)
+    assert hit2 and sched2 == sched and ms2 == pytest.approx(ms, rel=1e-5)
+    assert bt.schedule() == sched
+    xp = bt.pack_x0(x0s)
+    bt.replan(xp, shift=1)
+    acts = bt.actions()
+    for i, c in enumerate(cfgs):
+        mu, sg, a, _ = standalone(c, x0s[i], 1)
+        b = bt.buffers(i)
+        assert np.array_equal(b["mu"].cpu().numpy(), mu), c.name
+        assert np.array_equal(b["sigma"].cpu().numpy(), sg), c.name
+        assert np.array_equal(acts[i], a), c.name
+    bt.close()
+    # another mix misses and adds its own entry
+    bt = mtp.Batch(cfgs[:3], device="cuda:0")
+    _, _, hit3 = bt.tune(reps=1, cache_path=path)
+    assert not hit3
+    assert len(json.load(open(path))["entries"]) == 2
+    bt.close()
+
+
 def test_mix_of_256_sampled_against_standalone():
     """The full uneven mix in one launch; a sample of instances checked bit for bit."""
     import torch
