@@ -1,5 +1,7 @@
 // Single-plan kernels of one MTP replan for gfx950 and their host launchers.
 // Each kernel is a thin grid over the stage tiles of mtp_device.hpp.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "rollout_grid.hpp"
 
@@ -72,6 +74,13 @@ __global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(N >= 20) void k_rollou
   if (threadIdx.x == 0 && __hip_atomic_load(&P.seg_ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
     atomicOr(&P.ctrl[2], 4u);
 }
+
+// Tensor-path controls of iteration P.gen_k into P.U2 (P.roll_blocks = 0: every
+// workgroup draws), run beside a time-sliced rollout that holds one wave per
+// SIMD.  The launch asks for LDS that admits at most two of these workgroups on
+// a compute unit, so the rollout's workgroup finds its registers free on every
+// unit whichever kernel is dispatched first.
+__global__ __launch_bounds__(kCandThreads) void k_gen_tensor(PlanDesc P) { gen_tensor_tiles(P); }
 
 // New launch of the time-sliced rollout: next epoch, unit counter and error cleared.
 __global__ __launch_bounds__(64) void k_seg_init(SegCtl* ctl) {
@@ -151,6 +160,8 @@ int rollout_blocks(const PlanDesc& P) {
 // its SIMDs (the dispatcher was seen to pair workgroups on a unit now and
 // then, which doubles those waves' time).
 constexpr size_t kOnePerUnitLds = 96 * 1024;
+// LDS that leaves room for at most two workgroups per compute unit.
+constexpr size_t kTwoPerUnitLds = 64 * 1024;
 
 // LDS of a rollout launch that also draws tensor-path controls: the candidate
 // tile's arrays over the whole horizon, at least kOnePerUnitLds.
@@ -300,16 +311,45 @@ hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st) {
 // nominal mean there from each refitted (t, j), so iteration k+1 launches no
 // candidate kernel.  The values are those of the plain sequence: the tensor
 // paths do not depend on the sampling distribution.
-hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st) {
+hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st,
+                                  const SideLane* side) {
   // the plan's layout assumed a 256-unit chip; a device without a free unit
   // beyond the rollout's workgroups runs the plain sequence
-  const bool overlap = P.U2 != nullptr && P.gen_grid > rollout_blocks(P);
+  const bool sliced = is_pair_chain(P.dyn, P.n_links) && P.seg_ctl != nullptr && P.seg_grid > 0;
+  const bool overlap = P.U2 != nullptr && (sliced || P.gen_grid > rollout_blocks(P));
   if (!overlap) return launch_stage(P, stage, k, st);
   PlanDesc Pk = P;
   if ((k1 - 1 - k) & 1) { Pk.U = P.U2; Pk.U2 = P.U; }
   switch (stage) {
     case 0: return k > k0 ? hipSuccess : launch_candidates(Pk, k, st);
-    case 1: return launch_rollout(Pk, st, k + 1 < k1 ? k + 1 : -1);
+    case 1: {
+      if (!sliced) return launch_rollout(Pk, st, k + 1 < k1 ? k + 1 : -1);
+      if (k + 1 >= k1) return launch_rollout(Pk, st, -1);
+      PlanDesc G = Pk;
+      G.roll_blocks = 0;
+      G.gen_k = k + 1;
+      const size_t tile = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, P.T < kTChunk ? P.T : kTChunk));
+      const size_t lds = std::max(tile, kTwoPerUnitLds);
+      const hipStream_t gs = side != nullptr ? side->st : st;
+      hipError_t e = hipSuccess;
+      if (side != nullptr) {
+        e = hipEventRecord(side->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->st, side->fork, 0);
+        if (e != hipSuccess) return e;
+        k_gen_tensor<<<2 * G.gen_grid, kCandThreads, lds, gs>>>(G);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+      e = launch_rollout(Pk, st, -1);
+      if (e != hipSuccess) return e;
+      if (side == nullptr) {
+        k_gen_tensor<<<2 * G.gen_grid, kCandThreads, lds, gs>>>(G);
+        return hipGetLastError();
+      }
+      e = hipEventRecord(side->join, side->st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+      return e;
+    }
     case 3: {
       if (k + 1 >= k1) return launch_stage(Pk, stage, k, st);
       k_update_next<<<Pk.T * Pk.n, kUpdThreads, 0, st>>>(Pk, k + 1);

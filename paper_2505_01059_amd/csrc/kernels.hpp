@@ -12,9 +12,19 @@ hipError_t launch_set_ctrl(const PlanDesc& P, uint32_t r, int shift, const float
 hipError_t launch_shift(const PlanDesc& P, hipStream_t st);
 // stage: 0 candidates, 1 rollout, 2 top-E, 3 refit (the replan index is read from P.ctrl[0])
 hipError_t launch_stage(const PlanDesc& P, int stage, int k, hipStream_t st);
+// A second stream that a launch sequence forks work onto and joins back from
+// (fork / join events recorded on the streams; usable under graph capture).
+struct SideLane {
+  hipStream_t st;
+  hipEvent_t fork, join;
+};
 // Stage of iteration k in a run of iterations [k0, k1) (next iteration's tensor
-// paths drawn during the rollout when the plan has a second U buffer).
-hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st);
+// paths drawn during the rollout when the plan has a second U buffer).  A
+// time-sliced rollout fills every SIMD, so there the next tensor paths are drawn
+// by a kernel of their own on `side`, beside the rollout (on `st` after it when
+// side is null).
+hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, int k1, hipStream_t st,
+                                  const SideLane* side = nullptr);
 // Quad-lane chain rollout (rollout_quad.hip); one: the launch holds one
 // workgroup per compute unit.
 hipError_t launch_rollout_quad(const PlanDesc& P, dim3 grid, size_t lds, hipStream_t st, bool one);

@@ -234,6 +234,7 @@ struct mtp_plan {
   PlanDesc P;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  SideLane side{nullptr, nullptr, nullptr};   // second stream of plans that draw beside a time-sliced rollout
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   bool use_graph = true;
@@ -283,7 +284,8 @@ void mtp::set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8
 bool mtp::uses_gen_overlap(const mtp_config& c) {
   constexpr long long kUnits = 256;     // compute units
   constexpr long long kMinFree = 32;    // units left for drawing the next tensor paths
-  if (c.n_iters < 2 || c.sample_wor || c.n_tensor < 1 || uses_segmented_rollout(c)) return false;
+  if (c.n_iters < 2 || c.sample_wor || c.n_tensor < 1) return false;
+  if (uses_segmented_rollout(c)) return true;
   const long long B = static_cast<long long>(c.n_tensor) + c.n_gauss;
   const bool chain = c.dynamics == MTP_DYN_CHAIN || c.dynamics == MTP_DYN_CHAIN_CONTACT;
   const bool quad = c.dynamics == MTP_DYN_CHAIN && c.n_links >= 5 && c.n_links <= 8;
@@ -407,10 +409,10 @@ mtp_status mtp::upload_plan_tables(const mtp_config& c, const PlanDesc& P, const
   return MTP_OK;
 }
 
-hipError_t mtp::enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStream_t st) {
+hipError_t mtp::enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStream_t st, const SideLane* side) {
   for (int k = k_begin; k < k_end; ++k)
     for (int stage = 0; stage < 4; ++stage) {
-      const hipError_t e = launch_iteration_stage(P, stage, k, k_begin, k_end, st);
+      const hipError_t e = launch_iteration_stage(P, stage, k, k_begin, k_end, st, side);
       if (e != hipSuccess) return e;
     }
   return hipSuccess;
@@ -442,15 +444,34 @@ static hipError_t drain_events(mtp_plan* p) {
 
 // Launch iterations [k0, k1) one kernel at a time, with event pairs around each
 // stage when timing is on.
+// The plan's second stream and its fork / join events, created on first use by
+// plans that draw the next tensor paths beside a time-sliced rollout; null for
+// the others.
+static hipError_t side_lane(mtp_plan* p, const SideLane** out) {
+  *out = nullptr;
+  if (!(p->lay.overlap && p->lay.segmented)) return hipSuccess;
+  if (p->side.st == nullptr) {
+    hipError_t e = hipStreamCreateWithFlags(&p->side.st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->side.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->side.join, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  *out = &p->side;
+  return hipSuccess;
+}
+
 static hipError_t enqueue_iterations_plan(mtp_plan* p, int k0, int k1) {
-  if (!p->timing) return enqueue_iterations(p->P, k0, k1, p->stream);
+  const SideLane* side = nullptr;
+  hipError_t es = side_lane(p, &side);
+  if (es != hipSuccess) return es;
+  if (!p->timing) return enqueue_iterations(p->P, k0, k1, p->stream, side);
   for (int k = k0; k < k1; ++k)
     for (int stage = 0; stage < 4; ++stage) {
       hipEvent_t a, b;
       hipError_t e = take_event(p, &a);
       if (e == hipSuccess) e = take_event(p, &b);
       if (e == hipSuccess) e = hipEventRecord(a, p->stream);
-      if (e == hipSuccess) e = launch_iteration_stage(p->P, stage, k, k0, k1, p->stream);
+      if (e == hipSuccess) e = launch_iteration_stage(p->P, stage, k, k0, k1, p->stream, side);
       if (e == hipSuccess) e = hipEventRecord(b, p->stream);
       if (e != hipSuccess) return e;
       p->pending.push_back({stage, a, b});
@@ -531,9 +552,11 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
 static mtp_status ensure_graph(mtp_plan* p) {
   if (p->exec) return MTP_OK;
   if (!p->cap_stream) HIPCHK(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "stream create");
+  const SideLane* side = nullptr;
+  HIPCHK(p, side_lane(p, &side), "side stream create");
   HIPCHK(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   hipError_t e = launch_shift(p->P, p->cap_stream);
-  if (e == hipSuccess) e = enqueue_iterations(p->P, 0, p->cfg.n_iters, p->cap_stream);
+  if (e == hipSuccess) e = enqueue_iterations(p->P, 0, p->cfg.n_iters, p->cap_stream, side);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
   if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return device_err(p, e, "capture launch"); }
@@ -621,7 +644,7 @@ mtp_status mtp_run_stage(mtp_plan* p, int32_t stage, uint32_t replan_idx, int32_
 }
 
 int32_t mtp_plan_draws_ahead(const mtp_plan* p) {
-  return (p != nullptr && p->lay.overlap && p->P.gen_grid > rollout_blocks(p->P)) ? 1 : 0;
+  return (p != nullptr && p->lay.overlap && (p->lay.segmented || p->P.gen_grid > rollout_blocks(p->P))) ? 1 : 0;
 }
 
 mtp_status mtp_set_graph_mode(mtp_plan* p, int32_t use_graph) {
@@ -671,6 +694,9 @@ mtp_status mtp_plan_destroy(mtp_plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->side.fork) (void)hipEventDestroy(p->side.fork);
+  if (p->side.join) (void)hipEventDestroy(p->side.join);
+  if (p->side.st) (void)hipStreamDestroy(p->side.st);
   delete p;
   return MTP_OK;
 }

@@ -34,7 +34,9 @@ Layout compute_layout(const mtp_config& c, bool plan = false);
 void build_tables(const mtp_config& c, std::vector<float>* basis, std::vector<int32_t>* span);
 mtp_status upload_plan_tables(const mtp_config& c, const PlanDesc& P, const float* task, const float* sparams,
                               hipStream_t st, std::string* err);
-hipError_t enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStream_t st);
+struct SideLane;
+hipError_t enqueue_iterations(const PlanDesc& P, int k_begin, int k_end, hipStream_t st,
+                              const SideLane* side = nullptr);
 PlanDesc make_desc(const mtp_config& c, const Layout& L, uint8_t* resident, uint8_t* transient);
 // Point a descriptor's transient buffers at a new base.
 void set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* transient);
@@ -43,9 +45,10 @@ void set_transient(PlanDesc* P, const mtp_config& c, const Layout& L, uint8_t* t
 // the chip has SIMDs.
 bool uses_segmented_rollout(const mtp_config& c);
 // Whether a single plan draws the next iteration's tensor-path controls during
-// each rollout: more than one iteration, with-replacement tensor paths,
-// no time slicing, and a rollout that leaves at least 32 of the 256 compute
-// units free.
+// each rollout: more than one iteration, with-replacement tensor paths, and
+// either a time-sliced rollout (the paths are then drawn by a kernel of their
+// own beside it) or a rollout that leaves at least 32 of the 256 compute units
+// free (drawn by workgroups the rollout launch adds).
 bool uses_gen_overlap(const mtp_config& c);
 // Segments of the time-sliced rollout for a given number of resident waves.
 int segment_count(int groups, int resident_waves);

@@ -223,9 +223,11 @@ def test_transient_bytes_smaller_than_plan_workspace():
 
 def test_single_plan_overlap_buffer():
     """A single plan that draws the next iteration's tensor paths during the
-    rollout holds a second [T][n][ldU] candidate buffer; plans that cannot
+    rollout holds a second [T][n][ldU] candidate buffer (also a time-sliced
+    rollout, beside which a kernel of their own draws them); plans that cannot
     (paths without replacement, one iteration, no tensor paths, a rollout that
-    fills the chip) and the server's transient slabs do not."""
+    fills the chip without time slicing) and the server's transient slabs do
+    not."""
     c1 = W.c1()
     B = c1.n_tensor + c1.n_gauss
     ldU = (B * 4 + 255) // 256 * 256 // 4
@@ -233,8 +235,12 @@ def test_single_plan_overlap_buffer():
     assert N.workspace_bytes(c1) - N.workspace_bytes(c1.replace(sample_wor=1)) == u_bytes
     assert N.transient_bytes(c1) == N.transient_bytes(c1.replace(sample_wor=1))
     big = c1.replace(n_tensor=16384, n_gauss=1024)          # 4 lanes x 17408 candidates = 272 workgroups
-    for off in (c1.replace(n_iters=1), c1.replace(n_tensor=0, n_gauss=9216), big, W.c4()):
+    for off in (c1.replace(n_iters=1), c1.replace(n_tensor=0, n_gauss=9216), big, W.c4().replace(n_iters=1)):
         assert N.workspace_bytes(off) == N.workspace_bytes(off.replace(sample_wor=1)), off.name
+    c4 = W.c4()                                              # time-sliced: 2176 pair-lane waves
+    ldU4 = (c4.n_samples * 4 + 255) // 256 * 256 // 4
+    assert N.workspace_bytes(c4) - N.workspace_bytes(c4.replace(sample_wor=1)) == c4.horizon * c4.ctrl_dim * ldU4 * 4
+    assert N.transient_bytes(c4) == N.transient_bytes(c4.replace(sample_wor=1))
 
 
 def test_one_hip_runtime_whatever_the_import_order():

@@ -64,6 +64,12 @@ def overlap_mix():
         # randomised replicas on the one-lane contact rollout
         W.chain_contact_config(name="o_k7r2", n_links=7, n_tensor=1100, n_gauss=90, horizon=28, n_layers=5,
                                n_width=12, n_elites=20, n_iters=2, seed=28, n_replicas=2),
+        # time-sliced pair-lane rollouts (more pair-lane waves than SIMDs): the
+        # next tensor paths are drawn by their own kernel beside the rollout
+        W.chain_config(name="o_c12s", n_links=12, interp=W.BSPLINE, n_tensor=32000, n_gauss=1000, horizon=16,
+                       n_layers=5, n_width=16, n_elites=64, n_iters=3, seed=29),
+        W.chain_contact_config(name="o_k24s", n_links=24, n_tensor=32800, n_gauss=70, horizon=24, n_layers=6,
+                               n_width=12, n_elites=48, n_iters=2, seed=30, ground_y=-0.02),
     ]
 
 
