@@ -10,14 +10,16 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmtp.so")
 
-SOURCES = ["kernels.hip", "rollout_quad.hip", "plan.cpp", "batch.hip", "batch.cpp", "server.cpp", "plant.cpp", "noalloc.hip",
+SOURCES = ["kernels.hip", "rollout_quad.hip", "rollout_seg.hip", "plan.cpp", "batch.hip", "batch.cpp", "server.cpp", "plant.cpp", "noalloc.hip",
            "schedule_cache.cpp"]
-# The batched persistent kernel and the quad-lane rollout run one wave per SIMD,
-# and LLVM's iterative ILP scheduler orders their long dependent chains better
-# than the default (measured: 256-instance batched replan 86.1 -> 82.2 ms).
+# The batched persistent kernel, the quad-lane and the time-sliced pair-lane
+# rollouts run one wave per SIMD, and LLVM's iterative ILP scheduler orders their
+# long dependent chains better than the default (measured: 256-instance batched
+# replan 86.1 -> 82.2 ms; 24-link contact rollout 3756 -> 3640 us).
 EXTRA_FLAGS = {
     "batch.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "rollout_quad.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "rollout_seg.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
 }
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -65,31 +65,12 @@ __global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE || N >= 20) void k
   if (b < P.B) rollout_chain_pair<N, CONTACT>(P, b, (g & 1) != 0);
 }
 
-// Time-sliced pair-lane rollout: every wave of the grid is a worker.
-constexpr uint64_t kSegWaitTicks = 1000000000ull;   // 10 s of the 100 MHz wall clock
-
-template <int N, bool CONTACT>
-__global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(N >= 20) void k_rollout_pair_seg(PlanDesc P) {
-  rollout_pair_segmented<N, CONTACT>(P, P.seg_ctl, P.seg_done, P.seg_state, P.seg_S, P.seg_len, kSegWaitTicks);
-  if (threadIdx.x == 0 && __hip_atomic_load(&P.seg_ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
-    atomicOr(&P.ctrl[2], 4u);
-}
-
 // Tensor-path controls of iteration P.gen_k into P.U2 (P.roll_blocks = 0: every
 // workgroup draws), run beside a time-sliced rollout that holds one wave per
 // SIMD.  The launch asks for LDS that admits at most two of these workgroups on
 // a compute unit, so the rollout's workgroup finds its registers free on every
 // unit whichever kernel is dispatched first.
 __global__ __launch_bounds__(kCandThreads) void k_gen_tensor(PlanDesc P) { gen_tensor_tiles(P); }
-
-// New launch of the time-sliced rollout: next epoch, unit counter and error cleared.
-__global__ __launch_bounds__(64) void k_seg_init(SegCtl* ctl) {
-  if (threadIdx.x == 0) {
-    ctl->head = 0u;
-    ctl->error = 0u;
-    ctl->epoch = ctl->epoch + 1u;
-  }
-}
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {
   __shared__ TopkSmem sm;
@@ -177,27 +158,7 @@ static hipError_t launch_rollout_kernel(const PlanDesc& P, dim3 grid, size_t lds
 // P.gen_grid that draw iteration gen_k's tensor-path controls into P.U2.
 static hipError_t launch_rollout(const PlanDesc& P0, hipStream_t st, int gen_k) {
   PlanDesc P = P0;
-  if (is_pair_chain(P.dyn, P.n_links) && P.seg_ctl != nullptr && P.seg_grid > 0) {
-    k_seg_init<<<1, 64, 0, st>>>(P.seg_ctl);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (P.dyn == kChain) {
-      switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, false><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
-        MTP_CHAIN_LINKS(X)
-#undef X
-        default: break;
-      }
-      return hipErrorInvalidValue;
-    }
-    switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, true><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
-      MTP_CONTACT_LINKS(X)
-#undef X
-      default: break;
-    }
-    return hipErrorInvalidValue;
-  }
+  if (is_pair_chain(P.dyn, P.n_links) && P.seg_ctl != nullptr && P.seg_grid > 0) return launch_rollout_seg(P, st);
   P.roll_blocks = rollout_blocks(P);
   P.gen_k = gen_k;
   int blocks = P.roll_blocks;
@@ -359,44 +320,12 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
   }
 }
 
-template <typename F>
-static hipError_t seg_grid_for(F kernel, const PlanDesc& P, int* grid) {
-  int dev = 0, cus = 0, occ = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kRollThreads, 0);
-  if (e != hipSuccess) return e;
-  *grid = (occ > 0 ? occ : 1) * (cus > 0 ? cus : 1);
-  (void)P;
-  return hipSuccess;
-}
-
 hipError_t gen_configure(PlanDesc* P) {
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   P->gen_grid = cus;
-  return hipSuccess;
-}
-
-hipError_t seg_configure(PlanDesc* P) {
-  if (P->seg_ctl == nullptr) return hipSuccess;
-  int grid = 0;
-  hipError_t e = hipErrorInvalidValue;
-  const bool contact = P->dyn == kChainContact;
-  switch (P->n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { e = contact ? seg_grid_for(k_rollout_pair_seg<N, true>, *P, &grid) : seg_grid_for(k_rollout_pair_seg<N, false>, *P, &grid); } break;
-    MTP_CHAIN_LINKS(X)
-#undef X
-    default: break;
-  }
-  if (e != hipSuccess) return e;
-  const int groups = (P->B + 31) / 32;
-  P->seg_S = segment_count(groups, grid * (kRollThreads / 64));
-  P->seg_len = (P->T + P->seg_S - 1) / P->seg_S;
-  P->seg_S = (P->T + P->seg_len - 1) / P->seg_len;   // no empty trailing segment
-  P->seg_grid = grid;
   return hipSuccess;
 }
 

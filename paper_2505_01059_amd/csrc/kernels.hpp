@@ -28,6 +28,9 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
 // Quad-lane chain rollout (rollout_quad.hip); one: the launch holds one
 // workgroup per compute unit.
 hipError_t launch_rollout_quad(const PlanDesc& P, dim3 grid, size_t lds, hipStream_t st, bool one);
+// Time-sliced pair-lane rollout (rollout_seg.hip): epoch bump, then the
+// persistent launch of P.seg_grid workgroups.
+hipError_t launch_rollout_seg(const PlanDesc& P, hipStream_t st);
 // Workgroups of the (not time-sliced) rollout kernel of a plan.
 int rollout_blocks(const PlanDesc& P);
 // Grid and segment count of the time-sliced pair-lane rollout for the current

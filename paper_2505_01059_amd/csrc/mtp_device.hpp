@@ -1182,7 +1182,18 @@ struct PairConsts {
   float g0;              // base node's relative acceleration against free fall: g (lane A), 0 (lane B)
   float sgn;             // +1 (lane A), -1 (lane B)
   float yg, kc, dc, inv_vs, muf;   // contact only
+  float fm[M + 1];       // contact only: -muf * im, the friction per unit normal force of each node's mass
+  float ks;              // contact only: 2 log2(e) / v_slip, the slip-velocity scale of the tanh by exp2
   bool B;                // lane owns the tip half
+};
+
+// Torque products of one RK4 step (the controls are held over its four
+// stages), per local link i with q_i = (u_i - u_distal) / l_i and q_n the next
+// link's term (the other lane's at the middle):
+//   qa_i = -im_{i+1} q_n,  qb_i = im_i q_{i-1} (i > 0),  qc_i = (im_i + im_{i+1}) q_i.
+template <int N>
+struct PairTorque {
+  float qa[N / 2], qb[N / 2], qc[N / 2];
 };
 
 template <int N>
@@ -1199,14 +1210,20 @@ __device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N>& 
   for (int i = 0; i <= M; ++i) K.im[i] = (i == 0 && !K.B) ? 0.0f : 1.0f / m[pair_node_mass<N>(K.B, i)];
 }
 
+// Friction coefficients of the lane's nodes, after the masses and muf are set.
+template <int N>
+__device__ __forceinline__ void pair_friction(PairConsts<N>& K) {
+#pragma unroll
+  for (int i = 0; i <= N / 2; ++i) K.fm[i] = -K.muf * K.im[i];
+}
+
 
 // Local-frame accelerations of the lane's M links from the local sin/cos, the
 // angular velocities and the per-step torque terms q (q_o: the other lane's
 // link next to the middle).
 template <int N, bool CONTACT>
 __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
-                                           const float (&q)[N / 2], float q_o, const PairConsts<N>& K,
-                                           float (&acc)[N / 2]) {
+                                           const PairTorque<N>& Q, const PairConsts<N>& K, float (&acc)[N / 2]) {
   constexpr int M = N / 2;
   // the other lane's middle link in this lane's frame (its frame is reversed)
   const float so = -pswap(s[M - 1]), co = -pswap(c[M - 1]);
@@ -1233,7 +1250,9 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
       float fx = 0.0f, fy = 0.0f;
       if (pen > 0.0f) {
         const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vyy), 0.0f);
-        fx = -K.muf * fn * fast_tanh(vxx * K.inv_vs) * K.im[i];
+        // tanh(v / v_slip) = 1 - 2 / (1 + e^{2 v / v_slip})
+        const float th = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(K.ks * vxx));
+        fx = (K.fm[i] * fn) * th;
         fy = fn * K.im[i];
       }
       Fx[i] = fx;
@@ -1255,13 +1274,12 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
     float rhs = K.l[i] * w[i] * w[i];
     rhs = fmaf(s[i], Fx[i + 1] - Fx[i], rhs);
     rhs = fmaf(-c[i], Fy[i + 1] - Fy[i], rhs);
-    const float qn = (i + 1 < M) ? q[i + 1] : q_o;
-    rhs = fmaf(-K.im[i + 1] * qn, Qn, rhs);
+    rhs = fmaf(Q.qa[i], Qn, rhs);
     float Dg = K.im[i] + K.im[i + 1];
     if (i > 0) {
       const float Pp = fmaf(c[i - 1], c[i], s[i - 1] * s[i]);
       const float Qp = fmaf(s[i - 1], c[i], -c[i - 1] * s[i]);
-      rhs = fmaf(K.im[i] * q[i - 1], Qp, rhs);
+      rhs = fmaf(Q.qb[i], Qp, rhs);
       const float Lp = -K.im[i] * Pp;
       const float inv = __builtin_amdgcn_rcpf(fmaf(-Lp, cp_prev, Dg));
       cp_prev = -K.im[i + 1] * Pn * inv;
@@ -1287,14 +1305,14 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
     const float sn = (i + 1 < M) ? s[i + 1] : so, cn = (i + 1 < M) ? c[i + 1] : co;
     const float Pn = fmaf(c[i], cn, s[i] * sn);
     const float Qn = fmaf(s[i], cn, -c[i] * sn);
-    const float qn = (i + 1 < M) ? q[i + 1] : q_o;
     const float Tn = (i + 1 < M) ? dp[i + 1] : xo;
-    float a = (K.im[i] + K.im[i + 1]) * q[i];
-    a = fmaf(-K.im[i + 1], fmaf(Tn, Qn, qn * Pn), a);
+    float a = fmaf(Q.qa[i], Pn, Q.qc[i]);
+    a = fmaf(-K.im[i + 1] * Tn, Qn, a);
     if (i > 0) {
       const float Pp = fmaf(c[i - 1], c[i], s[i - 1] * s[i]);
       const float Qp = fmaf(s[i - 1], c[i], -c[i - 1] * s[i]);
-      a = fmaf(-K.im[i], fmaf(-dp[i - 1], Qp, q[i - 1] * Pp), a);
+      a = fmaf(-Q.qb[i], Pp, a);
+      a = fmaf(K.im[i] * dp[i - 1], Qp, a);
     }
     a = fmaf(c[i], Fx[i + 1] - Fx[i], fmaf(s[i], Fy[i + 1] - Fy[i], a));
     acc[i] = a * K.invl[i];
@@ -1317,8 +1335,10 @@ __device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts
   }
   if constexpr (CONTACT) {
     K.yg = tk[5 + 2 * N]; K.kc = tk[6 + 2 * N]; K.dc = tk[7 + 2 * N]; K.inv_vs = 1.0f / tk[8 + 2 * N];
+    K.ks = 2.8853900817779268f * K.inv_vs;
   } else {
     pair_load_masses<N>(tk + 5, K);
+    K.ks = 0.0f;
     K.muf = 0.0f; K.yg = 0.0f; K.kc = 0.0f; K.dc = 0.0f; K.inv_vs = 0.0f;
   }
 }
@@ -1366,9 +1386,16 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
       q[i] = (u[i] - u_tip) * K.invl[i];
     }
     const float q_o = pswap(q[M - 1]);
+    PairTorque<N> Q;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      Q.qa[i] = -K.im[i + 1] * ((i + 1 < M) ? q[i + 1] : q_o);
+      Q.qb[i] = (i > 0) ? K.im[i] * q[i - 1] : 0.0f;
+      Q.qc[i] = (K.im[i] + K.im[i + 1]) * q[i];
+    }
 
     float kk[M], oms[M], aph[M], aom[M];
-    pair_accel<N, CONTACT>(s, c, om, q, q_o, K, kk);
+    pair_accel<N, CONTACT>(s, c, om, Q, K, kk);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       aph[i] = om[i];
@@ -1385,7 +1412,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
         rev_sincos_unit(fmaf(hr, oms[i], ph[i]), &s2[i], &c2[i]);
         oms[i] = fmaf(h, kk[i], om[i]);
       }
-      pair_accel<N, CONTACT>(s2, c2, oms, q, q_o, K, kk);
+      pair_accel<N, CONTACT>(s2, c2, oms, Q, K, kk);
       const float wgt = (stage == 3) ? 1.0f : 2.0f;
 #pragma unroll
       for (int i = 0; i < M; ++i) {
@@ -1461,6 +1488,7 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
       const float* sp = P.sparams + (static_cast<size_t>(rep) * P.B + b) * (N + 1);
       pair_load_masses<N>(sp, K);
       K.muf = sp[N];
+      pair_friction<N>(K);
     }
     float ph[M], om[M], turn[M];
     pair_start<N>(P, K, ph, om, turn);
@@ -1536,6 +1564,7 @@ __device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl
       const float* sp = P.sparams + static_cast<size_t>(b) * (N + 1);
       pair_load_masses<N>(sp, K);
       K.muf = sp[N];
+      pair_friction<N>(K);
     }
     float ph[M], om[M], turn[M], cost;
     const size_t gl = static_cast<size_t>(g) * 64 + static_cast<size_t>(lane);
