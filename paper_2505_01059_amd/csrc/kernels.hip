@@ -82,23 +82,27 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(PlanDesc P) {
   if (o < P.T * P.n) update_output(P, o);
 }
 
-// Refit of iteration k, one (t, j) output per workgroup, and from it iteration
-// k_next's local samples and nominal mean at (t, j) into P.U2 (its tensor paths
-// were drawn during iteration k's rollout).  Wave 0 refits while every thread
-// draws the normals of its share of the local samples.
+// Refit of iteration k at the four steps t = 4 tq + c of joint j (one wave per
+// step), and from each refitted (t, j) iteration k_next's local samples and
+// nominal mean at (t, j) into P.U2 (its tensor paths were drawn during
+// iteration k's rollout).  The four steps of a local sample come from one
+// Philox block; every thread draws its first samples' normals while the waves
+// refit.
 __global__ __launch_bounds__(kUpdThreads) void k_update_next(PlanDesc P, int k_next) {
-  __shared__ float mom[2];
-  const int o = blockIdx.x;
+  __shared__ float mom[4][2];
+  const int tq = static_cast<int>(blockIdx.x) / P.n, j = static_cast<int>(blockIdx.x) - tq * P.n;
+  const int c = static_cast<int>(threadIdx.x) >> 6;
+  const int t = 4 * tq + c;
   const uint32_t r = P.ctrl[0];
-  float z[kLocalKeep];
-  local_normals<kUpdThreads>(P, o, k_next, r, z);
-  if (threadIdx.x < 64) {
+  float z[kLocalKeep][4];
+  local_normals<kUpdThreads>(P, tq, j, k_next, r, z);
+  if (t < P.T) {
     float mn, sn;
-    update_output(P, o, &mn, &sn);
-    if (threadIdx.x == 0) { mom[0] = mn; mom[1] = sn; }
+    update_output(P, t * P.n + j, &mn, &sn);
+    if ((threadIdx.x & 63) == 0) { mom[c][0] = mn; mom[c][1] = sn; }
   }
   __syncthreads();
-  local_store<kUpdThreads>(P, P.U2, o, k_next, r, z, mom[0], mom[1]);
+  local_store<kUpdThreads>(P, P.U2, tq, j, k_next, r, z, mom);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -313,7 +317,7 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
     }
     case 3: {
       if (k + 1 >= k1) return launch_stage(Pk, stage, k, st);
-      k_update_next<<<Pk.T * Pk.n, kUpdThreads, 0, st>>>(Pk, k + 1);
+      k_update_next<<<((Pk.T + 3) / 4) * Pk.n, kUpdThreads, 0, st>>>(Pk, k + 1);
       return hipGetLastError();
     }
     default: return launch_stage(Pk, stage, k, st);

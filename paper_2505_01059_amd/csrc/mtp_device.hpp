@@ -1243,20 +1243,28 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
     // lane B starts at the tip: the sum of lane A's links minus its own (reversed) ones
     const float y0 = K.bf * (pswap(py[M]) - py[M]);
     const float u0 = K.bf * (pswap(vx[M]) - vx[M]), v0 = K.bf * (pswap(vy[M]) - vy[M]);
+    // One branch for the wave: the contact terms of all nodes are formed when
+    // some node of some lane is below the ground (the lowest height decides, as
+    // rounding of the offset is monotone), with a select per node, so their
+    // transcendental chains interleave; otherwise every node is free.
+    float lowest = py[0];
 #pragma unroll
-    for (int i = 0; i <= M; ++i) {
-      const float yy = py[i] + y0, vyy = vy[i] + v0, vxx = vx[i] + u0;
-      const float pen = K.yg - yy;
-      float fx = 0.0f, fy = 0.0f;
-      if (pen > 0.0f) {
+    for (int i = 1; i <= M; ++i) lowest = fminf(lowest, py[i]);
+    if (__builtin_amdgcn_ballot_w64(lowest + y0 < K.yg) != 0) {
+#pragma unroll
+      for (int i = 0; i <= M; ++i) {
+        const float yy = py[i] + y0, vyy = vy[i] + v0, vxx = vx[i] + u0;
+        const float pen = K.yg - yy;
         const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vyy), 0.0f);
         // tanh(v / v_slip) = 1 - 2 / (1 + e^{2 v / v_slip})
         const float th = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(K.ks * vxx));
-        fx = (K.fm[i] * fn) * th;
-        fy = fn * K.im[i];
+        const bool in = pen > 0.0f;
+        Fx[i] = in ? (K.fm[i] * fn) * th : 0.0f;
+        Fy[i] = in ? fn * K.im[i] : 0.0f;
       }
-      Fx[i] = fx;
-      Fy[i] = fy;
+    } else {
+#pragma unroll
+      for (int i = 0; i <= M; ++i) { Fx[i] = 0.0f; Fy[i] = 0.0f; }
     }
   } else {
 #pragma unroll
@@ -2088,45 +2096,76 @@ __device__ __forceinline__ void topk_block(const PlanDesc& P, TopkSmem& sm) {
 // The normals do not depend on the refit: local_normals draws a thread's share
 // (samples tid, tid + BS, ...; the first kLocalKeep kept in registers) while
 // the refit runs, local_store writes them once the moments are known.
-constexpr int kLocalKeep = 8;
+constexpr int kLocalKeep = 4;
 
-__device__ __forceinline__ float local_normal(const PlanDesc& P, int o, int b, int k_next, uint32_t r) {
-  const int t = o / P.n, j = o - t * P.n;
-  const int Tq = (P.T + 3) >> 2, tq = t >> 2, c = t & 3;
+// Iteration k_next's local-sample normals at the four steps t = 4 tq + c
+// (c = 0..3) of joint j for candidates b = threadIdx.x + i BS, i < kLocalKeep:
+// the one Philox block of (j, tq, b) gives all four, two Box-Muller pairs,
+// exactly as the candidate tile draws them.
+__device__ __forceinline__ void local_normals4(const PlanDesc& P, int tq, int j, int b, int k_next, uint32_t r,
+                                               float (&z)[4]) {
+  const int Tq = (P.T + 3) >> 2;
   const Words4 q = philox(static_cast<uint32_t>(j * Tq + tq), static_cast<uint32_t>(b), r,
                           stream_c3(kTagEps, k_next), P.key0, P.key1);
-  float z0, z1;
-  if (c < 2) box_muller(q.w[0], q.w[1], z0, z1);
-  else box_muller(q.w[2], q.w[3], z0, z1);
-  return (c & 1) ? z1 : z0;
+  box_muller(q.w[0], q.w[1], z[0], z[1]);
+  box_muller(q.w[2], q.w[3], z[2], z[3]);
 }
 
 template <int BS>
-__device__ __forceinline__ void local_normals(const PlanDesc& P, int o, int k_next, uint32_t r,
-                                              float (&z)[kLocalKeep]) {
+__device__ __forceinline__ void local_normals(const PlanDesc& P, int tq, int j, int k_next, uint32_t r,
+                                              float (&z)[kLocalKeep][4]) {
   const int G1 = P.G - 1;
 #pragma unroll
   for (int i = 0; i < kLocalKeep; ++i) {
     const int b = static_cast<int>(threadIdx.x) + i * BS;
-    z[i] = b < G1 ? local_normal(P, o, b, k_next, r) : 0.0f;
+    if (b < G1) {
+      local_normals4(P, tq, j, b, k_next, r, z[i]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) z[i][c] = 0.0f;
+    }
   }
 }
 
+// Local samples clip(mu_t + sg_t z) and the nominal clip(mu_t) of iteration
+// k_next at the steps t = 4 tq + c < T of joint j, from the refitted moments
+// mom[c] = (mu_t, sg_t).
 template <int BS>
-__device__ __forceinline__ void local_store(const PlanDesc& P, float* U, int o, int k_next, uint32_t r,
-                                            const float (&z)[kLocalKeep], float mu_t, float sg_t) {
+__device__ __forceinline__ void local_store(const PlanDesc& P, float* U, int tq, int j, int k_next, uint32_t r,
+                                            const float (&z)[kLocalKeep][4], const float (&mom)[4][2]) {
   const auto Ug = gptr(U);
-  const size_t row = static_cast<size_t>(o) * static_cast<size_t>(P.ldU);
+  const size_t ld = static_cast<size_t>(P.ldU);
   const float lo = P.u_min, hi = P.u_max;
   const int G1 = P.G - 1;
+  const int nc = min(4, P.T - 4 * tq);
+  size_t row[4];
+  float mu_t[4], sg_t[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    row[c] = static_cast<size_t>((4 * tq + c) * P.n + j) * ld;
+    mu_t[c] = mom[c][0];
+    sg_t[c] = mom[c][1];
+  }
 #pragma unroll
   for (int i = 0; i < kLocalKeep; ++i) {
     const int b = static_cast<int>(threadIdx.x) + i * BS;
-    if (b < G1) __builtin_nontemporal_store(clampf(fmaf(sg_t, z[i], mu_t), lo, hi), &Ug[row + b]);
+    if (b < G1) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < nc) __builtin_nontemporal_store(clampf(fmaf(sg_t[c], z[i][c], mu_t[c]), lo, hi), &Ug[row[c] + b]);
+    }
   }
-  for (int b = static_cast<int>(threadIdx.x) + kLocalKeep * BS; b < G1; b += BS)
-    __builtin_nontemporal_store(clampf(fmaf(sg_t, local_normal(P, o, b, k_next, r), mu_t), lo, hi), &Ug[row + b]);
-  if (threadIdx.x == 0) __builtin_nontemporal_store(clampf(mu_t, lo, hi), &Ug[row + (P.B - 1)]);
+  for (int b = static_cast<int>(threadIdx.x) + kLocalKeep * BS; b < G1; b += BS) {
+    float zz[4];
+    local_normals4(P, tq, j, b, k_next, r, zz);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nc) __builtin_nontemporal_store(clampf(fmaf(sg_t[c], zz[c], mu_t[c]), lo, hi), &Ug[row[c] + b]);
+  }
+  if (static_cast<int>(threadIdx.x) < nc) {
+    const int c = static_cast<int>(threadIdx.x);
+    __builtin_nontemporal_store(clampf(mom[c][0], lo, hi), &Ug[row[c] + (P.B - 1)]);
+  }
 }
 
 // ------------------------------------------------------------------ cost entropy
