@@ -1245,8 +1245,11 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
     const float u0 = K.bf * (pswap(vx[M]) - vx[M]), v0 = K.bf * (pswap(vy[M]) - vy[M]);
     // One branch for the wave: the contact terms of all nodes are formed when
     // some node of some lane is below the ground (the lowest height decides, as
-    // rounding of the offset is monotone), with a select per node, so their
-    // transcendental chains interleave; otherwise every node is free.
+    // rounding of the offset is monotone), otherwise every node is free.  In
+    // the branch the normal force is selected (zero above the ground) and the
+    // friction factor is formed for every node, so the thirteen transcendental
+    // chains interleave; a select on the friction term itself would be turned
+    // back into a branch per node by the compiler.
     float lowest = py[0];
 #pragma unroll
     for (int i = 1; i <= M; ++i) lowest = fminf(lowest, py[i]);
@@ -1255,12 +1258,11 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
       for (int i = 0; i <= M; ++i) {
         const float yy = py[i] + y0, vyy = vy[i] + v0, vxx = vx[i] + u0;
         const float pen = K.yg - yy;
-        const float fn = fmaxf(fmaf(K.kc, pen, -K.dc * vyy), 0.0f);
+        const float fn = pen > 0.0f ? fmaxf(fmaf(K.kc, pen, -K.dc * vyy), 0.0f) : 0.0f;
         // tanh(v / v_slip) = 1 - 2 / (1 + e^{2 v / v_slip})
         const float th = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(K.ks * vxx));
-        const bool in = pen > 0.0f;
-        Fx[i] = in ? (K.fm[i] * fn) * th : 0.0f;
-        Fy[i] = in ? fn * K.im[i] : 0.0f;
+        Fx[i] = (K.fm[i] * fn) * th;
+        Fy[i] = fn * K.im[i];
       }
     } else {
 #pragma unroll
