@@ -1182,7 +1182,6 @@ struct PairConsts {
   float g0;              // base node's relative acceleration against free fall: g (lane A), 0 (lane B)
   float sgn;             // +1 (lane A), -1 (lane B)
   float yg, kc, dc, inv_vs, muf;   // contact only
-  float fm[M + 1];       // contact only: -muf * im, the friction per unit normal force of each node's mass
   float ks;              // contact only: 2 log2(e) / v_slip, the slip-velocity scale of the tanh by exp2
   bool B;                // lane owns the tip half
 };
@@ -1210,12 +1209,6 @@ __device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N>& 
   for (int i = 0; i <= M; ++i) K.im[i] = (i == 0 && !K.B) ? 0.0f : 1.0f / m[pair_node_mass<N>(K.B, i)];
 }
 
-// Friction coefficients of the lane's nodes, after the masses and muf are set.
-template <int N>
-__device__ __forceinline__ void pair_friction(PairConsts<N>& K) {
-#pragma unroll
-  for (int i = 0; i <= N / 2; ++i) K.fm[i] = -K.muf * K.im[i];
-}
 
 
 // Local-frame accelerations of the lane's M links from the local sin/cos, the
@@ -1254,15 +1247,18 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
 #pragma unroll
     for (int i = 1; i <= M; ++i) lowest = fminf(lowest, py[i]);
     if (__builtin_amdgcn_ballot_w64(lowest + y0 < K.yg) != 0) {
+      // the tip offsets of lane B folded into per-evaluation constants:
+      // penetration (yg - y0) - y_i, damping dc (v_i + v0), slip ks (u_i + u0)
+      const float ygl = K.yg - y0, dv0 = -K.dc * v0, ku0 = K.ks * u0;
+      // friction -muf tanh(v / v_slip) = -muf (1 - 2 r) = 2 muf r - muf, r = 1 / (1 + e^{2 v / v_slip})
+      const float mu2 = 2.0f * K.muf, nmu = -K.muf;
 #pragma unroll
       for (int i = 0; i <= M; ++i) {
-        const float yy = py[i] + y0, vyy = vy[i] + v0, vxx = vx[i] + u0;
-        const float pen = K.yg - yy;
-        const float fn = pen > 0.0f ? fmaxf(fmaf(K.kc, pen, -K.dc * vyy), 0.0f) : 0.0f;
-        // tanh(v / v_slip) = 1 - 2 / (1 + e^{2 v / v_slip})
-        const float th = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(K.ks * vxx));
-        Fx[i] = (K.fm[i] * fn) * th;
+        const float pen = ygl - py[i];
+        const float fn = pen > 0.0f ? fmaxf(fmaf(K.kc, pen, fmaf(-K.dc, vy[i], dv0)), 0.0f) : 0.0f;
+        const float fr = fmaf(mu2, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(fmaf(K.ks, vx[i], ku0))), nmu);
         Fy[i] = fn * K.im[i];
+        Fx[i] = Fy[i] * fr;
       }
     } else {
 #pragma unroll
@@ -1498,7 +1494,6 @@ __device__ __forceinline__ void rollout_chain_pair(const PlanDesc& P, int b, boo
       const float* sp = P.sparams + (static_cast<size_t>(rep) * P.B + b) * (N + 1);
       pair_load_masses<N>(sp, K);
       K.muf = sp[N];
-      pair_friction<N>(K);
     }
     float ph[M], om[M], turn[M];
     pair_start<N>(P, K, ph, om, turn);
@@ -1574,7 +1569,6 @@ __device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl
       const float* sp = P.sparams + static_cast<size_t>(b) * (N + 1);
       pair_load_masses<N>(sp, K);
       K.muf = sp[N];
-      pair_friction<N>(K);
     }
     float ph[M], om[M], turn[M], cost;
     const size_t gl = static_cast<size_t>(g) * 64 + static_cast<size_t>(lane);
