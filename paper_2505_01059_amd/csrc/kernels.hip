@@ -67,9 +67,10 @@ __global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE || N >= 20) void k
 
 // Tensor-path controls of iteration P.gen_k into P.U2 (P.roll_blocks = 0: every
 // workgroup draws), run beside a time-sliced rollout that holds one wave per
-// SIMD.  The launch asks for LDS that admits at most two of these workgroups on
-// a compute unit, so the rollout's workgroup finds its registers free on every
-// unit whichever kernel is dispatched first.
+// SIMD.  The launch asks for LDS that admits one of these workgroups per
+// compute unit (one wave of 72 VGPRs per SIMD), so the rollout's workgroup
+// (up to 440 registers per lane) finds its registers free on every unit
+// whichever kernel is dispatched first.
 __global__ __launch_bounds__(kCandThreads) void k_gen_tensor(PlanDesc P) { gen_tensor_tiles(P); }
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {
@@ -145,8 +146,6 @@ int rollout_blocks(const PlanDesc& P) {
 // its SIMDs (the dispatcher was seen to pair workgroups on a unit now and
 // then, which doubles those waves' time).
 constexpr size_t kOnePerUnitLds = 96 * 1024;
-// LDS that leaves room for at most two workgroups per compute unit.
-constexpr size_t kTwoPerUnitLds = 64 * 1024;
 
 // LDS of a rollout launch that also draws tensor-path controls: the candidate
 // tile's arrays over the whole horizon, at least kOnePerUnitLds.
@@ -294,21 +293,21 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
       G.roll_blocks = 0;
       G.gen_k = k + 1;
       const size_t tile = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, P.T < kTChunk ? P.T : kTChunk));
-      const size_t lds = std::max(tile, kTwoPerUnitLds);
+      const size_t lds = std::max(tile, kOnePerUnitLds);
       const hipStream_t gs = side != nullptr ? side->st : st;
       hipError_t e = hipSuccess;
       if (side != nullptr) {
         e = hipEventRecord(side->fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(side->st, side->fork, 0);
         if (e != hipSuccess) return e;
-        k_gen_tensor<<<2 * G.gen_grid, kCandThreads, lds, gs>>>(G);
+        k_gen_tensor<<<G.gen_grid, kCandThreads, lds, gs>>>(G);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
       e = launch_rollout(Pk, st, -1);
       if (e != hipSuccess) return e;
       if (side == nullptr) {
-        k_gen_tensor<<<2 * G.gen_grid, kCandThreads, lds, gs>>>(G);
+        k_gen_tensor<<<G.gen_grid, kCandThreads, lds, gs>>>(G);
         return hipGetLastError();
       }
       e = hipEventRecord(side->join, side->st);

@@ -1214,61 +1214,16 @@ __device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N>& 
 // Local-frame accelerations of the lane's M links from the local sin/cos, the
 // angular velocities and the per-step torque terms q (q_o: the other lane's
 // link next to the middle).
-template <int N, bool CONTACT>
-__device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
-                                           const PairTorque<N>& Q, const PairConsts<N>& K, float (&acc)[N / 2]) {
+// Tension solve and link accelerations of pair_accel from the node relative
+// accelerations F[0..M] (contact and, at the base node, gravity).  FORCES =
+// false: no node touches the ground, so F is zero but for the base node's g0,
+// and the terms that would multiply zeros are left out (same values).
+template <int N, bool FORCES>
+__device__ __forceinline__ void pair_solve(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
+                                           const PairTorque<N>& Q, const PairConsts<N>& K, float so, float co,
+                                           const float (&Fx)[N / 2 + 1], const float (&Fy)[N / 2 + 1],
+                                           float (&acc)[N / 2]) {
   constexpr int M = N / 2;
-  // the other lane's middle link in this lane's frame (its frame is reversed)
-  const float so = -pswap(s[M - 1]), co = -pswap(c[M - 1]);
-  // node relative accelerations F[0..M]
-  float Fx[M + 1], Fy[M + 1];
-  if constexpr (CONTACT) {
-    // node heights and velocities: y_{i+1} = y_i - l_i c_i, v_{i+1} = v_i + l_i w_i (c_i, s_i)
-    float py[M + 1], vx[M + 1], vy[M + 1];
-    py[0] = 0.0f; vx[0] = 0.0f; vy[0] = 0.0f;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const float lw = K.l[i] * w[i];
-      py[i + 1] = fmaf(-K.l[i], c[i], py[i]);
-      vx[i + 1] = fmaf(lw, c[i], vx[i]);
-      vy[i + 1] = fmaf(lw, s[i], vy[i]);
-    }
-    // lane B starts at the tip: the sum of lane A's links minus its own (reversed) ones
-    const float y0 = K.bf * (pswap(py[M]) - py[M]);
-    const float u0 = K.bf * (pswap(vx[M]) - vx[M]), v0 = K.bf * (pswap(vy[M]) - vy[M]);
-    // One branch for the wave: the contact terms of all nodes are formed when
-    // some node of some lane is below the ground (the lowest height decides, as
-    // rounding of the offset is monotone), otherwise every node is free.  In
-    // the branch the normal force is selected (zero above the ground) and the
-    // friction factor is formed for every node, so the thirteen transcendental
-    // chains interleave; a select on the friction term itself would be turned
-    // back into a branch per node by the compiler.
-    float lowest = py[0];
-#pragma unroll
-    for (int i = 1; i <= M; ++i) lowest = fminf(lowest, py[i]);
-    if (__builtin_amdgcn_ballot_w64(lowest + y0 < K.yg) != 0) {
-      // the tip offsets of lane B folded into per-evaluation constants:
-      // penetration (yg - y0) - y_i, damping dc (v_i + v0), slip ks (u_i + u0)
-      const float ygl = K.yg - y0, dv0 = -K.dc * v0, ku0 = K.ks * u0;
-      // friction -muf tanh(v / v_slip) = -muf (1 - 2 r) = 2 muf r - muf, r = 1 / (1 + e^{2 v / v_slip})
-      const float mu2 = 2.0f * K.muf, nmu = -K.muf;
-#pragma unroll
-      for (int i = 0; i <= M; ++i) {
-        const float pen = ygl - py[i];
-        const float fn = pen > 0.0f ? fmaxf(fmaf(K.kc, pen, fmaf(-K.dc, vy[i], dv0)), 0.0f) : 0.0f;
-        const float fr = fmaf(mu2, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(fmaf(K.ks, vx[i], ku0))), nmu);
-        Fy[i] = fn * K.im[i];
-        Fx[i] = Fy[i] * fr;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i <= M; ++i) { Fx[i] = 0.0f; Fy[i] = 0.0f; }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i <= M; ++i) { Fx[i] = 0.0f; Fy[i] = 0.0f; }
-  }
-  Fy[0] += K.g0;
   // forward elimination from the lane's outer end towards the middle
   float cp[M], dp[M];
   float cp_prev = 0.0f, dp_prev = 0.0f;
@@ -1278,8 +1233,12 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
     const float Pn = fmaf(c[i], cn, s[i] * sn);            // cos(phi_i - phi_{i+1})
     const float Qn = fmaf(s[i], cn, -c[i] * sn);           // sin(phi_i - phi_{i+1})
     float rhs = K.l[i] * w[i] * w[i];
-    rhs = fmaf(s[i], Fx[i + 1] - Fx[i], rhs);
-    rhs = fmaf(-c[i], Fy[i + 1] - Fy[i], rhs);
+    if constexpr (FORCES) {
+      rhs = fmaf(s[i], Fx[i + 1] - Fx[i], rhs);
+      rhs = fmaf(-c[i], Fy[i + 1] - Fy[i], rhs);
+    } else if (i == 0) {
+      rhs = fmaf(-c[0], -K.g0, rhs);
+    }
     rhs = fmaf(Q.qa[i], Qn, rhs);
     float Dg = K.im[i] + K.im[i + 1];
     if (i > 0) {
@@ -1320,9 +1279,72 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
       a = fmaf(-Q.qb[i], Pp, a);
       a = fmaf(K.im[i] * dp[i - 1], Qp, a);
     }
-    a = fmaf(c[i], Fx[i + 1] - Fx[i], fmaf(s[i], Fy[i + 1] - Fy[i], a));
+    if constexpr (FORCES) {
+      a = fmaf(c[i], Fx[i + 1] - Fx[i], fmaf(s[i], Fy[i + 1] - Fy[i], a));
+    } else if (i == 0) {
+      a = fmaf(s[0], -K.g0, a);
+    }
     acc[i] = a * K.invl[i];
   }
+}
+
+
+template <int N, bool CONTACT>
+__device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
+                                           const PairTorque<N>& Q, const PairConsts<N>& K, float (&acc)[N / 2]) {
+  constexpr int M = N / 2;
+  // the other lane's middle link in this lane's frame (its frame is reversed)
+  const float so = -pswap(s[M - 1]), co = -pswap(c[M - 1]);
+  // node relative accelerations F[0..M]
+  float Fx[M + 1], Fy[M + 1];
+  if constexpr (CONTACT) {
+    // node heights y_{i+1} = y_i - l_i c_i; lane B starts at the tip: the sum
+    // of lane A's links minus its own (reversed) ones
+    float py[M + 1];
+    py[0] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < M; ++i) py[i + 1] = fmaf(-K.l[i], c[i], py[i]);
+    const float y0 = K.bf * (pswap(py[M]) - py[M]);
+    // One branch for the wave: the contact terms of all nodes are formed when
+    // some node of some lane is below the ground (the lowest height decides, as
+    // rounding of the offset is monotone), otherwise every node is free.  In
+    // the branch the normal force is selected (zero above the ground) and the
+    // friction factor is formed for every node, so the thirteen transcendental
+    // chains interleave; a select on the friction term itself would be turned
+    // back into a branch per node by the compiler.
+    float lowest = py[0];
+#pragma unroll
+    for (int i = 1; i <= M; ++i) lowest = fminf(lowest, py[i]);
+    if (__builtin_amdgcn_ballot_w64(lowest + y0 < K.yg) != 0) {
+      // node velocities v_{i+1} = v_i + l_i w_i (c_i, s_i), lane B's from the tip
+      float vx[M + 1], vy[M + 1];
+      vx[0] = 0.0f; vy[0] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const float lw = K.l[i] * w[i];
+        vx[i + 1] = fmaf(lw, c[i], vx[i]);
+        vy[i + 1] = fmaf(lw, s[i], vy[i]);
+      }
+      const float u0 = K.bf * (pswap(vx[M]) - vx[M]), v0 = K.bf * (pswap(vy[M]) - vy[M]);
+      // the tip offsets of lane B folded into per-evaluation constants:
+      // penetration (yg - y0) - y_i, damping dc (v_i + v0), slip ks (u_i + u0)
+      const float ygl = K.yg - y0, dv0 = -K.dc * v0, ku0 = K.ks * u0;
+      // friction -muf tanh(v / v_slip) = -muf (1 - 2 r) = 2 muf r - muf, r = 1 / (1 + e^{2 v / v_slip})
+      const float mu2 = 2.0f * K.muf, nmu = -K.muf;
+#pragma unroll
+      for (int i = 0; i <= M; ++i) {
+        const float pen = ygl - py[i];
+        const float fn = pen > 0.0f ? fmaxf(fmaf(K.kc, pen, fmaf(-K.dc, vy[i], dv0)), 0.0f) : 0.0f;
+        const float fr = fmaf(mu2, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(fmaf(K.ks, vx[i], ku0))), nmu);
+        Fy[i] = fn * K.im[i];
+        Fx[i] = Fy[i] * fr;
+      }
+      Fy[0] += K.g0;
+      pair_solve<N, true>(s, c, w, Q, K, so, co, Fx, Fy, acc);
+      return;
+    }
+  }
+  pair_solve<N, false>(s, c, w, Q, K, so, co, Fx, Fy, acc);
 }
 
 template <int N, bool CONTACT>
