@@ -69,8 +69,8 @@ __global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE || N >= 20) void k
 // workgroup draws), run beside a time-sliced rollout that holds one wave per
 // SIMD.  The launch asks for LDS that admits one of these workgroups per
 // compute unit (one wave of 72 VGPRs per SIMD), so the rollout's workgroup
-// (up to 440 registers per lane) finds its registers free on every unit
-// whichever kernel is dispatched first.
+// (up to 440 registers per lane; 408 for 24 links with contact) finds its
+// registers free on every unit whichever kernel is dispatched first.
 __global__ __launch_bounds__(kCandThreads) void k_gen_tensor(PlanDesc P) { gen_tensor_tiles(P); }
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {

@@ -107,6 +107,10 @@ __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
 // memory (the persistent kernel's descriptor table) and would otherwise be a
 // flat access; flat accesses also count against the LDS wait counter, so every
 // LDS wait that follows one waits for it to reach memory as well.
+// Fourth word of a raw (untyped, unswizzled) buffer descriptor on gfx9-family
+// chips such as gfx950.
+constexpr int kBufferWord3 = 0x00020000;
+
 template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
   return (__attribute__((address_space(1))) T*)(p);
@@ -1391,19 +1395,34 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
   float s[M], c[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) rev_sincos_unit(ph[i], &s[i], &c[i]);
-  const size_t ld = static_cast<size_t>(P.ldU);
-  const float* ub = P.U + b;
-  float u[M];
+  // Controls through a buffer descriptor based at step t's block of U rows:
+  // the lane's byte offset (its link's row and its candidate) is the same at
+  // every step and below 2^31 for every valid plan (N <= 24, ldU <= 2^24 + 64),
+  // so a load takes no address arithmetic.
+  const uint32_t ldu = static_cast<uint32_t>(P.ldU);
+  uint32_t uoff[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) u[i] = ub[(t0 * N + pair_link<N>(B, i)) * ld];
+  for (int i = 0; i < M; ++i) uoff[i] = (static_cast<uint32_t>(pair_link<N>(B, i)) * ldu + static_cast<uint32_t>(b)) * 4u;
+  const int step_bytes = static_cast<int>(static_cast<uint32_t>(N) * ldu * 4u);
+  auto step_rows = [&](int t) {
+    return __builtin_amdgcn_make_buffer_rsrc(P.U + static_cast<size_t>(t) * N * ldu, static_cast<short>(0), step_bytes,
+                                             kBufferWord3);
+  };
+  float u[M];
+  {
+    const auto rs = step_rows(t0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) u[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, uoff[i], 0, 0));
+  }
   for (int t = t0; t < t1; ++t) {
     // next step's controls, loaded a whole step ahead; the last step re-reads
     // its own row (no select on the loaded values, which would make the wave
     // wait for the loads at once)
     float un[M];
     const int tn = (t + 1 < t1) ? t + 1 : t;
+    const auto rs = step_rows(tn);
 #pragma unroll
-    for (int i = 0; i < M; ++i) un[i] = ub[(tn * N + pair_link<N>(B, i)) * ld];
+    for (int i = 0; i < M; ++i) un[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, uoff[i], 0, 0));
     // torque terms (u_k - u_{k+1}) / l_k: the distal neighbour is local i+1 in lane A
     // (the other lane's link at the middle) and local i-1 in lane B (none at the tip)
     float q[M];
