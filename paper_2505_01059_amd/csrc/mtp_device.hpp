@@ -70,6 +70,7 @@ struct PlanDesc {
   // write the tensor-path controls of iteration gen_k into U2
   float* U2;             // second [T][n][ldU] buffer, or null
   int32_t roll_blocks, gen_k;
+  int32_t eq_len;        // chains: every link has the same length (bit for bit)
   int32_t gen_grid;      // compute units: workgroups of such a launch (one per unit)
 };
 
@@ -1176,10 +1177,14 @@ __device__ __forceinline__ float pswap(float v) { return qperm<kQXor1>(v); }
 // the node positions (the tip, for lane B) and the sign of the end-effector sum
 // depend on the lane, once per step.
 
-template <int N>
+// EQ: every link of the chain has the same length, held once (the per-link
+// arrays would sit in AGPRs of the long-chain kernels and cost a move per use).
+template <int N, bool EQ = false>
 struct PairConsts {
   static constexpr int M = N / 2;
-  float l[M], invl[M];   // own links in local order
+  float l[EQ ? 1 : M], invl[EQ ? 1 : M];   // own links in local order
+  __device__ __forceinline__ float len(int i) const { return l[EQ ? 0 : i]; }
+  __device__ __forceinline__ float ilen(int i) const { return invl[EQ ? 0 : i]; }
   float im[M + 1];       // inverse masses of local nodes 0..M (node M is the middle one)
   float half;            // revolution offset of the local frame: 0 (lane A) or 1/2 (lane B)
   float bf;              // 1 for lane B, 0 for lane A
@@ -1206,8 +1211,8 @@ __device__ __forceinline__ int pair_link(bool B, int i) { return B ? N - 1 - i :
 template <int N>
 __device__ __forceinline__ int pair_node_mass(bool B, int i) { return B ? (i < N / 2 ? N - 1 - i : N / 2 - 1) : i - 1; }
 
-template <int N>
-__device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N>& K) {
+template <int N, bool EQ>
+__device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N, EQ>& K) {
   constexpr int M = N / 2;
 #pragma unroll
   for (int i = 0; i <= M; ++i) K.im[i] = (i == 0 && !K.B) ? 0.0f : 1.0f / m[pair_node_mass<N>(K.B, i)];
@@ -1222,9 +1227,9 @@ __device__ __forceinline__ void pair_load_masses(const float* m, PairConsts<N>& 
 // accelerations F[0..M] (contact and, at the base node, gravity).  FORCES =
 // false: no node touches the ground, so F is zero but for the base node's g0,
 // and the terms that would multiply zeros are left out (same values).
-template <int N, bool FORCES>
+template <int N, bool FORCES, bool EQ>
 __device__ __forceinline__ void pair_solve(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
-                                           const PairTorque<N>& Q, const PairConsts<N>& K, float so, float co,
+                                           const PairTorque<N>& Q, const PairConsts<N, EQ>& K, float so, float co,
                                            const float (&Fx)[N / 2 + 1], const float (&Fy)[N / 2 + 1],
                                            float (&acc)[N / 2]) {
   constexpr int M = N / 2;
@@ -1236,7 +1241,7 @@ __device__ __forceinline__ void pair_solve(const float (&s)[N / 2], const float 
     const float sn = (i + 1 < M) ? s[i + 1] : so, cn = (i + 1 < M) ? c[i + 1] : co;
     const float Pn = fmaf(c[i], cn, s[i] * sn);            // cos(phi_i - phi_{i+1})
     const float Qn = fmaf(s[i], cn, -c[i] * sn);           // sin(phi_i - phi_{i+1})
-    float rhs = K.l[i] * w[i] * w[i];
+    float rhs = K.len(i) * w[i] * w[i];
     if constexpr (FORCES) {
       rhs = fmaf(s[i], Fx[i + 1] - Fx[i], rhs);
       rhs = fmaf(-c[i], Fy[i + 1] - Fy[i], rhs);
@@ -1288,14 +1293,14 @@ __device__ __forceinline__ void pair_solve(const float (&s)[N / 2], const float 
     } else if (i == 0) {
       a = fmaf(s[0], -K.g0, a);
     }
-    acc[i] = a * K.invl[i];
+    acc[i] = a * K.ilen(i);
   }
 }
 
 
-template <int N, bool CONTACT>
+template <int N, bool CONTACT, bool EQ>
 __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float (&c)[N / 2], const float (&w)[N / 2],
-                                           const PairTorque<N>& Q, const PairConsts<N>& K, float (&acc)[N / 2]) {
+                                           const PairTorque<N>& Q, const PairConsts<N, EQ>& K, float (&acc)[N / 2]) {
   constexpr int M = N / 2;
   // the other lane's middle link in this lane's frame (its frame is reversed)
   const float so = -pswap(s[M - 1]), co = -pswap(c[M - 1]);
@@ -1307,7 +1312,7 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
     float py[M + 1];
     py[0] = 0.0f;
 #pragma unroll
-    for (int i = 0; i < M; ++i) py[i + 1] = fmaf(-K.l[i], c[i], py[i]);
+    for (int i = 0; i < M; ++i) py[i + 1] = fmaf(-K.len(i), c[i], py[i]);
     const float y0 = K.bf * (pswap(py[M]) - py[M]);
     // One branch for the wave: the contact terms of all nodes are formed when
     // some node of some lane is below the ground (the lowest height decides, as
@@ -1325,7 +1330,7 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
       vx[0] = 0.0f; vy[0] = 0.0f;
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        const float lw = K.l[i] * w[i];
+        const float lw = K.len(i) * w[i];
         vx[i + 1] = fmaf(lw, c[i], vx[i]);
         vy[i + 1] = fmaf(lw, s[i], vy[i]);
       }
@@ -1351,8 +1356,8 @@ __device__ __forceinline__ void pair_accel(const float (&s)[N / 2], const float 
   pair_solve<N, false>(s, c, w, Q, K, so, co, Fx, Fy, acc);
 }
 
-template <int N, bool CONTACT>
-__device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts<N>& K) {
+template <int N, bool CONTACT, bool EQ>
+__device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts<N, EQ>& K) {
   constexpr int M = N / 2;
   const float* tk = P.task;
   K.B = B;
@@ -1361,7 +1366,7 @@ __device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts
   K.g0 = B ? 0.0f : tk[0];
   K.sgn = B ? -1.0f : 1.0f;
 #pragma unroll
-  for (int i = 0; i < M; ++i) {
+  for (int i = 0; i < (EQ ? 1 : M); ++i) {
     K.l[i] = tk[5 + N + pair_link<N>(B, i)];
     K.invl[i] = 1.0f / K.l[i];
   }
@@ -1382,8 +1387,8 @@ __device__ __forceinline__ void pair_setup(const PlanDesc& P, bool B, PairConsts
 // v_sin / v_cos as it is; rates stay in rad/s, and the stage offsets h / 2pi
 // are uniform.  `turn` holds the whole turns taken off, kept up to date only
 // for recorded candidates (the state output gives physical radians).
-template <int N, bool CONTACT>
-__device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N>& K, int b, float (&ph)[N / 2],
+template <int N, bool CONTACT, bool EQ>
+__device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N, EQ>& K, int b, float (&ph)[N / 2],
                                            float (&om)[N / 2], float (&turn)[N / 2], float& cost, int t0, int t1,
                                            bool record, int rep = 0) {
   constexpr int M = N / 2;
@@ -1430,7 +1435,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       const float u_tip = B ? (i > 0 ? u[i - 1] : 0.0f) : (i + 1 < M ? u[i + 1] : u_other);
-      q[i] = (u[i] - u_tip) * K.invl[i];
+      q[i] = (u[i] - u_tip) * K.ilen(i);
     }
     const float q_o = pswap(q[M - 1]);
     PairTorque<N> Q;
@@ -1475,8 +1480,8 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
       ph[i] = __builtin_amdgcn_fractf(pu[i]);
       om[i] = fmaf(dt6, aom[i], om[i]);
       rev_sincos_unit(ph[i], &s[i], &c[i]);
-      ex = fmaf(K.l[i], s[i], ex);
-      ey = fmaf(-K.l[i], c[i], ey);
+      ex = fmaf(K.len(i), s[i], ex);
+      ey = fmaf(-K.len(i), c[i], ey);
       uu = fmaf(u[i], u[i], uu);
     }
     // end effector: the lanes' link sums, lane B's taken back to the physical frame
@@ -1505,8 +1510,8 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
 
 // Start state of the lane's links: angles in revolutions of the local frame,
 // reduced to [0, 1), with the whole turns taken off; rates in rad/s.
-template <int N>
-__device__ __forceinline__ void pair_start(const PlanDesc& P, const PairConsts<N>& K, float (&ph)[N / 2],
+template <int N, bool EQ>
+__device__ __forceinline__ void pair_start(const PlanDesc& P, const PairConsts<N, EQ>& K, float (&ph)[N / 2],
                                            float (&om)[N / 2], float (&turn)[N / 2]) {
 #pragma unroll
   for (int i = 0; i < N / 2; ++i) {
@@ -1567,7 +1572,7 @@ __device__ __forceinline__ uint32_t seg_tag(uint32_t epoch, int done) { return (
 // One wave: lanes 2c, 2c+1 hold candidate g*32 + c.  `state` holds 3M + 1
 // floats per lane per group, laid out [k][group][lane]: angles, rates, cost so
 // far, and the whole turns of recorded candidates.
-template <int N, bool CONTACT>
+template <int N, bool CONTACT, bool EQ = false>
 __device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl* ctl, uint32_t* done, float* state,
                                                        int S, int seg_len, uint64_t wait_ticks) {
   constexpr int M = N / 2;
@@ -1576,7 +1581,7 @@ __device__ __forceinline__ void rollout_pair_segmented(const PlanDesc& P, SegCtl
   const int groups = (P.B + 31) / 32;
   const uint32_t total = static_cast<uint32_t>(groups) * static_cast<uint32_t>(S);
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  PairConsts<N> K;
+  PairConsts<N, EQ> K;
   pair_setup<N, CONTACT>(P, B, K);
   for (;;) {
     uint32_t u = 0u;

@@ -349,6 +349,14 @@ PlanDesc mtp::make_desc(const mtp_config& c, const Layout& L, uint8_t* base, uin
   P.wor = c.sample_wor;
   P.sw_rounds = c.sample_wor ? perm_rounds(c.n_layers, c.n_width) : 0;
   P.diag = c.diagnostics;
+  // task of a chain: gravity, goal weight, control weight, target (2), masses[N], lengths[N], ...
+  P.eq_len = 0;
+  if ((c.dynamics == MTP_DYN_CHAIN || c.dynamics == MTP_DYN_CHAIN_CONTACT) && c.task_params != nullptr &&
+      c.n_task_params >= 5 + 2 * c.n_links) {
+    P.eq_len = 1;
+    for (int k = 1; k < c.n_links; ++k)
+      if (std::memcmp(&c.task_params[5 + c.n_links + k], &c.task_params[5 + c.n_links], sizeof(float)) != 0) P.eq_len = 0;
+  }
   P.tc = cand_time_chunk(P.B, P.T, P.n);
   P.lam = c.temperature; P.alpha = c.smoothing; P.sigma_min = c.sigma_min; P.sigma_init = c.sigma_init;
   P.u_min = c.u_min; P.u_max = c.u_max; P.dt = c.dt;

@@ -11,9 +11,10 @@ namespace mtp {
 // Every wave of the grid is a worker.
 constexpr uint64_t kSegWaitTicks = 1000000000ull;   // 10 s of the 100 MHz wall clock
 
-template <int N, bool CONTACT>
+// EQ: every link has the same length (P.eq_len), held once instead of per link.
+template <int N, bool CONTACT, bool EQ>
 __global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(N >= 20) void k_rollout_pair_seg(PlanDesc P) {
-  rollout_pair_segmented<N, CONTACT>(P, P.seg_ctl, P.seg_done, P.seg_state, P.seg_S, P.seg_len, kSegWaitTicks);
+  rollout_pair_segmented<N, CONTACT, EQ>(P, P.seg_ctl, P.seg_done, P.seg_state, P.seg_S, P.seg_len, kSegWaitTicks);
   if (threadIdx.x == 0 && __hip_atomic_load(&P.seg_ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
     atomicOr(&P.ctrl[2], 4u);
 }
@@ -33,7 +34,14 @@ hipError_t launch_rollout_seg(const PlanDesc& P, hipStream_t st) {
   if (e != hipSuccess) return e;
   if (P.dyn == kChain) {
     switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, false><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+#define X(N)                                                                                         \
+  case N:                                                                                            \
+    if constexpr (pair_chain_links<N>()) {                                                           \
+      if (P.eq_len) k_rollout_pair_seg<N, false, true><<<P.seg_grid, kRollThreads, 0, st>>>(P);      \
+      else k_rollout_pair_seg<N, false, false><<<P.seg_grid, kRollThreads, 0, st>>>(P);              \
+      return hipGetLastError();                                                                      \
+    }                                                                                                \
+    break;
       MTP_CHAIN_LINKS(X)
 #undef X
       default: break;
@@ -41,7 +49,14 @@ hipError_t launch_rollout_seg(const PlanDesc& P, hipStream_t st) {
     return hipErrorInvalidValue;
   }
   switch (P.n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { k_rollout_pair_seg<N, true><<<P.seg_grid, kRollThreads, 0, st>>>(P); return hipGetLastError(); } break;
+#define X(N)                                                                                         \
+  case N:                                                                                            \
+    if constexpr (pair_chain_links<N>()) {                                                           \
+      if (P.eq_len) k_rollout_pair_seg<N, true, true><<<P.seg_grid, kRollThreads, 0, st>>>(P);       \
+      else k_rollout_pair_seg<N, true, false><<<P.seg_grid, kRollThreads, 0, st>>>(P);               \
+      return hipGetLastError();                                                                      \
+    }                                                                                                \
+    break;
     MTP_CONTACT_LINKS(X)
 #undef X
     default: break;
@@ -67,7 +82,17 @@ hipError_t seg_configure(PlanDesc* P) {
   hipError_t e = hipErrorInvalidValue;
   const bool contact = P->dyn == kChainContact;
   switch (P->n_links) {
-#define X(N) case N: if constexpr (pair_chain_links<N>()) { e = contact ? seg_grid_for(k_rollout_pair_seg<N, true>, *P, &grid) : seg_grid_for(k_rollout_pair_seg<N, false>, *P, &grid); } break;
+#define X(N)                                                                                              \
+  case N:                                                                                                 \
+    if constexpr (pair_chain_links<N>()) {                                                                \
+      if (P->eq_len)                                                                                      \
+        e = contact ? seg_grid_for(k_rollout_pair_seg<N, true, true>, *P, &grid)                          \
+                    : seg_grid_for(k_rollout_pair_seg<N, false, true>, *P, &grid);                        \
+      else                                                                                                \
+        e = contact ? seg_grid_for(k_rollout_pair_seg<N, true, false>, *P, &grid)                         \
+                    : seg_grid_for(k_rollout_pair_seg<N, false, false>, *P, &grid);                       \
+    }                                                                                                     \
+    break;
     MTP_CHAIN_LINKS(X)
 #undef X
     default: break;

@@ -70,7 +70,22 @@ def overlap_mix():
                        n_layers=5, n_width=16, n_elites=64, n_iters=3, seed=29),
         W.chain_contact_config(name="o_k24s", n_links=24, n_tensor=32800, n_gauss=70, horizon=24, n_layers=6,
                                n_width=12, n_elites=48, n_iters=2, seed=30, ground_y=-0.02),
+        # the same with links of different lengths (the time-sliced rollout's
+        # per-link form; the ones above have equal links, held once)
+        _uneven_links(W.chain_config(name="o_c12u", n_links=12, interp=W.BSPLINE, n_tensor=32000, n_gauss=1000,
+                                     horizon=16, n_layers=5, n_width=16, n_elites=64, n_iters=2, seed=31)),
+        _uneven_links(W.chain_contact_config(name="o_k24u", n_links=24, n_tensor=32800, n_gauss=70, horizon=24,
+                                             n_layers=6, n_width=12, n_elites=48, n_iters=2, seed=32,
+                                             ground_y=-0.02)),
     ]
+
+
+def _uneven_links(cfg):
+    """The config with link lengths drawn in [0.7, 1.3] (seeded by the config)."""
+    import dataclasses
+    rng = np.random.default_rng(cfg.seed + 1000)
+    lengths = rng.uniform(0.7, 1.3, cfg.n_links).astype(np.float32)
+    return cfg.replace(task=dataclasses.replace(cfg.task, lengths=lengths))
 
 
 def standalone(cfg, x0, replans, shift=1):

@@ -99,7 +99,28 @@ def configs():
                                      n_tensor=300, n_gauss=60, horizon=50, n_elites=20, n_iters=2),
         "linear": W.point_mass_config(name="linear", interp=W.LINEAR, n_tensor=250, n_gauss=40, n_layers=6,
                                       horizon=45, n_elites=16, n_iters=2),
+        # links of different lengths and masses: one-lane, quad-lane and pair-lane forms,
+        # the last with ground contact reached mid-horizon
+        "uneven3": _uneven(W.chain_config(name="uneven3", n_links=3, n_tensor=150, n_gauss=30, horizon=40,
+                                          n_layers=6, n_width=10, n_elites=10, n_iters=2)),
+        "uneven7": _uneven(W.chain_config(name="uneven7", n_tensor=300, n_gauss=45, horizon=50, n_elites=20,
+                                          n_iters=2)),
+        "uneven12": _uneven(W.chain_config(name="uneven12", n_links=12, interp=W.BSPLINE, n_tensor=250,
+                                           n_gauss=70, horizon=32, n_layers=9, n_width=40, n_elites=30,
+                                           n_iters=2)),
+        "uneven_contact24": _uneven(W.chain_contact_config(name="uneven_contact24", n_tensor=100, n_gauss=28,
+                                                           horizon=100, n_elites=12, n_iters=2, ground_y=-2.0)),
     }
+
+
+def _uneven(cfg):
+    """The config with link lengths in [0.7, 1.3] and nominal masses in [0.8, 1.5]
+    (seeded by the config)."""
+    import dataclasses
+    rng = np.random.default_rng(cfg.seed + 2000 + cfg.n_links)
+    lengths = rng.uniform(0.7, 1.3, cfg.n_links).astype(np.float32)
+    masses = rng.uniform(0.8, 1.5, cfg.n_links).astype(np.float32)
+    return cfg.replace(task=dataclasses.replace(cfg.task, lengths=lengths, masses=masses))
 
 
 CONFIGS = configs()
