@@ -571,30 +571,10 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* u0 = P.U + b;
   float cost = 0.0f;
-  // controls arrive in blocks of kPmBlock steps, the next block loading while
-  // the current one is integrated: one step is too short to hide a load
-  constexpr int kPmBlock = 8;
-  float cux[kPmBlock], cuy[kPmBlock];
-#pragma unroll
-  for (int i = 0; i < kPmBlock; ++i) {
-    const bool in = i < P.T;
-    cux[i] = in ? u0[(2 * i) * ld] : 0.0f;
-    cuy[i] = in ? u0[(2 * i + 1) * ld] : 0.0f;
-  }
-  for (int t0 = 0; t0 < P.T; t0 += kPmBlock) {
-    float nux[kPmBlock], nuy[kPmBlock];
-#pragma unroll
-    for (int i = 0; i < kPmBlock; ++i) {
-      const int tn = t0 + kPmBlock + i;
-      const bool in = tn < P.T;
-      nux[i] = in ? u0[(2 * tn) * ld] : 0.0f;
-      nuy[i] = in ? u0[(2 * tn + 1) * ld] : 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < kPmBlock; ++i) {
-    const int t = t0 + i;
-    if (t >= P.T) break;
-    const float ux = cux[i], uy = cuy[i];
+  // One step: semi-implicit Euler, then the cost of the new position and the
+  // control.  Recording the states is a separate instantiation, chosen once
+  // per wave, so the step loop of the other waves carries no branch.
+  auto step = [&](float ux, float uy, int t, auto rec) {
     vx = fmaf(dt, ux, vx);
     vy = fmaf(dt, uy, vy);
     px = fmaf(dt, vx, px);
@@ -618,16 +598,52 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
     }
     c = fmaf(wu, fmaf(ux, ux, uy * uy), c);
     cost += c;
-    if (b < P.n_dbg) {
-      float* X = P.X + b;
-      const size_t ldx = static_cast<size_t>(P.n_dbg);
-      X[(t * 4 + 0) * ldx] = px; X[(t * 4 + 1) * ldx] = py;
-      X[(t * 4 + 2) * ldx] = vx; X[(t * 4 + 3) * ldx] = vy;
+    if constexpr (decltype(rec)::value) {
+      if (b < P.n_dbg) {
+        float* X = P.X + b;
+        const size_t ldx = static_cast<size_t>(P.n_dbg);
+        X[(t * 4 + 0) * ldx] = px; X[(t * 4 + 1) * ldx] = py;
+        X[(t * 4 + 2) * ldx] = vx; X[(t * 4 + 3) * ldx] = vy;
+      }
     }
-    }
+  };
+  // controls arrive in blocks of kPmBlock steps, the next block loading while
+  // the current one is integrated: one step is too short to hide a load; whole
+  // blocks run without a bound test, the last partial block step by step
+  constexpr int kPmBlock = 8;
+  auto run = [&](auto rec) {
+    const int full = P.T / kPmBlock * kPmBlock;
+    float cux[kPmBlock], cuy[kPmBlock];
 #pragma unroll
-    for (int i = 0; i < kPmBlock; ++i) { cux[i] = nux[i]; cuy[i] = nuy[i]; }
-  }
+    for (int i = 0; i < kPmBlock; ++i) {
+      const int tt = i < P.T ? i : 0;
+      cux[i] = u0[(2 * tt) * ld];
+      cuy[i] = u0[(2 * tt + 1) * ld];
+    }
+    for (int t0 = 0; t0 < full; t0 += kPmBlock) {
+      float nux[kPmBlock], nuy[kPmBlock];
+#pragma unroll
+      for (int i = 0; i < kPmBlock; ++i) {
+        const int tn = t0 + kPmBlock + i < P.T ? t0 + kPmBlock + i : 0;
+        nux[i] = u0[(2 * tn) * ld];
+        nuy[i] = u0[(2 * tn + 1) * ld];
+      }
+#pragma unroll
+      for (int i = 0; i < kPmBlock; ++i) step(cux[i], cuy[i], t0 + i, rec);
+#pragma unroll
+      for (int i = 0; i < kPmBlock; ++i) { cux[i] = nux[i]; cuy[i] = nuy[i]; }
+    }
+    for (int t = full; t < P.T; ++t) {
+      const int i = t - full;
+      float ux = cux[0], uy = cuy[0];
+#pragma unroll
+      for (int q = 1; q < kPmBlock; ++q)
+        if (q == i) { ux = cux[q]; uy = cuy[q]; }
+      step(ux, uy, t, rec);
+    }
+  };
+  if (__builtin_amdgcn_ballot_w64(b < P.n_dbg) != 0) run(std::true_type{});
+  else run(std::false_type{});
   P.cost[b] = finite_or_inf(cost);
 }
 
