@@ -1097,6 +1097,9 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
   float u0 = K.v0f * *p0, u1 = K.v1f * *p1;
   float cost = 0.0f;   // goal term; the control term is summed per lane (uacc) and joined once
   float uacc = 0.0f;
+  // recording the states is a separate instantiation, chosen once per wave, so
+  // the step loop of the other waves carries no branch
+  auto run = [&](auto rec) {
   for (int t = 0; t < P.T; ++t) {
     // next step's controls (the last step re-reads its own row)
     const size_t adv = (t + 1 < P.T) ? row : 0;
@@ -1145,7 +1148,7 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     ey = quad_sum(ey);
     const float dx = ex - tx, dy = ey - ty;
     cost = fmaf(wg, fmaf(dx, dx, dy * dy), cost);
-    if (b < P.n_dbg) {
+    if (decltype(rec)::value && b < P.n_dbg) {
       float* X = P.X + b;
       const size_t ldx = static_cast<size_t>(P.n_dbg);
       turn0 += floorf(pu0);
@@ -1156,6 +1159,9 @@ __device__ __forceinline__ void rollout_chain_quad(const PlanDesc& P, int b, int
     u0 = un0;
     u1 = un1;
   }
+  };
+  if (__builtin_amdgcn_ballot_w64(b < P.n_dbg) != 0) run(std::true_type{});
+  else run(std::false_type{});
   cost = fmaf(wu, quad_sum(uacc), cost);
   if (s == 0) P.cost[b] = finite_or_inf(cost);
 }
