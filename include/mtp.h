@@ -237,7 +237,11 @@ mtp_status mtp_get_buffers(const mtp_plan* p, mtp_buffers* out);
  * plan's workspace holds a second [T][n][ldU] candidate buffer; the U buffer of
  * mtp_get_buffers still holds the candidates of the last iteration run.  The
  * results are the same bits either way (Alg. 2: the tensor paths do not depend
- * on the sampling distribution being refitted). */
+ * on the sampling distribution being refitted).  With an even iteration count
+ * such a plan also draws across replans: the last iteration of replan r draws
+ * the iteration-0 tensor paths of replan r + 1, which that replan takes when it
+ * is the next one run (mtp_replan, or mtp_replan_at with index r + 1); any
+ * other replan index, or an mtp_run_stage call in between, discards them. */
 int32_t mtp_plan_draws_ahead(const mtp_plan* p);
 /* Status of Alg. 2's last planning step: bit 0 = every elite cost was +inf (weights fell back to uniform);
  * bit 1 = an elite index out of range (never expected); bit 2 = a wait of the time-sliced rollout

@@ -11,8 +11,10 @@ __global__ __launch_bounds__(64) void k_set_ctrl(PlanDesc P, uint32_t r, int shi
   set_ctrl_block(P, r, shift, x0_src);
 }
 
-__global__ __launch_bounds__(256) void k_shift(PlanDesc P) {
-  shift_block<256>(P, static_cast<int>(P.ctrl[1]));
+// One workgroup (the shift is in place through a scratch copy and a barrier);
+// 1024 threads keep four times as many loads in flight as 256.
+__global__ __launch_bounds__(1024) void k_shift(PlanDesc P) {
+  shift_block<1024>(P, static_cast<int>(P.ctrl[1]));
 }
 
 __global__ __launch_bounds__(kCandThreads) void k_paths(PlanDesc P, int k) {
@@ -26,9 +28,22 @@ static int cand_chunk(const PlanDesc& P) { return P.tc < kTChunk ? P.tc : kTChun
 // the plan so that several workgroups fit on a compute unit
 __global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) {
   extern __shared__ float cand_lds[];
+  // tensor paths already drawn by the previous replan: only the local samples
+  // and the nominal are written, and tiles of tensor paths alone return
+  const bool ahead = P.cand_skip && P.ctrl[4] != 0u;
+  const int b0 = static_cast<int>(blockIdx.x) * kCandThreads;
+  if (ahead && b0 >= P.G - 1 && b0 + kCandThreads <= P.B - 1) return;
   const CandView v = cand_view_dyn(cand_lds, P.L, P.W, P.tc < kTChunk ? P.tc : kTChunk);
   const int t_begin = blockIdx.z * P.tc;
-  cand_tile(P, P.ctrl[0], k, blockIdx.y, blockIdx.x * kCandThreads, t_begin, min(P.T, t_begin + P.tc), v);
+  cand_tile(P, P.ctrl[0], k, blockIdx.y, b0, t_begin, min(P.T, t_begin + P.tc), v, ahead ? kCandLocal : kCandAll);
+}
+
+// Tensor paths drawn ahead are complete: record the replan they are for.
+__global__ __launch_bounds__(64) void k_ahead_mark(PlanDesc P) {
+  if (threadIdx.x == 0) {
+    P.ctrl[3] = P.ctrl[0] + 1u;
+    P.ctrl[5] = 1u;
+  }
 }
 
 __global__ __launch_bounds__(kTopkThreads) void k_entropy(PlanDesc P, int k) {
@@ -238,7 +253,7 @@ hipError_t launch_set_ctrl(const PlanDesc& P, uint32_t r, int shift, const float
 }
 
 hipError_t launch_shift(const PlanDesc& P, hipStream_t st) {
-  k_shift<<<1, 256, 0, st>>>(P);
+  k_shift<<<1, 1024, 0, st>>>(P);
   return hipGetLastError();
 }
 
@@ -284,18 +299,35 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
   if (!overlap) return launch_stage(P, stage, k, st);
   PlanDesc Pk = P;
   if ((k1 - 1 - k) & 1) { Pk.U = P.U2; Pk.U2 = P.U; }
+  // a whole replan of a plan that draws across replans: iteration 0 may take
+  // the tensor paths the previous replan drew, and the last iteration draws
+  // the next replan's into the buffer iteration 0 reads (the other one, K even)
+  const bool across = P.spec && k0 == 0 && k1 == P.K;
+  const bool last = k + 1 >= k1;
   switch (stage) {
-    case 0: return k > k0 ? hipSuccess : launch_candidates(Pk, k, st);
+    case 0:
+      if (k > k0) return hipSuccess;
+      Pk.cand_skip = across ? 1 : 0;
+      return launch_candidates(Pk, k, st);
     case 1: {
-      if (!sliced) return launch_rollout(Pk, st, k + 1 < k1 ? k + 1 : -1);
-      if (k + 1 >= k1) return launch_rollout(Pk, st, -1);
+      if (last && !across) return launch_rollout(Pk, st, -1);
+      hipError_t e = hipSuccess;
+      if (!sliced) {
+        Pk.gen_spec = last ? 1 : 0;
+        e = launch_rollout(Pk, st, last ? 0 : k + 1);
+        if (e == hipSuccess && last) {
+          k_ahead_mark<<<1, 64, 0, st>>>(P);
+          e = hipGetLastError();
+        }
+        return e;
+      }
       PlanDesc G = Pk;
       G.roll_blocks = 0;
-      G.gen_k = k + 1;
+      G.gen_k = last ? 0 : k + 1;
+      G.gen_spec = last ? 1 : 0;
       const size_t tile = sizeof(float) * static_cast<size_t>(cand_dyn_floats(P.L, P.W, P.T < kTChunk ? P.T : kTChunk));
       const size_t lds = std::max(tile, kOnePerUnitLds);
       const hipStream_t gs = side != nullptr ? side->st : st;
-      hipError_t e = hipSuccess;
       if (side != nullptr) {
         e = hipEventRecord(side->fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(side->st, side->fork, 0);
@@ -308,14 +340,19 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
       if (e != hipSuccess) return e;
       if (side == nullptr) {
         k_gen_tensor<<<G.gen_grid, kCandThreads, lds, gs>>>(G);
-        return hipGetLastError();
+        e = hipGetLastError();
+      } else {
+        e = hipEventRecord(side->join, side->st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
       }
-      e = hipEventRecord(side->join, side->st);
-      if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+      if (e == hipSuccess && last) {
+        k_ahead_mark<<<1, 64, 0, st>>>(P);
+        e = hipGetLastError();
+      }
       return e;
     }
     case 3: {
-      if (k + 1 >= k1) return launch_stage(Pk, stage, k, st);
+      if (last) return launch_stage(Pk, stage, k, st);
       k_update_next<<<((Pk.T + 3) / 4) * Pk.n, kUpdThreads, 0, st>>>(Pk, k + 1);
       return hipGetLastError();
     }

@@ -71,6 +71,14 @@ struct PlanDesc {
   float* U2;             // second [T][n][ldU] buffer, or null
   int32_t roll_blocks, gen_k;
   int32_t eq_len;        // chains: every link has the same length (bit for bit)
+  // Drawing across replans (single plans with an even number of iterations):
+  // the last iteration's generator also draws the next replan's iteration-0
+  // tensor paths; ctrl[3] holds the replan index they were drawn for and
+  // ctrl[5] is set while they are unused, ctrl[4] tells iteration 0 of the
+  // current replan whether it may take them.
+  int32_t spec;          // the plan draws across replans
+  int32_t gen_spec;      // this generator launch draws for replan ctrl[0] + 1, iteration 0, leaving Z and I
+  int32_t cand_skip;     // this candidate launch leaves the tensor paths when ctrl[4] is set
   int32_t gen_grid;      // compute units: workgroups of such a launch (one per unit)
 };
 
@@ -383,7 +391,9 @@ __device__ __forceinline__ void path_tile(const PlanDesc& P, uint32_t r, int k, 
 
 // Which candidates a tile writes: all, or only the tensor paths (they do not
 // depend on the sampling distribution, so they can be drawn an iteration ahead).
-constexpr int kCandAll = 0, kCandTensor = 1;
+// kCandTensorAhead: tensor paths only, for a later replan: Z and I of the
+// current one are left as they are.  kCandLocal: local samples and nominal only.
+constexpr int kCandAll = 0, kCandTensor = 1, kCandTensorAhead = 2, kCandLocal = 3;
 
 // Candidates [b0, b0 + kCandThreads) of joint j over steps [t_begin, t_end)
 // (t_begin a multiple of 4).  Tensor paths read their layer indices from I.
@@ -397,13 +407,14 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
   const int b = b0 + tid;
   const int G1 = P.G - 1;                       // local samples [0, G1)
   const int tens_lo = G1, tens_hi = G1 + P.P;   // tensor paths [G1, G1+P)
-  const bool tile_has_tensor = (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
+  const bool tensor_only = mode == kCandTensor || mode == kCandTensorAhead;
+  const bool tile_has_tensor = mode != kCandLocal && (b0 < tens_hi) && (b0 + kCandThreads > tens_lo);
   const float lo = P.u_min, hi = P.u_max;
   const size_t ld = static_cast<size_t>(P.ldU);
   const bool live = b < P.B;
-  const bool is_local = mode != kCandTensor && live && b < G1;
-  const bool is_tensor = live && b >= tens_lo && b < tens_hi;
-  const bool is_nominal = mode != kCandTensor && live && b >= tens_hi;
+  const bool is_local = !tensor_only && live && b < G1;
+  const bool is_tensor = mode != kCandLocal && live && b >= tens_lo && b < tens_hi;
+  const bool is_nominal = !tensor_only && live && b >= tens_hi;
 
   if (tile_has_tensor) {
     if (P.wor) {
@@ -412,7 +423,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
     } else {
       // draw the graph column of joint j here; the tile holding the first tensor
       // path stores it to Z
-      const bool z_writer = (b0 <= tens_lo) && t_begin == 0;
+      const bool z_writer = mode != kCandTensorAhead && (b0 <= tens_lo) && t_begin == 0;
       const float span = hi - lo;
       for (int e = tid; e < P.L * P.W; e += kCandThreads) {
         const int l = e / P.W, w = e - l * P.W;
@@ -431,7 +442,7 @@ __device__ __forceinline__ void cand_tile(const PlanDesc& P, uint32_t r, int k, 
       for (int l = 0; l < P.L; ++l) sm.ctrl[l * kCandThreads + tid] = sm.z[l * P.W + Ig[static_cast<size_t>(l) * P.P + pp]];
     } else {
       // Alg. 1 indices drawn here; the tiles of joint 0 and the first horizon chunk store I
-      const bool i_writer = j == 0 && t_begin == 0;
+      const bool i_writer = mode != kCandTensorAhead && j == 0 && t_begin == 0;
       for (int l4 = 0; l4 < P.L; l4 += 4) {
         const Words4 q = philox(static_cast<uint32_t>(l4 >> 2), static_cast<uint32_t>(pp), r, stream_c3(kTagI, k),
                                 P.key0, P.key1);
@@ -2354,7 +2365,13 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
 // in-place shift has no read-after-write hazard.
 __device__ __forceinline__ void set_ctrl_block(const PlanDesc& P, uint32_t r, int shift, const float* x0_src) {
   const int tid = threadIdx.x;
-  if (tid == 0) { P.ctrl[0] = r; P.ctrl[1] = static_cast<uint32_t>(shift > 0 ? shift : 0); P.ctrl[2] = 0u; }
+  if (tid == 0) {
+    // tensor paths drawn ahead by the previous replan are for this one only if
+    // it is the replan they were drawn for; either way they are used up now
+    P.ctrl[4] = (P.spec && P.ctrl[5] != 0u && P.ctrl[3] == r) ? 1u : 0u;
+    P.ctrl[5] = 0u;
+    P.ctrl[0] = r; P.ctrl[1] = static_cast<uint32_t>(shift > 0 ? shift : 0); P.ctrl[2] = 0u;
+  }
   if (x0_src != nullptr)
     for (int i = tid; i < P.d; i += blockDim.x) P.x0[i] = x0_src[i];
 }
@@ -2365,18 +2382,38 @@ __device__ __forceinline__ void shift_block(const PlanDesc& P, int shift) {
   if (shift <= 0) return;
   const int Tn = P.T * P.n;
   const int s = shift < P.T ? shift : P.T;
-  float* tmu = P.tmp;
-  float* tsg = P.tmp + Tn;
-  for (int e = tid; e < Tn; e += BS) {
+  // the value that lands at flat index e: step t + s of the warm start, or
+  // the last step's mean with the initial spread past the end
+  auto src = [&](int e, float& m, float& g) {
     const int t = e / P.n, j = e - t * P.n;
     if (t < P.T - s) {
-      tmu[e] = P.mu[e + s * P.n];
-      tsg[e] = P.sigma[e + s * P.n];
+      m = P.mu[e + s * P.n];
+      g = P.sigma[e + s * P.n];
     } else {
-      tmu[e] = P.mu[(P.T - 1) * P.n + j];
-      tsg[e] = P.sigma_init;
+      m = P.mu[(P.T - 1) * P.n + j];
+      g = P.sigma_init;
     }
+  };
+  constexpr int R = 8;
+  if (Tn <= BS * R) {
+    // every value held in registers across the barrier: all loads in flight
+    // at once and no staging copy
+    float m[R], g[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (tid + i * BS < Tn) src(tid + i * BS, m[i], g[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (tid + i * BS < Tn) {
+        P.mu[tid + i * BS] = m[i];
+        P.sigma[tid + i * BS] = g[i];
+      }
+    return;
   }
+  float* tmu = P.tmp;
+  float* tsg = P.tmp + Tn;
+  for (int e = tid; e < Tn; e += BS) src(e, tmu[e], tsg[e]);
   __syncthreads();
   for (int e = tid; e < Tn; e += BS) {
     P.mu[e] = tmu[e];

@@ -390,7 +390,7 @@ mtp_status mtp::upload_plan_tables(const mtp_config& c, const PlanDesc& P, const
   build_tables(c, &basis, &span);
   const size_t Tn = static_cast<size_t>(c.horizon) * c.ctrl_dim;
   std::vector<float> mu(Tn, 0.5f * (c.u_min + c.u_max)), sg(Tn, c.sigma_init);
-  const uint32_t ctrl[4] = {0u, 0u, 0u, 0u};
+  const uint32_t ctrl[6] = {0u, 0u, 0u, 0u, 0u, 0u};
   const size_t B = static_cast<size_t>(c.n_tensor) + c.n_gauss;
   hipError_t e = hipSuccess;
   auto cp = [&](void* dst, const void* src, size_t bytes) {
@@ -553,6 +553,9 @@ mtp_status mtp_plan_create(const mtp_config* cfg, void* d_workspace, size_t ws_b
     delete p;
     return MTP_ERR_DEVICE;
   }
+  // with an even iteration count the last iteration's generator writes the
+  // buffer that the next replan's iteration 0 reads
+  p->P.spec = (mtp_plan_draws_ahead(p) && cfg->n_iters % 2 == 0) ? 1 : 0;
   *out = p;
   return MTP_OK;
 }

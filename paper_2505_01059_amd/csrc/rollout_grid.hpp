@@ -31,10 +31,12 @@ __device__ __forceinline__ void gen_tensor_tiles(const PlanDesc& P) {
   const int last = (P.G - 1 + P.P - 1) / kCandThreads;         // tile of the last one
   const int items = (last - first + 1) * P.n;
   const int gens = static_cast<int>(gridDim.x) - P.roll_blocks;
-  const uint32_t r = P.ctrl[0];
+  // drawing for the next replan: its index and iteration 0, leaving Z and I
+  const uint32_t r = P.ctrl[0] + (P.gen_spec ? 1u : 0u);
+  const int mode = P.gen_spec ? kCandTensorAhead : kCandTensor;
   for (int it = static_cast<int>(blockIdx.x) - P.roll_blocks; it < items; it += gens) {
     const int tile = first + it / P.n, j = it - (it / P.n) * P.n;
-    cand_tile(Q, r, P.gen_k, j, tile * kCandThreads, 0, P.T, v, kCandTensor);
+    cand_tile(Q, r, P.gen_k, j, tile * kCandThreads, 0, P.T, v, mode);
   }
 }
 

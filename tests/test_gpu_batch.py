@@ -159,6 +159,47 @@ def test_overlapped_tensor_paths_equal_the_plain_sequence():
     bt.close()
 
 
+def test_draws_across_replans_follow_the_replan_index():
+    """Plans with an even iteration count draw the next replan's first tensor
+    paths during their last rollout.  A replan takes them only when its index
+    is the one they were drawn for: consecutive replans, a jump in the index, a
+    single iteration run in between and a repeat of the same index all give the
+    bits of the batched kernel, which draws every iteration's paths itself."""
+    import torch
+    import paper_2505_01059_amd as mtp
+    mix = {c.name: c for c in overlap_mix()}
+    cfgs = [mix["o_c7b"], mix["o_c12"], mix["o_k24s"]]
+    x0s = [W.initial_state(c, seed=40 + i) for i, c in enumerate(cfgs)]
+    ops = [("replan", 0), ("replan", 1), ("replan", 5), ("replan", 6), ("iter", 7), ("replan", 7),
+           ("replan", 8), ("replan", 8)]
+    n = len(cfgs)
+    bt = mtp.Batch(cfgs, device="cuda:0")
+    xp = bt.pack_x0(x0s)
+    plans = []
+    for i, c in enumerate(cfgs):
+        p = mtp.Plan(c, device="cuda:0")
+        assert p.draws_ahead() and c.n_iters % 2 == 0, c.name
+        plans.append(p)
+    for op, r in ops:
+        _log(f"[across] {op} {r}")
+        if op == "replan":
+            bt.step(list(range(n)), [0] * n, [c.n_iters for c in cfgs], [1] * n, [r] * n, xp)
+            for i, p in enumerate(plans):
+                p.replan(x0s[i], shift=1, replan_idx=r)
+        else:
+            bt.step(list(range(n)), [0] * n, [1] * n, [0] * n, [r] * n, xp)
+            for p in plans:
+                p.run_stage(mtp.STAGE_ALL, r, 0)
+        torch.cuda.synchronize()
+        for i, (c, p) in enumerate(zip(cfgs, plans)):
+            b, pb = bt.buffers(i), p.buffers()
+            assert np.array_equal(pb["mu"].cpu().numpy(), b["mu"].cpu().numpy()), (c.name, op, r)
+            assert np.array_equal(pb["sigma"].cpu().numpy(), b["sigma"].cpu().numpy()), (c.name, op, r)
+    for p in plans:
+        p.close()
+    bt.close()
+
+
 def test_batch_step_split_iterations_and_subsets():
     """Running iterations [0, 1) and then [1, K) of a replan, in launches that
     include other instances or not, gives the same bits as one replan."""

@@ -494,3 +494,53 @@ def test_cost_entropy_in_whole_replan(torch_mod):
     assert np.all(np.isfinite(ent)) and np.all(ent >= 0)
     assert abs(ent[-1] - OP.cost_entropy(s)) <= 1e-4 * max(1.0, ent[-1])
     plan.close()
+
+
+SHIFT_CONFIGS = {
+    # the single-plan shift holds every value in registers up to 8192 of them,
+    # the batched one up to 2048; the long horizon takes the staged copy in both
+    "shift_pm": W.point_mass_config(name="shift_pm", n_tensor=64, n_gauss=40, horizon=50, n_layers=4, n_width=4,
+                                    n_elites=8, n_iters=1, seed=3),
+    "shift_c12": W.chain_config(name="shift_c12", n_links=12, interp=W.BSPLINE, n_tensor=64, n_gauss=40, horizon=300,
+                                n_layers=6, n_width=8, n_elites=8, n_iters=1, seed=4),
+    "shift_long": W.chain_config(name="shift_long", n_links=3, interp=W.LINEAR, n_tensor=64, n_gauss=40,
+                                 horizon=3000, n_layers=6, n_width=8, n_elites=8, n_iters=1, seed=5),
+}
+
+
+@pytest.mark.parametrize("runner", ["plan", "batch"])
+@pytest.mark.parametrize("name", sorted(SHIFT_CONFIGS))
+def test_warm_start_shift(name, runner, torch_mod):
+    """The replan's first step moves the mean and spread s steps forward and
+    pads the tail with the last mean and the initial spread (Alg. 2's warm
+    start).  With a random mean and spread, the first iteration's nominal
+    candidate is the shifted mean bit for bit and its local samples match the
+    oracle's candidates drawn from the shifted distribution."""
+    import paper_2505_01059_amd as mtp
+    cfg = SHIFT_CONFIGS[name]
+    T, B, G1 = cfg.horizon, cfg.n_samples, cfg.n_gauss - 1
+    x0 = W.initial_state(cfg, seed=2)
+    for i, s in enumerate((1, 7, T + 3)):
+        _log(f"[shift] {name} {runner} T={T} n={cfg.ctrl_dim} shift={s}")
+        mu, sg = random_state(cfg, 20 + i)
+        r = 3 + i
+        if runner == "plan":
+            plan = make_plan(cfg)
+            plan.set_state(mu, sg, r)
+            plan.replan(x0, shift=s, replan_idx=r)
+            torch_mod.cuda.synchronize()
+            U = H.to_oracle_U(plan.buffers()["U"][:, :, :B])
+            plan.close()
+        else:
+            bt = mtp.Batch([cfg], device="cuda:0")
+            bt.set_state(0, mu, sg)
+            bt.step([0], [0], [1], [s], [r], bt.pack_x0([x0]))
+            torch_mod.cuda.synchronize()
+            U = H.to_oracle_U(bt.buffers(0)["U"][:, :, :B])
+            bt.close()
+        mu_s, sg_s = OP.shift_distribution(mu.astype(np.float64), sg.astype(np.float64), s, cfg.sigma_init)
+        nominal = np.clip(mu_s.astype(np.float32), cfg.u_min, cfg.u_max).astype(np.float64)
+        assert np.array_equal(U[B - 1], nominal), "nominal candidate is not the shifted mean"
+        _, _, U_ref = OP.candidates(cfg, mu_s, sg_s, r, 0)
+        ok = H.u_close(U[:G1], U_ref[:G1], cfg.u_max)
+        assert ok.all(), f"{(~ok).sum()} local-sample values differ, max err {np.max(np.abs(U[:G1] - U_ref[:G1]))}"
