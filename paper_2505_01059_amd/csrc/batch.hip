@@ -44,7 +44,7 @@ __device__ __forceinline__ void run_rollout_tile(const PlanDesc& P, uint32_t til
   if (P.dyn == kPointMass) {
     stage_obstacles(P, sm.pm);
     __syncthreads();
-    if (b < P.B) rollout_point_mass_any(P, b, sm.pm);
+    if (b < P.B) rollout_point_mass_any<1>(P, b, 0, sm.pm);
     return;
   }
   if (is_quad_chain(P.dyn, P.n_links)) {

@@ -554,26 +554,59 @@ __device__ __forceinline__ void stage_obstacles(const PlanDesc& P, PointMassSmem
   }
 }
 
+// Quad-permute DPP: moves values among the four lanes of a quad.
+constexpr int qperm_ctrl(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+constexpr int kQNext1 = qperm_ctrl(1, 2, 3, 3);
+constexpr int kQPrev1 = qperm_ctrl(0, 0, 1, 2);
+constexpr int kQNext2 = qperm_ctrl(2, 3, 2, 3);
+constexpr int kQPrev2 = qperm_ctrl(0, 1, 0, 1);
+constexpr int kQXor1 = qperm_ctrl(1, 0, 3, 2);
+constexpr int kQXor2 = qperm_ctrl(2, 3, 0, 1);
+
+template <int CTRL>
+__device__ __forceinline__ float qperm(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float quad_sum(float v) {
+  v += qperm<kQXor1>(v);
+  return v + qperm<kQXor2>(v);
+}
+
 // Obstacle tests: the uniform obstacle table either lives in registers (up to
 // NOBS obstacles, padded with radius^2 = -1 so the padding never hits) or, for
 // longer tables, is read from LDS.  Register tables avoid one LDS round trip per
 // obstacle and step, which dominates a rollout of a few hundred candidates.
-template <int NOBS>
-__device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, const PointMassSmem& sm) {
+//
+// The obstacle penalties of a step are summed in four groups, obstacle o in
+// group o mod 4, each in increasing o, and the groups as (g0 + g1) + (g2 + g3).
+// LANES = 1: one lane per candidate holds every group.  LANES = 4: lane q of
+// the candidate's quad holds group q (a quarter of the table) and the quad
+// adds the groups with two quad permutes in the same order, so every lane ends
+// the step with the same bits as the one-lane form; the state update, goal and
+// control terms run on all four lanes alike.  A step is issue-bound on one
+// wave per SIMD, and the quad form issues about a third of the instructions
+// per lane.
+template <int NOBS, int LANES = 1>
+__device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, int q, const PointMassSmem& sm) {
+  static_assert(LANES == 1 || LANES == 4, "one lane or a quad per candidate");
+  static_assert(NOBS % 4 == 0, "register tables hold whole groups");
   // task: goal_x, goal_y, goal_w, obstacle_penalty, ctrl_w, n_obs, (cx, cy, r)*
   const float* tk = P.task;
   const float gx = tk[0], gy = tk[1], wg = tk[2], pen = tk[3], wu = tk[4];
   const int n_obs = static_cast<int>(tk[5]);
-  float ocx[NOBS > 0 ? NOBS : 1], ocy[NOBS > 0 ? NOBS : 1], orr[NOBS > 0 ? NOBS : 1];
+  constexpr int NL = NOBS > 0 ? NOBS / LANES : 1;   // register obstacles per lane
+  float ocx[NL], ocy[NL], orr[NL];
   if constexpr (NOBS > 0) {
     // read from the LDS copy so that the table lands in vector registers (as
     // uniform scalars it would not fit the scalar register file)
 #pragma unroll
-    for (int o = 0; o < NOBS; ++o) {
+    for (int i = 0; i < NL; ++i) {
+      const int o = LANES == 1 ? i : q + 4 * i;
       const bool on = o < n_obs;
-      ocx[o] = on ? sm.obs[3 * o] : 0.0f;
-      ocy[o] = on ? sm.obs[3 * o + 1] : 0.0f;
-      orr[o] = on ? sm.obs[3 * o + 2] : -1.0f;
+      ocx[i] = on ? sm.obs[3 * o] : 0.0f;
+      ocy[i] = on ? sm.obs[3 * o + 1] : 0.0f;
+      orr[i] = on ? sm.obs[3 * o + 2] : -1.0f;
     }
   }
   const float* obs = sm.obs;
@@ -582,6 +615,8 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
   const size_t ld = static_cast<size_t>(P.ldU);
   const float* u0 = P.U + b;
   float cost = 0.0f;
+  // penalty of obstacle o (table entry i of this lane) at the new position
+  auto hit = [&](float ox, float oy, float rr) { return (fmaf(ox, ox, oy * oy) < rr) ? pen : 0.0f; };
   // One step: semi-implicit Euler, then the cost of the new position and the
   // control.  Recording the states is a separate instantiation, chosen once
   // per wave, so the step loop of the other waves carries no branch.
@@ -591,26 +626,31 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
     px = fmaf(dt, vx, px);
     py = fmaf(dt, vy, py);
     const float dx = px - gx, dy = py - gy;
-    float c = wg * fmaf(dx, dx, dy * dy);
-    if constexpr (NOBS > 0) {
-      // four partial sums: the obstacle terms form four short chains, not one long one
+    float obst;
+    if constexpr (LANES == 1) {
       float pc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if constexpr (NOBS > 0) {
 #pragma unroll
-      for (int o = 0; o < NOBS; ++o) {
-        const float ox = px - ocx[o], oy = py - ocy[o];
-        pc[o & 3] += (fmaf(ox, ox, oy * oy) < orr[o]) ? pen : 0.0f;
+        for (int o = 0; o < NOBS; ++o) pc[o & 3] += hit(px - ocx[o], py - ocy[o], orr[o]);
+      } else {
+        for (int o = 0; o < n_obs; ++o) pc[o & 3] += hit(px - obs[3 * o], py - obs[3 * o + 1], obs[3 * o + 2]);
       }
-      c += (pc[0] + pc[1]) + (pc[2] + pc[3]);
+      obst = (pc[0] + pc[1]) + (pc[2] + pc[3]);
     } else {
-      for (int o = 0; o < n_obs; ++o) {
-        const float ox = px - obs[3 * o], oy = py - obs[3 * o + 1];
-        c += (fmaf(ox, ox, oy * oy) < obs[3 * o + 2]) ? pen : 0.0f;
+      float g = 0.0f;
+      if constexpr (NOBS > 0) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) g += hit(px - ocx[i], py - ocy[i], orr[i]);
+      } else {
+        for (int o = q; o < n_obs; o += 4) g += hit(px - obs[3 * o], py - obs[3 * o + 1], obs[3 * o + 2]);
       }
+      obst = quad_sum(g);
     }
+    float c = fmaf(wg, fmaf(dx, dx, dy * dy), obst);
     c = fmaf(wu, fmaf(ux, ux, uy * uy), c);
     cost += c;
     if constexpr (decltype(rec)::value) {
-      if (b < P.n_dbg) {
+      if (b < P.n_dbg && q == 0) {
         float* X = P.X + b;
         const size_t ldx = static_cast<size_t>(P.n_dbg);
         X[(t * 4 + 0) * ldx] = px; X[(t * 4 + 1) * ldx] = py;
@@ -648,14 +688,14 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, con
       const int i = t - full;
       float ux = cux[0], uy = cuy[0];
 #pragma unroll
-      for (int q = 1; q < kPmBlock; ++q)
-        if (q == i) { ux = cux[q]; uy = cuy[q]; }
+      for (int k = 1; k < kPmBlock; ++k)
+        if (k == i) { ux = cux[k]; uy = cuy[k]; }
       step(ux, uy, t, rec);
     }
   };
   if (__builtin_amdgcn_ballot_w64(b < P.n_dbg) != 0) run(std::true_type{});
   else run(std::false_type{});
-  P.cost[b] = finite_or_inf(cost);
+  if (q == 0) P.cost[b] = finite_or_inf(cost);
 }
 
 // Obstacle-table size class of a point-mass plan: 8, 16, 32 in registers, 0 in LDS.
@@ -663,13 +703,14 @@ __device__ __host__ __forceinline__ int point_mass_obs_class(int n_obs) {
   return n_obs <= 8 ? 8 : (n_obs <= 16 ? 16 : (n_obs <= 20 ? 20 : (n_obs <= 32 ? 32 : 0)));
 }
 
-__device__ __forceinline__ void rollout_point_mass_any(const PlanDesc& P, int b, const PointMassSmem& sm) {
+template <int LANES = 1>
+__device__ __forceinline__ void rollout_point_mass_any(const PlanDesc& P, int b, int q, const PointMassSmem& sm) {
   switch (point_mass_obs_class(static_cast<int>(P.task[5]))) {
-    case 8: rollout_point_mass<8>(P, b, sm); return;
-    case 16: rollout_point_mass<16>(P, b, sm); return;
-    case 20: rollout_point_mass<20>(P, b, sm); return;
-    case 32: rollout_point_mass<32>(P, b, sm); return;
-    default: rollout_point_mass<0>(P, b, sm); return;
+    case 8: rollout_point_mass<8, LANES>(P, b, q, sm); return;
+    case 16: rollout_point_mass<16, LANES>(P, b, q, sm); return;
+    case 20: rollout_point_mass<20, LANES>(P, b, q, sm); return;
+    case 32: rollout_point_mass<32, LANES>(P, b, q, sm); return;
+    default: rollout_point_mass<0, LANES>(P, b, q, sm); return;
   }
 }
 
@@ -948,24 +989,6 @@ __device__ __forceinline__ void rollout_chain(const PlanDesc& P, int b) {
 // of the even rows.  Cross-lane values move with quad-permute DPP, which never
 // leaves the four lanes of a candidate.  Four times as many lanes as the
 // one-lane form for the same candidates, at about 60% of its instructions per lane.
-
-constexpr int qperm_ctrl(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
-constexpr int kQNext1 = qperm_ctrl(1, 2, 3, 3);
-constexpr int kQPrev1 = qperm_ctrl(0, 0, 1, 2);
-constexpr int kQNext2 = qperm_ctrl(2, 3, 2, 3);
-constexpr int kQPrev2 = qperm_ctrl(0, 1, 0, 1);
-constexpr int kQXor1 = qperm_ctrl(1, 0, 3, 2);
-constexpr int kQXor2 = qperm_ctrl(2, 3, 0, 1);
-
-template <int CTRL>
-__device__ __forceinline__ float qperm(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-__device__ __forceinline__ float quad_sum(float v) {
-  v += qperm<kQXor1>(v);
-  return v + qperm<kQXor2>(v);
-}
 
 template <int N>
 constexpr bool quad_chain_links() { return N >= 5 && N <= 8; }
