@@ -171,10 +171,25 @@ __device__ __forceinline__ void rev_sincos(float rev, float* s, float* c) {
 // rollouts use it; in the 7-link chain the bias is swamped by the rest of the
 // rounding (2.6e-5 against 2.1e-5 after 128 steps) and the shorter chains keep
 // the plain pair.
-__device__ __forceinline__ void rev_sincos_unit(float rev, float* s, float* c) {
+__device__ __forceinline__ void rev_sincos_unit(float rev, float* s, float* c, float* h_out = nullptr) {
   const float sv = __builtin_amdgcn_sinf(rev);
   const float cv = __builtin_amdgcn_cosf(rev);
   const float h = fmaf(-sv, sv, fmaf(-cv, cv, 1.0f)) * 0.5f;
+  *s = fmaf(sv, h, sv);
+  *c = fmaf(cv, h, cv);
+  if (h_out != nullptr) *h_out = h;
+}
+
+// The same with a Newton factor h taken from a nearby argument: the RK4 stage
+// angles of a step lie within a few thousandths of a turn of the step's start
+// angle, where the length deficit is nearly the same (it follows the argument
+// slowly), so the stages reuse the start angle's factor: two instructions per
+// pair instead of five.  For a link that turns slowly (the case in which the
+// deficit would pile up) the factor is the stage angle's own to within the
+// deficit's local variation.
+__device__ __forceinline__ void rev_sincos_scaled(float rev, float h, float* s, float* c) {
+  const float sv = __builtin_amdgcn_sinf(rev);
+  const float cv = __builtin_amdgcn_cosf(rev);
   *s = fmaf(sv, h, sv);
   *c = fmaf(cv, h, cv);
 }
@@ -1453,9 +1468,9 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
   const float wg = tk[1], wu = tk[2], tgx = tk[3], tgy = tk[4];
   const float dt = P.dt, hdt = 0.5f * P.dt, dt6 = P.dt * (1.0f / 6.0f);
   const float dtr = kInvTwoPi * dt, hdtr = kInvTwoPi * hdt, dt6r = kInvTwoPi * dt6;
-  float s[M], c[M];
+  float s[M], c[M], hu[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) rev_sincos_unit(ph[i], &s[i], &c[i]);
+  for (int i = 0; i < M; ++i) rev_sincos_unit(ph[i], &s[i], &c[i], &hu[i]);
   // Controls through a buffer descriptor based at step t's block of U rows:
   // the lane's byte offset (its link's row and its candidate) is the same at
   // every step and below 2^31 for every valid plan (N <= 24, ldU <= 2^24 + 64),
@@ -1517,7 +1532,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
       float s2[M], c2[M];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        rev_sincos_unit(fmaf(hr, oms[i], ph[i]), &s2[i], &c2[i]);
+        rev_sincos_scaled(fmaf(hr, oms[i], ph[i]), hu[i], &s2[i], &c2[i]);
         oms[i] = fmaf(h, kk[i], om[i]);
       }
       pair_accel<N, CONTACT>(s2, c2, oms, Q, K, kk);
@@ -1535,7 +1550,7 @@ __device__ __forceinline__ void pair_steps(const PlanDesc& P, const PairConsts<N
       pu[i] = fmaf(dt6r, aph[i], ph[i]);
       ph[i] = __builtin_amdgcn_fractf(pu[i]);
       om[i] = fmaf(dt6, aom[i], om[i]);
-      rev_sincos_unit(ph[i], &s[i], &c[i]);
+      rev_sincos_unit(ph[i], &s[i], &c[i], &hu[i]);
       ex = fmaf(K.len(i), s[i], ex);
       ey = fmaf(-K.len(i), c[i], ey);
       uu = fmaf(u[i], u[i], uu);
