@@ -2422,24 +2422,22 @@ __device__ __forceinline__ void shift_block(const PlanDesc& P, int shift) {
   const int s = shift < P.T ? shift : P.T;
   // the value that lands at flat index e: step t + s of the warm start, or
   // the last step's mean with the initial spread past the end
-  auto src = [&](int e, float& m, float& g) {
-    const int t = e / P.n, j = e - t * P.n;
-    if (t < P.T - s) {
-      m = P.mu[e + s * P.n];
-      g = P.sigma[e + s * P.n];
-    } else {
-      m = P.mu[(P.T - 1) * P.n + j];
-      g = P.sigma_init;
-    }
+  auto src_mu = [&](int e) {
+    const int t = e / P.n;
+    return P.mu[t < P.T - s ? e + s * P.n : (P.T - 1) * P.n + (e - t * P.n)];
   };
+  auto src_sg = [&](int e) { return e / P.n < P.T - s ? P.sigma[e + s * P.n] : P.sigma_init; };
   constexpr int R = 8;
   if (Tn <= BS * R) {
     // every value held in registers across the barrier: all loads in flight
     // at once and no staging copy
     float m[R], g[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (tid + i * BS < Tn) src(tid + i * BS, m[i], g[i]);
+    for (int i = 0; i < R; ++i) {
+      const int e = tid + i * BS < Tn ? tid + i * BS : 0;
+      m[i] = src_mu(e);
+      g[i] = src_sg(e);
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R; ++i)
@@ -2451,7 +2449,10 @@ __device__ __forceinline__ void shift_block(const PlanDesc& P, int shift) {
   }
   float* tmu = P.tmp;
   float* tsg = P.tmp + Tn;
-  for (int e = tid; e < Tn; e += BS) src(e, tmu[e], tsg[e]);
+  for (int e = tid; e < Tn; e += BS) {
+    tmu[e] = src_mu(e);
+    tsg[e] = src_sg(e);
+  }
   __syncthreads();
   for (int e = tid; e < Tn; e += BS) {
     P.mu[e] = tmu[e];

@@ -352,7 +352,11 @@ def test_topk_sizes(E, torch_mod):
 
 @pytest.mark.parametrize("B, E, kind", [(70000, 512, "ties"), (20011, 1500, "uniform"), (3000, 100, "equal"),
                                         (17000, 4096, "ties"), (16384, 1, "uniform"), (30000, 2000, "clustered"),
-                                        (900, 50, "extremes"), (5000, 2500, "equal"), (12000, 300, "lognormal")])
+                                        (900, 50, "extremes"), (5000, 2500, "equal"), (12000, 300, "lognormal"),
+                                        # around the 24-link workload's size
+                                        (69632, 512, "uniform"), (53248, 4096, "equal"), (70144, 1000, "clustered"),
+                                        (61001, 2000, "extremes"), (65536, 300, "lognormal"),
+                                        (70145, 100, "uniform")])
 def test_topk_batches_beyond_the_lds_cache_and_degenerate(B, E, kind, torch_mod):
     """Top-E for batches larger than the cost cache (read from HBM every pass),
     with rounded costs (many ties across the elite boundary), all-equal costs
