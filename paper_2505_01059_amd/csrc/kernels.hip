@@ -38,14 +38,6 @@ __global__ __launch_bounds__(kCandThreads) void k_candidates(PlanDesc P, int k) 
   cand_tile(P, P.ctrl[0], k, blockIdx.y, b0, t_begin, min(P.T, t_begin + P.tc), v, ahead ? kCandLocal : kCandAll);
 }
 
-// Tensor paths drawn ahead are complete: record the replan they are for.
-__global__ __launch_bounds__(64) void k_ahead_mark(PlanDesc P) {
-  if (threadIdx.x == 0) {
-    P.ctrl[3] = P.ctrl[0] + 1u;
-    P.ctrl[5] = 1u;
-  }
-}
-
 __global__ __launch_bounds__(kTopkThreads) void k_entropy(PlanDesc P, int k) {
   __shared__ EntropySmem sm;
   entropy_block<kTopkThreads>(P, k, sm);
@@ -97,6 +89,12 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(PlanDesc P) {
 
 __global__ __launch_bounds__(kUpdThreads) void k_update(PlanDesc P) {
   const int o = blockIdx.x * (kUpdThreads / 64) + (threadIdx.x >> 6);
+  // the last refit of a replan that drew the next replan's first tensor paths
+  // (its launch follows the generator's): record the replan they are for
+  if (P.gen_spec && blockIdx.x == 0 && threadIdx.x == 0) {
+    P.ctrl[3] = P.ctrl[0] + 1u;
+    P.ctrl[5] = 1u;
+  }
   if (o < P.T * P.n) update_output(P, o);
 }
 
@@ -317,12 +315,7 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
       hipError_t e = hipSuccess;
       if (!sliced) {
         Pk.gen_spec = last ? 1 : 0;
-        e = launch_rollout(Pk, st, last ? 0 : k + 1);
-        if (e == hipSuccess && last) {
-          k_ahead_mark<<<1, 64, 0, st>>>(P);
-          e = hipGetLastError();
-        }
-        return e;
+        return launch_rollout(Pk, st, last ? 0 : k + 1);
       }
       PlanDesc G = Pk;
       G.roll_blocks = 0;
@@ -343,19 +336,18 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
       if (e != hipSuccess) return e;
       if (side == nullptr) {
         k_gen_tensor<<<G.gen_grid, kCandThreads, lds, gs>>>(G);
-        e = hipGetLastError();
-      } else {
-        e = hipEventRecord(side->join, side->st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+        return hipGetLastError();
       }
-      if (e == hipSuccess && last) {
-        k_ahead_mark<<<1, 64, 0, st>>>(P);
-        e = hipGetLastError();
-      }
+      e = hipEventRecord(side->join, side->st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
       return e;
     }
     case 3: {
-      if (last) return launch_stage(Pk, stage, k, st);
+      if (last) {
+        // the last refit also records the replan whose tensor paths were drawn
+        Pk.gen_spec = across ? 1 : 0;
+        return launch_stage(Pk, stage, k, st);
+      }
       k_update_next<<<((Pk.T + 3) / 4) * Pk.n, kUpdThreads, 0, st>>>(Pk, k + 1);
       return hipGetLastError();
     }
