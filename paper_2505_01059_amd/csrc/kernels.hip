@@ -53,10 +53,10 @@ __global__ __launch_bounds__(kRollThreads) MTP_ROLL_WAVES(ONE) void k_rollout_po
   __shared__ PointMassSmem sm;
   stage_obstacles(P, sm);
   __syncthreads();
-  // four lanes (a quad) per candidate, each with a quarter of the obstacle table
+  // eight lanes per candidate, each with an eighth of the obstacle table
   const int g = xcd_contiguous_block(blockIdx.x, P.roll_blocks) * kRollThreads + threadIdx.x;
-  const int b = g >> 2;
-  if (b < P.B) rollout_point_mass_any<4>(P, b, g & 3, sm);
+  const int b = g / kPmLanes;
+  if (b < P.B) rollout_point_mass_any<kPmLanes>(P, b, g % kPmLanes, sm);
 }
 
 template <int N, bool CONTACT, bool ONE>
@@ -151,8 +151,10 @@ int supported_chain_links(int* out, int cap) {
 
 // Workgroups of the rollout kernel proper (one to four lanes per candidate).
 int rollout_blocks(const PlanDesc& P) {
-  const long long lanes_per =
-      (P.dyn == kPointMass || is_quad_chain(P.dyn, P.n_links)) ? 4 : is_pair_chain(P.dyn, P.n_links) ? 2 : 1;
+  const long long lanes_per = P.dyn == kPointMass             ? kPmLanes
+                              : is_quad_chain(P.dyn, P.n_links) ? 4
+                              : is_pair_chain(P.dyn, P.n_links) ? 2
+                                                                : 1;
   return static_cast<int>((lanes_per * P.B + kRollThreads - 1) / kRollThreads);
 }
 

@@ -593,19 +593,27 @@ __device__ __forceinline__ float quad_sum(float v) {
 // longer tables, is read from LDS.  Register tables avoid one LDS round trip per
 // obstacle and step, which dominates a rollout of a few hundred candidates.
 //
-// The obstacle penalties of a step are summed in four groups, obstacle o in
-// group o mod 4, each in increasing o, and the groups as (g0 + g1) + (g2 + g3).
-// LANES = 1: one lane per candidate holds every group.  LANES = 4: lane q of
-// the candidate's quad holds group q (a quarter of the table) and the quad
-// adds the groups with two quad permutes in the same order, so every lane ends
-// the step with the same bits as the one-lane form; the state update, goal and
-// control terms run on all four lanes alike.  A step is issue-bound on one
-// wave per SIMD, and the quad form issues about a third of the instructions
-// per lane.
+// The obstacle penalties of a step are summed in eight groups, obstacle o in
+// group o mod 8, each in increasing o, and the groups as
+// ((g0 + g1) + (g2 + g3)) + ((g4 + g5) + (g6 + g7)).  LANES = 1: one lane per
+// candidate holds every group.  LANES = 8: lane q of the candidate's eight
+// holds group q (an eighth of the table); two quad permutes add the groups of
+// each quad and a half-row mirror adds the two quads, in the same order, so
+// every lane ends the step with the same bits as the one-lane form; the state
+// update, goal and control terms run on all eight lanes alike.  A step is
+// issue-bound on one wave per SIMD, and the eight-lane form issues about a
+// quarter of the one-lane instructions per lane.
+constexpr int kPmLanes = 8;
+constexpr int kDppHalfMirror = 0x141;   // lane i of each eight reads lane 7 - i
+
+__device__ __forceinline__ float half_mirror(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppHalfMirror, 0xF, 0xF, true));
+}
+
 template <int NOBS, int LANES = 1>
 __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, int q, const PointMassSmem& sm) {
-  static_assert(LANES == 1 || LANES == 4, "one lane or a quad per candidate");
-  static_assert(NOBS % 4 == 0, "register tables hold whole groups");
+  static_assert(LANES == 1 || LANES == kPmLanes, "one lane or eight per candidate");
+  static_assert(NOBS % 8 == 0, "register tables hold whole groups");
   // task: goal_x, goal_y, goal_w, obstacle_penalty, ctrl_w, n_obs, (cx, cy, r)*
   const float* tk = P.task;
   const float gx = tk[0], gy = tk[1], wg = tk[2], pen = tk[3], wu = tk[4];
@@ -617,7 +625,7 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, int
     // uniform scalars it would not fit the scalar register file)
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      const int o = LANES == 1 ? i : q + 4 * i;
+      const int o = LANES == 1 ? i : q + kPmLanes * i;
       const bool on = o < n_obs;
       ocx[i] = on ? sm.obs[3 * o] : 0.0f;
       ocy[i] = on ? sm.obs[3 * o + 1] : 0.0f;
@@ -643,23 +651,24 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, int
     const float dx = px - gx, dy = py - gy;
     float obst;
     if constexpr (LANES == 1) {
-      float pc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      float pc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (NOBS > 0) {
 #pragma unroll
-        for (int o = 0; o < NOBS; ++o) pc[o & 3] += hit(px - ocx[o], py - ocy[o], orr[o]);
+        for (int o = 0; o < NOBS; ++o) pc[o & 7] += hit(px - ocx[o], py - ocy[o], orr[o]);
       } else {
-        for (int o = 0; o < n_obs; ++o) pc[o & 3] += hit(px - obs[3 * o], py - obs[3 * o + 1], obs[3 * o + 2]);
+        for (int o = 0; o < n_obs; ++o) pc[o & 7] += hit(px - obs[3 * o], py - obs[3 * o + 1], obs[3 * o + 2]);
       }
-      obst = (pc[0] + pc[1]) + (pc[2] + pc[3]);
+      obst = ((pc[0] + pc[1]) + (pc[2] + pc[3])) + ((pc[4] + pc[5]) + (pc[6] + pc[7]));
     } else {
       float g = 0.0f;
       if constexpr (NOBS > 0) {
 #pragma unroll
         for (int i = 0; i < NL; ++i) g += hit(px - ocx[i], py - ocy[i], orr[i]);
       } else {
-        for (int o = q; o < n_obs; o += 4) g += hit(px - obs[3 * o], py - obs[3 * o + 1], obs[3 * o + 2]);
+        for (int o = q; o < n_obs; o += kPmLanes) g += hit(px - obs[3 * o], py - obs[3 * o + 1], obs[3 * o + 2]);
       }
-      obst = quad_sum(g);
+      g = quad_sum(g);
+      obst = g + half_mirror(g);
     }
     float c = fmaf(wg, fmaf(dx, dx, dy * dy), obst);
     c = fmaf(wu, fmaf(ux, ux, uy * uy), c);
@@ -713,9 +722,9 @@ __device__ __forceinline__ void rollout_point_mass(const PlanDesc& P, int b, int
   if (q == 0) P.cost[b] = finite_or_inf(cost);
 }
 
-// Obstacle-table size class of a point-mass plan: 8, 16, 32 in registers, 0 in LDS.
+// Obstacle-table size class of a point-mass plan: 8, 16, 24, 32 in registers, 0 in LDS.
 __device__ __host__ __forceinline__ int point_mass_obs_class(int n_obs) {
-  return n_obs <= 8 ? 8 : (n_obs <= 16 ? 16 : (n_obs <= 20 ? 20 : (n_obs <= 32 ? 32 : 0)));
+  return n_obs <= 8 ? 8 : (n_obs <= 16 ? 16 : (n_obs <= 24 ? 24 : (n_obs <= 32 ? 32 : 0)));
 }
 
 template <int LANES = 1>
@@ -723,7 +732,7 @@ __device__ __forceinline__ void rollout_point_mass_any(const PlanDesc& P, int b,
   switch (point_mass_obs_class(static_cast<int>(P.task[5]))) {
     case 8: rollout_point_mass<8, LANES>(P, b, q, sm); return;
     case 16: rollout_point_mass<16, LANES>(P, b, q, sm); return;
-    case 20: rollout_point_mass<20, LANES>(P, b, q, sm); return;
+    case 24: rollout_point_mass<24, LANES>(P, b, q, sm); return;
     case 32: rollout_point_mass<32, LANES>(P, b, q, sm); return;
     default: rollout_point_mass<0, LANES>(P, b, q, sm); return;
   }

@@ -291,7 +291,7 @@ bool mtp::uses_gen_overlap(const mtp_config& c) {
   const bool quad = c.dynamics == MTP_DYN_CHAIN && c.n_links >= 5 && c.n_links <= 8;
   const bool pair = chain && c.n_links >= 10 && (c.n_links % 2) == 0;
   const bool pm = c.dynamics == MTP_DYN_POINT_MASS;
-  const long long lanes = (quad || pm ? 4 : pair ? 2 : 1) * B;
+  const long long lanes = (pm ? kPmLanes : quad ? 4 : pair ? 2 : 1) * B;
   return (lanes + kRollThreads - 1) / kRollThreads <= kUnits - kMinFree;
 }
 
