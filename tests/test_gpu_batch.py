@@ -159,16 +159,20 @@ def test_overlapped_tensor_paths_equal_the_plain_sequence():
     bt.close()
 
 
-def test_draws_across_replans_follow_the_replan_index():
+@pytest.mark.parametrize("mode", ["graph", "eager", "timed"])
+def test_draws_across_replans_follow_the_replan_index(mode):
     """Plans with an even iteration count draw the next replan's first tensor
     paths during their last rollout.  A replan takes them only when its index
     is the one they were drawn for: consecutive replans, a jump in the index, a
     single iteration run in between and a repeat of the same index all give the
-    bits of the batched kernel, which draws every iteration's paths itself."""
+    bits of the batched kernel, which draws every iteration's paths itself
+    (replayed graph, eager launches and stage-timed launches alike)."""
     import torch
     import paper_2505_01059_amd as mtp
     mix = {c.name: c for c in overlap_mix()}
-    cfgs = [mix["o_c7b"], mix["o_c12"], mix["o_k24s"]]
+    cfgs = [mix["o_c7b"], mix["o_c12"], mix["o_k24s"], mix["o_k7r2"],
+            W.point_mass_config(name="a_pm", n_tensor=2048, n_gauss=100, horizon=40, n_elites=32, n_iters=4,
+                                seed=50)]
     x0s = [W.initial_state(c, seed=40 + i) for i, c in enumerate(cfgs)]
     ops = [("replan", 0), ("replan", 1), ("replan", 5), ("replan", 6), ("iter", 7), ("replan", 7),
            ("replan", 8), ("replan", 8)]
@@ -177,11 +181,12 @@ def test_draws_across_replans_follow_the_replan_index():
     xp = bt.pack_x0(x0s)
     plans = []
     for i, c in enumerate(cfgs):
-        p = mtp.Plan(c, device="cuda:0")
+        p = mtp.Plan(c, device="cuda:0", use_graph=(mode == "graph"))
+        p.set_stage_timing(mode == "timed")
         assert p.draws_ahead() and c.n_iters % 2 == 0, c.name
         plans.append(p)
     for op, r in ops:
-        _log(f"[across] {op} {r}")
+        _log(f"[across] {mode} {op} {r}")
         if op == "replan":
             bt.step(list(range(n)), [0] * n, [c.n_iters for c in cfgs], [1] * n, [r] * n, xp)
             for i, p in enumerate(plans):
