@@ -237,6 +237,12 @@ def test_single_plan_overlap_buffer():
     big = c1.replace(n_tensor=16384, n_gauss=1024)          # 4 lanes x 17408 candidates = 272 workgroups
     for off in (c1.replace(n_iters=1), c1.replace(n_tensor=0, n_gauss=9216), big, W.c4().replace(n_iters=1)):
         assert N.workspace_bytes(off) == N.workspace_bytes(off.replace(sample_wor=1)), off.name
+    # the point-mass rollout takes eight lanes per candidate: 7168 candidates
+    # are 224 workgroups (32 units left for the generator), 7200 are 225
+    pm_in = W.point_mass_config(n_tensor=7168 - 64, n_gauss=64, n_layers=5)
+    pm_out = W.point_mass_config(n_tensor=7200 - 64, n_gauss=64, n_layers=5)
+    assert N.workspace_bytes(pm_in) > N.workspace_bytes(pm_in.replace(sample_wor=1))
+    assert N.workspace_bytes(pm_out) == N.workspace_bytes(pm_out.replace(sample_wor=1))
     c4 = W.c4()                                              # time-sliced: 2176 pair-lane waves
     ldU4 = (c4.n_samples * 4 + 255) // 256 * 256 // 4
     assert N.workspace_bytes(c4) - N.workspace_bytes(c4.replace(sample_wor=1)) == c4.horizon * c4.ctrl_dim * ldU4 * 4
