@@ -121,6 +121,37 @@ __global__ __launch_bounds__(kUpdThreads) void k_update_next(PlanDesc P, int k_n
   local_store<kUpdThreads>(P, P.U2, tq, j, k_next, r, z, mom);
 }
 
+// The refit of iteration k from its elites' controls drawn again
+// (regen_elites) rather than gathered from U, one workgroup per four steps of
+// a joint; with NEXT also iteration k_next's local samples and nominal (as
+// k_update_next), without it the last iteration's refit (as k_update, which
+// also records the replan whose tensor paths were drawn when P.gen_spec).
+template <bool NEXT>
+__global__ __launch_bounds__(kUpdThreads) void k_refit_regen(PlanDesc P, int k, int k_next) {
+  __shared__ RegenSmem sm;
+  __shared__ float mom[4][2];
+  const int tq = static_cast<int>(blockIdx.x) / P.n, j = static_cast<int>(blockIdx.x) - tq * P.n;
+  const int c = static_cast<int>(threadIdx.x) >> 6;
+  const int t = 4 * tq + c;
+  const uint32_t r = P.ctrl[0];
+  float z[kLocalKeep][4];
+  if constexpr (NEXT) local_normals<kUpdThreads>(P, tq, j, k_next, r, z);
+  if (!NEXT && P.gen_spec && blockIdx.x == 0 && threadIdx.x == 0) {
+    P.ctrl[3] = P.ctrl[0] + 1u;
+    P.ctrl[5] = 1u;
+  }
+  regen_elites(P, k, tq, j, sm);
+  if (t < P.T) {
+    float mn, sn;
+    update_output_from(P, t * P.n + j, [&](int e) { return sm.vals[c][e]; }, &mn, &sn);
+    if ((threadIdx.x & 63) == 0) { mom[c][0] = mn; mom[c][1] = sn; }
+  }
+  if constexpr (NEXT) {
+    __syncthreads();
+    local_store<kUpdThreads>(P, P.U2, tq, j, k_next, r, z, mom);
+  }
+}
+
 // ---------------------------------------------------------------- dispatch
 
 static const int kChainLinks[] = {
@@ -345,12 +376,17 @@ hipError_t launch_iteration_stage(const PlanDesc& P, int stage, int k, int k0, i
       return e;
     }
     case 3: {
+      const bool regen = refit_regenerates(Pk.interp, Pk.p, Pk.wor, Pk.E, Pk.B);
+      const int tiles = ((Pk.T + 3) / 4) * Pk.n;
       if (last) {
         // the last refit also records the replan whose tensor paths were drawn
         Pk.gen_spec = across ? 1 : 0;
-        return launch_stage(Pk, stage, k, st);
+        if (!regen) return launch_stage(Pk, stage, k, st);
+        k_refit_regen<false><<<tiles, kUpdThreads, 0, st>>>(Pk, k, -1);
+        return hipGetLastError();
       }
-      k_update_next<<<((Pk.T + 3) / 4) * Pk.n, kUpdThreads, 0, st>>>(Pk, k + 1);
+      if (regen) k_refit_regen<true><<<tiles, kUpdThreads, 0, st>>>(Pk, k, k + 1);
+      else k_update_next<<<tiles, kUpdThreads, 0, st>>>(Pk, k + 1);
       return hipGetLastError();
     }
     default: return launch_stage(Pk, stage, k, st);

@@ -2347,14 +2347,13 @@ __device__ __forceinline__ void entropy_block(const PlanDesc& P, int k, EntropyS
 constexpr int kUpdKeep = 16;
 
 // Refits output o = (t, j); every lane returns the new mean and std, lane 0 stores them.
-__device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* mu_new = nullptr,
-                                              float* sg_new = nullptr) {
+// The refit of output o from the elites' controls val(e) (e < E), in a fixed
+// order: weighted mean, weighted variance about it, sigma floor, smoothing.
+template <class Val>
+__device__ __forceinline__ void update_output_from(const PlanDesc& P, int o, Val val, float* mu_new, float* sg_new) {
   const int lane = threadIdx.x & 63;
-  const size_t ld = static_cast<size_t>(P.ldU);
-  const auto row = gptr(P.U) + static_cast<size_t>(o) * ld;
-  const auto eidx = gptr(P.eidx);
   const auto w = gptr(P.w);
-  // the old moments do not depend on the gathers: their loads go out first
+  // the old moments do not depend on the elite values: their loads go out first
   const auto mu = gptr(P.mu), sigma = gptr(P.sigma);
   const float mu_old = mu[o], sg_old = sigma[o];
   float keep[kUpdKeep];
@@ -2363,7 +2362,7 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
 #pragma unroll
     for (int q = 0; q < kUpdKeep; ++q) {
       const int e = lane + 64 * q;
-      keep[q] = e < P.E ? row[eidx[e]] : 0.0f;
+      keep[q] = e < P.E ? val(e) : 0.0f;
     }
 #pragma unroll
     for (int q = 0; q < kUpdKeep; ++q) {
@@ -2371,7 +2370,7 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
       if (e < P.E) m = fmaf(w[e], keep[q], m);
     }
   } else {
-    for (int e = lane; e < P.E; e += 64) m = fmaf(w[e], row[eidx[e]], m);
+    for (int e = lane; e < P.E; e += 64) m = fmaf(w[e], val(e), m);
   }
   m = wave_sum64(m);
   float v = 0.0f;
@@ -2386,7 +2385,7 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
     }
   } else {
     for (int e = lane; e < P.E; e += 64) {
-      const float dv = row[eidx[e]] - m;
+      const float dv = val(e) - m;
       v = fmaf(w[e], dv * dv, v);
     }
   }
@@ -2399,9 +2398,106 @@ __device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* m
   if (lane == 0) {
     mu[o] = mn;
     sigma[o] = sn;
-    // first control of the best candidate (lane 0 gathered elite 0 already)
-    if (o < P.n) gptr(P.action)[o] = P.E <= 64 * kUpdKeep ? keep[0] : row[eidx[0]];
+    // first control of the best candidate (lane 0 holds elite 0 already)
+    if (o < P.n) gptr(P.action)[o] = P.E <= 64 * kUpdKeep ? keep[0] : val(0);
   }
+}
+
+// The refit of output o from the elites' rows of U (one gathered value each).
+__device__ __forceinline__ void update_output(const PlanDesc& P, int o, float* mu_new = nullptr,
+                                              float* sg_new = nullptr) {
+  const auto row = gptr(P.U) + static_cast<size_t>(o) * static_cast<size_t>(P.ldU);
+  const auto eidx = gptr(P.eidx);
+  update_output_from(P, o, [&](int e) { return row[eidx[e]]; }, mu_new, sg_new);
+}
+
+// Elite controls drawn again instead of gathered.  The gather reads one value
+// per elite from a 4-byte slot of its own cache line, 360 MB of lines per
+// 24-link refit for 12.6 MB of values; the values are functions of the seed,
+// the replan and iteration index and the moments the iteration sampled from,
+// so the refit tile of steps 4 tq..4 tq+3 of joint j recomputes them with the
+// arithmetic that drew them (cand_tile): the graph column of joint j (Def. 1),
+// each tensor elite's layer indices at the spans it needs (Alg. 1) and the
+// cubic B-spline, each local elite's normals (one Philox block) and the
+// nominal mean.  For plans drawing paths with replacement and cubic B-splines,
+// up to kRegenMaxElites elites; the values are the same bits as the gathered
+// ones.  Small batches keep the gather: their rows span a few lines that the
+// elites share, and the redraw's latency would cost more (C0: 6.8 -> 7.7 us
+// per refit, against 59.5 -> 33 us at the 24-link size).
+constexpr int kRegenMaxElites = 1024;
+constexpr int kRegenMinCandidates = 16384;
+
+struct RegenSmem {
+  float zc[kMaxLayers * kMaxWidth];          // graph column of joint j
+  uint8_t wi[kMaxLayers][kUpdThreads];       // each thread's current elite's layer indices
+  float vals[4][kRegenMaxElites];            // elite controls at the tile's four steps
+  float old[4][2];                           // the sampled moments at those steps
+};
+
+__host__ __device__ __forceinline__ bool refit_regenerates(int interp, int degree, int wor, int E, int B) {
+  return interp == kBspline && degree == 3 && !wor && E <= kRegenMaxElites && B >= kRegenMinCandidates;
+}
+
+__device__ __forceinline__ void regen_elites(const PlanDesc& P, int k, int tq, int j, RegenSmem& sm) {
+  const int tid = threadIdx.x;
+  const uint32_t r = P.ctrl[0];
+  const float lo = P.u_min, hi = P.u_max, span = hi - lo;
+  const int G1 = P.G - 1;
+  const int t0 = 4 * tq, nc = min(4, P.T - t0);
+  if (tid < nc) {
+    const int o = (t0 + tid) * P.n + j;
+    sm.old[tid][0] = gptr(P.mu)[o];
+    sm.old[tid][1] = gptr(P.sigma)[o];
+  }
+  for (int e = tid; e < P.L * P.W; e += kUpdThreads) {
+    const int l = e / P.W, w = e - l * P.W;
+    const uint32_t idx = static_cast<uint32_t>(w * P.n + j);
+    const Words4 q = philox(idx >> 2, static_cast<uint32_t>(l), r, stream_c3(kTagZ, k), P.key0, P.key1);
+    sm.zc[e] = fmaf(span, u01(word_at(q, idx & 3u)), lo);
+  }
+  __syncthreads();
+  const auto eidx = gptr(P.eidx);
+  const auto spn = gptr(P.span);
+  const auto basis = gptr(P.basis);
+  const int s_lo = spn[t0], s_hi = min(spn[t0 + nc - 1] + 3, P.L - 1);
+  for (int e = tid; e < P.E; e += kUpdThreads) {
+    const int b = eidx[e];
+    if (b < G1) {
+      float z[4];
+      local_normals4(P, tq, j, b, k, r, z);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < nc) sm.vals[c][e] = clampf(fmaf(sm.old[c][1], z[c], sm.old[c][0]), lo, hi);
+    } else if (b < G1 + P.P) {
+      const int pp = b - G1;
+      for (int l4 = s_lo >> 2; l4 <= (s_hi >> 2); ++l4) {
+        const Words4 q = philox(static_cast<uint32_t>(l4), static_cast<uint32_t>(pp), r, stream_c3(kTagI, k),
+                                P.key0, P.key1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int l = 4 * l4 + c;
+          if (l >= s_lo && l <= s_hi) sm.wi[l][tid] = static_cast<uint8_t>(__umulhi(q.w[c], static_cast<uint32_t>(P.W)));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c < nc) {
+          const int t = t0 + c, s0 = spn[t];
+          const auto bw = basis + t * kBasisStride;
+          float v = bw[0] * sm.zc[s0 * P.W + sm.wi[s0][tid]];
+          v = fmaf(bw[1], sm.zc[(s0 + 1) * P.W + sm.wi[s0 + 1][tid]], v);
+          v = fmaf(bw[2], sm.zc[(s0 + 2) * P.W + sm.wi[s0 + 2][tid]], v);
+          v = fmaf(bw[3], sm.zc[(s0 + 3) * P.W + sm.wi[s0 + 3][tid]], v);
+          sm.vals[c][e] = clampf(v, lo, hi);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < nc) sm.vals[c][e] = clampf(sm.old[c][0], lo, hi);
+    }
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ prologue
