@@ -270,9 +270,14 @@ def time_plan(cfg, name, steps, warmup):
     ms_per_step = wall / steps * 1e3
     print(f"[bench] {ms_per_step:.3f} ms/replan", file=sys.stderr, flush=True)
 
-    # latency: submit a replan and wait for its action, per replan
+    # latency: submit a replan and wait for its action, per replan (one untimed
+    # round first: the process's first read-back to host memory carries a
+    # one-time set-up of tens of ms on a fresh box)
+    plan.replan(x0_dev, shift=1)
+    plan.action()
+    # (enough samples that p99 is not simply the slowest one)
     lat = []
-    for _ in range(max(steps, 30 if B * T < 10 ** 7 else 10)):
+    for _ in range(max(steps, 200 if B * T < 10 ** 7 else 100)):
         t = time.perf_counter()
         plan.replan(x0_dev, shift=1)
         plan.action()
