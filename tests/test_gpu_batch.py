@@ -205,6 +205,37 @@ def test_draws_across_replans_follow_the_replan_index(mode):
     bt.close()
 
 
+@pytest.mark.parametrize("E", [1024, 1025])
+def test_refit_from_redrawn_elites_equals_the_gather(E):
+    """Large cubic B-spline plans refit from elite controls drawn again rather
+    than gathered from U (up to 1024 elites; one more falls back to the
+    gather): the same bits as the batched kernel, which gathers, with local
+    and tensor candidates among the elites."""
+    import torch
+    import paper_2505_01059_amd as mtp
+    c = W.chain_config(name=f"regen_e{E}", n_links=12, interp=W.BSPLINE, n_tensor=18000, n_gauss=2000, horizon=16,
+                       n_layers=5, n_width=16, n_elites=E, n_iters=3, seed=60 + E)
+    x0 = W.initial_state(c, seed=3)
+    _log(f"[regen] E={E}")
+    bt = mtp.Batch([c], device="cuda:0")
+    xp = bt.pack_x0([x0])
+    p = mtp.Plan(c, device="cuda:0")
+    assert p.draws_ahead()
+    for r in range(2):
+        bt.replan(xp, shift=1)
+        p.replan(x0, shift=1, replan_idx=r)
+    torch.cuda.synchronize()
+    b, pb = bt.buffers(0), p.buffers()
+    assert np.array_equal(pb["mu"].cpu().numpy(), b["mu"].cpu().numpy())
+    assert np.array_equal(pb["sigma"].cpu().numpy(), b["sigma"].cpu().numpy())
+    assert np.array_equal(p.action(), bt.actions()[0])
+    iE = pb["elite_idx"].cpu().numpy()
+    G1 = c.n_gauss - 1
+    assert (iE < G1).any() and (iE >= G1).any(), "elites of one kind only"
+    p.close()
+    bt.close()
+
+
 def test_batch_step_split_iterations_and_subsets():
     """Running iterations [0, 1) and then [1, K) of a replan, in launches that
     include other instances or not, gives the same bits as one replan."""
